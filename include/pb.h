@@ -1,0 +1,191 @@
+/*
+ * pb.h — C-ABI of the MI355X implicit boundary integral method (IBIM) library for the
+ * linearized Poisson–Boltzmann equation (Zhong, Ren, Tsai, arXiv:1709.08070).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Units: lengths in Å, charges in e. Potentials and energies are in the paper's units,
+ *   in which G0 = 1/(4πr) and charges enter as q/ε (energy unit e²/(ε0·Å));
+ *   pb_energy.g_pol_kcal multiplies by 4π·332.0637 to give kcal/mol.
+ * Memory: pointers documented as "device" are HIP device memory owned by the caller
+ *   (for example torch tensors); the library never frees them and never keeps them
+ *   after a call returns. "host" pointers are ordinary CPU memory. The library owns
+ *   its own workspace (allocated on demand, released by pb_destroy).
+ * Layouts:
+ *   atoms  — n_atoms × 5 doubles, row-major (x, y, z, radius, charge).
+ *   grid   — node (i, j, k) sits at origin + h·(i, j, k); linear index (i·ny + j)·nz + k.
+ *   band   — structure of arrays, one entry per band node, nodes in increasing linear
+ *            grid index (lexicographic order).
+ *   p, y, g — 2n doubles [ψ̄(band order); ψ̄_n(band order)].
+ * Streams: every kernel runs on the stream given to pb_create (0 = the null stream).
+ *   Calls that return host values (counts, statistics, energies) synchronize that stream.
+ * Errors: every call returns a pb_status; nothing throws across the ABI. pb_last_error
+ *   gives a message for the last failing call on a context. Inputs are validated
+ *   (PB_EINVAL) before any kernel is launched.
+ * Threads: a context is not thread-safe; use one context per host thread.
+ */
+#ifndef PB_H_
+#define PB_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PB_OK = 0,
+  PB_EINVAL = -1,    /* invalid argument (non-finite, non-positive, NULL, unsupported mode) */
+  PB_ENOMEM = -2,    /* device workspace allocation failed */
+  PB_EDEVICE = -3,   /* a HIP runtime call failed */
+  PB_ECAPACITY = -4, /* output buffer too small; the required size is reported */
+  PB_ENOCONV = -5,   /* solver stopped before the tolerance; best iterate and statistics written */
+  PB_EGEOM = -6      /* degenerate geometry: empty band, band touching the grid edge, zero gradient */
+} pb_status;
+
+/* Regularization predicate ‖x* − y*‖_P < τ of the kernel regularization (eq. reg-kernel):
+   tangent-plane distance at x* with the guard |x* − y*| < 2τ (default), the literal
+   tangent-plane distance, or the Euclidean distance. */
+enum { PB_REG_TANGENT_GUARDED = 0, PB_REG_TANGENT = 1, PB_REG_EUCLIDEAN = 2 };
+/* Level set: van der Waals union F(x) = min_k(|x − z_k| − r_k) (exact signed distance for a
+   single atom), or the solvent excluded surface of Stage 1. */
+enum { PB_LS_VDW = 0, PB_LS_SES = 1 };
+/* Arithmetic of the operator: FP64 everywhere, or FP32 pair kernels with FP64 near field,
+   FP64 accumulation and FP64 iterative refinement. */
+enum { PB_FP64 = 0, PB_MIXED = 1 };
+/* GMRES initial guess: zero, Λ⁻¹g (the paper's diagonal preconditioner), caller's p, learned. */
+enum { PB_X0_ZERO = 0, PB_X0_DIAG = 1, PB_X0_USER = 2, PB_X0_LEARNED = 3 };
+enum { PB_PRECOND_NONE = 0, PB_PRECOND_LEARNED = 1 };
+
+typedef struct pb_ctx pb_ctx;
+
+typedef struct {
+  double eps_in;     /* ε_I, dielectric constant inside the molecule (experiments: 1) */
+  double eps_out;    /* ε_E, dielectric constant of the solvent (experiments: 80) */
+  double kappa;      /* κ in Gκ = e^{−κr}/(4πr), Å⁻¹ (experiments: 0.1257) */
+  double probe;      /* ρ0, probe radius of the SES, Å (1.4) */
+  double h;          /* grid spacing, Å */
+  double band_k;     /* band half-width ε = band_k·h (experiments: 2) */
+  double tau_k;      /* regularization radius τ = tau_k·h (experiments: 1 or 0.5) */
+  double cfl;        /* level-set time step Δt = cfl·h (0.3) */
+  double near_k;     /* mixed path: pairs closer than max(near_k·h, 2τ) use the FP64 near field (2) */
+  int reg_metric;    /* PB_REG_* */
+  int ls_mode;       /* PB_LS_* */
+  int reinit_steps;  /* reinitialization steps; 0 = 2·ceil((band_k + 4)/cfl) */
+  int reserved;
+} pb_params;
+
+typedef struct {
+  int nx, ny, nz;
+  double origin[3];
+  double h;
+} pb_grid;
+
+typedef struct {
+  int64_t n;          /* out: band node count (on PB_ECAPACITY: the required count) */
+  int64_t capacity;   /* in: entries available in every array below */
+  double *px, *py, *pz;   /* device: closest-point projection x* = x − φ n */
+  double *nx, *ny, *nz;   /* device: unit normal ∇φ/|∇φ| (central differences) */
+  double *phi;            /* device: level-set value at the node */
+  double *w;              /* device: ω = J·δ_ε(φ) with J ≡ 1 (h³ is applied by the operator) */
+  int64_t *gidx;          /* device: linear grid index of the node */
+} pb_band;
+
+typedef struct {
+  double tol;        /* stop when ‖g − Ap‖₂/‖g‖₂ ≤ tol (true FP64 residual) */
+  int max_iter;      /* total Krylov iterations allowed (all restarts and refinement steps) */
+  int restart;       /* GMRES restart length m (basis of m+1 vectors of 2n doubles) */
+  int precision;     /* PB_FP64 or PB_MIXED */
+  int x0;            /* PB_X0_* */
+  int precond;       /* PB_PRECOND_* */
+  int max_outer;     /* mixed path: refinement steps (each one FP64 residual) */
+  const void* nn;    /* learned preconditioner weights (pb_nn handle) or NULL */
+} pb_solve_opts;
+
+typedef struct {
+  int iters;            /* Krylov iterations (operator applications inside Arnoldi) */
+  int outer;            /* refinement steps taken (1 for the FP64 path) */
+  int converged;        /* 1 if the true residual met tol */
+  int fallback_used;    /* 1 if the learned path was abandoned for plain GMRES */
+  int matvecs_fp64;     /* FP64 operator applications */
+  int matvecs_mixed;    /* mixed-precision operator applications */
+  double true_relres;   /* ‖g − Ap‖₂/‖g‖₂ with the FP64 operator, at exit */
+  double t_total_s;     /* wall time of the call */
+  double t_matvec_s;    /* device time inside the operator kernels */
+  double pairs;         /* pair-interactions evaluated (n² per operator application) */
+} pb_solve_stats;
+
+typedef struct {
+  double g_pol;       /* polarization energy ½ Σ q_k ψ_rxn(z_k), paper units */
+  double g_pol_kcal;  /* the same in kcal/mol */
+  double area;        /* surface area h³ Σ ω_j, Å² */
+} pb_energy;
+
+/* Context on one device and one stream. device: HIP ordinal; hip_stream: a hipStream_t
+   or NULL. Returns PB_EDEVICE if the device cannot be used. */
+pb_status pb_create(pb_ctx** out, int device, void* hip_stream);
+void pb_destroy(pb_ctx* ctx);
+const char* pb_last_error(const pb_ctx* ctx);
+/* Parameters of the paper's experiments ("Numerical experiments": ε_I = 1, ε_E = 80,
+   κ = 0.1257, ε = 2h, τ = h) with ρ0 = 1.4, h = 0.5, cfl = 0.3, near_k = 2. */
+void pb_default_params(pb_params* out);
+void pb_default_solve_opts(pb_solve_opts* out);
+
+/* Grid on hℤ³ covering the atoms (host, n_atoms × 5) with a margin of
+   r_max + ρ0 (SES only) + ε + 4h + 1 Å. Host-only; no device work. */
+pb_status pb_grid_for_atoms(const double* atoms_host, int n_atoms, const pb_params* prm, pb_grid* grid);
+
+/* Stage 1 (section "Creating a signed distance function to the solvent accessible
+   surface" and its subsections): φ on the grid.
+   PB_LS_VDW: φ = F(x) = min_k(|x − z_k| − r_k) (eq. vdW-levelset-fn).
+   PB_LS_SES: φ_SAS = F − ρ0, inward eikonal flow φ_t = |∇φ| to t = ρ0 (TVD-RK3, Godunov
+   Hamiltonian, WENO5, zero-Neumann ghosts), cavity removal (flood fill from the grid
+   boundary through φ > 0; unreached nodes within ε + h of a cavity set to −ε), then
+   reinitialization φ_t + sgn_h(φ0)(|∇φ| − 1) = 0 (eqs. reinit, signum).
+   atoms: device, n_atoms × 5. phi: device, nx·ny·nz doubles. */
+pb_status pb_build_levelset(pb_ctx* ctx, const double* atoms, int n_atoms, const pb_params* prm,
+                            const pb_grid* grid, double* phi);
+
+/* Stage 2 (section "Projections and weights"): band nodes −ε < φ < ε in lexicographic
+   order, n = ∇φ/|∇φ| by central differences, x* = x − φ n, ω = δ_ε(φ) (eq. cosine-kernel),
+   J ≡ 1. phi: device. band: caller fills capacity and the device arrays; on return n holds
+   the node count. PB_ECAPACITY if capacity < count (n = count, arrays untouched beyond
+   capacity); PB_EGEOM if a band node lies on the grid edge or has zero gradient. */
+pb_status pb_narrowband_compact(pb_ctx* ctx, const pb_grid* grid, const double* phi, const pb_params* prm,
+                                pb_band* band);
+
+/* The right-hand side g at the projections (eq. IBIM-PBE): g1 = Σ_k q_k/ε_I G0(x*, z_k),
+   g2 = Σ_k q_k/ε_I ∂G0(x*, z_k)/∂n(x*). atoms: device; g: device, 2n. */
+pb_status pb_ibim_rhs(pb_ctx* ctx, const pb_band* band, const double* atoms, int n_atoms, const pb_params* prm,
+                      double* g);
+
+/* y = Λp + KWp (eq. final-lin-sys), the four regularized kernels of eq. IBIM-PBE and the
+   regularization subsection, h³ and ω folded in. precision PB_FP64 or PB_MIXED.
+   p, y: device, 2n; they must not overlap. */
+pb_status pb_ibim_matvec(pb_ctx* ctx, const pb_band* band, const pb_params* prm, int precision, const double* p,
+                         double* y);
+
+/* Solve Λp + KWp = g by GMRES (section "Fast linear solvers"; x0 = Λ⁻¹g by default).
+   Computes g from the atoms (device). p: device, 2n; input when opts->x0 == PB_X0_USER,
+   output always (best iterate on PB_ENOCONV). stats: host, may be NULL. */
+pb_status pb_ibim_solve(pb_ctx* ctx, const pb_band* band, const double* atoms, int n_atoms, const pb_params* prm,
+                        const pb_solve_opts* opts, double* p, pb_solve_stats* stats);
+
+/* Stage 4 (sections "Computing surface area", "Computing the polarization energy"):
+   area = h³ Σ ω_j and G_pol = ½ Σ_k q_k ψ_rxn(z_k) with ψ_rxn by the IBIM sum. atoms and p:
+   device. out: host. psi_rxn: device, n_atoms doubles, or NULL. */
+pb_status pb_solvation_energy(pb_ctx* ctx, const pb_band* band, const double* atoms, int n_atoms,
+                              const pb_params* prm, const double* p, pb_energy* out, double* psi_rxn);
+
+/* Device time (ms) and launch count of one kernel family since the last reset, measured
+   with HIP events around each launch on the context stream when timing is enabled.
+   name: "p2p_f32", "p2p_f64", "near_f64", "reduce", "gmres", "levelset", "band", "rhs",
+   "energy". */
+pb_status pb_set_timing(pb_ctx* ctx, int enable);
+pb_status pb_kernel_time(pb_ctx* ctx, const char* name, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,165 @@
+// Right-hand side at the projections and Stage 4 (area and polarization energy).
+//
+// RHS (eq. IBIM-PBE): g1_i = Σ_k q_k/ε_I G0(x_i*, z_k),
+//                     g2_i = Σ_k q_k/ε_I ∂G0(x_i*, z_k)/∂n(x_i*) = −Σ_k q_k (x_i*−z_k)·n_i/(4π ε_I |x_i*−z_k|³).
+// Energy (eq. G pol): ψ_rxn(z_k) = h³ Σ_j ω_j [(θ1 ∂Gκ/∂n(y) − ∂G0/∂n(y)) ψ̄_j + (G0 − Gκ) ψ̄n_j]
+//   at y = y_j*, with ρ = |z − y|, s = (z − y)·n_j: ∂G0/∂n(y) = s/(4πρ³),
+//   ∂Gκ/∂n(y) = e^{−κρ}(1+κρ) s/(4πρ³). G_pol = ½ Σ_k q_k ψ_rxn(z_k); area = h³ Σ_j ω_j.
+// All FP64. Reductions are fixed-order block trees (bitwise reproducible).
+#include <cmath>
+
+#include "pb_internal.hpp"
+
+namespace pb {
+namespace {
+
+constexpr int kBlock = 256;
+
+__global__ void __launch_bounds__(kBlock) k_rhs(int n, const double* __restrict__ px, const double* __restrict__ py,
+                                                const double* __restrict__ pz, const double* __restrict__ nx,
+                                                const double* __restrict__ ny, const double* __restrict__ nz,
+                                                const double* __restrict__ atoms, int n_atoms, double eps_in,
+                                                double* __restrict__ g) {
+  __shared__ double4 tile[kBlock];
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const bool live = i < n;
+  double x = 0, y = 0, z = 0, a = 0, b = 0, c = 1;
+  if (live) {
+    x = px[i]; y = py[i]; z = pz[i];
+    a = nx[i]; b = ny[i]; c = nz[i];
+  }
+  double s1 = 0.0, s2 = 0.0;
+  const double c4 = 1.0 / (4.0 * kPi);
+  for (int base = 0; base < n_atoms; base += kBlock) {
+    int k = base + threadIdx.x;
+    if (k < n_atoms) tile[threadIdx.x] = make_double4(atoms[5 * k], atoms[5 * k + 1], atoms[5 * k + 2], atoms[5 * k + 4]);
+    __syncthreads();
+    int m = min(kBlock, n_atoms - base);
+    if (live)
+      for (int q = 0; q < m; ++q) {
+        const double4 at = tile[q];
+        double dx = x - at.x, dy = y - at.y, dz = z - at.z;
+        double r2 = dx * dx + dy * dy + dz * dz;
+        double rinv = 1.0 / sqrt(r2);
+        double dn = dx * a + dy * b + dz * c;
+        double qe = at.w / eps_in * c4;
+        s1 += qe * rinv;
+        s2 -= qe * dn * rinv * rinv * rinv;
+      }
+    __syncthreads();
+  }
+  if (live) {
+    g[i] = s1;
+    g[n + i] = s2;
+  }
+}
+
+// One block per atom: ψ_rxn(z_k) by a strided sum over the band and a fixed block tree.
+__global__ void __launch_bounds__(kBlock) k_psi_rxn(int n, const double* __restrict__ px, const double* __restrict__ py,
+                                                    const double* __restrict__ pz, const double* __restrict__ nx,
+                                                    const double* __restrict__ ny, const double* __restrict__ nz,
+                                                    const double* __restrict__ w, const double* __restrict__ p,
+                                                    const double* __restrict__ atoms, double th1, double kappa,
+                                                    double h3, double* __restrict__ psi) {
+  __shared__ double red[kBlock];
+  const int k = blockIdx.x;
+  const double zx = atoms[5 * k], zy = atoms[5 * k + 1], zz = atoms[5 * k + 2];
+  const double c4 = 1.0 / (4.0 * kPi);
+  double acc = 0.0;
+  for (int j = threadIdx.x; j < n; j += kBlock) {
+    double dx = zx - px[j], dy = zy - py[j], dz = zz - pz[j];
+    double rho = sqrt(dx * dx + dy * dy + dz * dz);
+    double s = dx * nx[j] + dy * ny[j] + dz * nz[j];
+    double E = exp(-kappa * rho);
+    double r3 = 1.0 / (rho * rho * rho);
+    double dG0 = c4 * s * r3;
+    double dGk = c4 * E * (1.0 + kappa * rho) * s * r3;
+    double G0mGk = c4 * (1.0 - E) / rho;
+    acc += h3 * w[j] * ((th1 * dGk - dG0) * p[j] + G0mGk * p[n + j]);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) psi[k] = red[0];
+}
+
+// out[0] = ½ Σ_k q_k ψ_k, out[1] = h³ Σ_j ω_j (one block, fixed order).
+__global__ void __launch_bounds__(kBlock) k_finish(int n_atoms, const double* __restrict__ atoms,
+                                                   const double* __restrict__ psi, int n, const double* __restrict__ w,
+                                                   double h3, double* __restrict__ out) {
+  __shared__ double r1[kBlock], r2[kBlock];
+  double a = 0.0, b = 0.0;
+  for (int k = threadIdx.x; k < n_atoms; k += kBlock) a += atoms[5 * k + 4] * psi[k];
+  for (int j = threadIdx.x; j < n; j += kBlock) b += w[j];
+  r1[threadIdx.x] = a;
+  r2[threadIdx.x] = b;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      r1[threadIdx.x] += r1[threadIdx.x + off];
+      r2[threadIdx.x] += r2[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = 0.5 * r1[0];
+    out[1] = h3 * r2[0];
+  }
+}
+
+}  // namespace
+
+pb_status rhs(pb_ctx* ctx, const pb_band* band, const double* atoms, int n_atoms, const Derived& d, double* g) {
+  const int n = (int)band->n;
+  Scope t(ctx, "rhs");
+  k_rhs<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, ctx->stream>>>(n, band->px, band->py, band->pz, band->nx,
+                                                                          band->ny, band->nz, atoms, n_atoms,
+                                                                          d.eps_in, g);
+  return launch_ok(ctx, "rhs");
+}
+
+}  // namespace pb
+
+extern "C" pb_status pb_ibim_rhs(pb_ctx* ctx, const pb_band* band, const double* atoms, int n_atoms,
+                                 const pb_params* prm, double* g) {
+  using namespace pb;
+  if (!ctx) return PB_EINVAL;
+  PB_TRY(check_params(ctx, prm));
+  PB_TRY(check_band(ctx, band));
+  if (!atoms || n_atoms <= 0 || !g) return ctx->fail(PB_EINVAL, "pb_ibim_rhs: NULL or empty input");
+  PB_HIP(ctx, hipSetDevice(ctx->device));
+  PB_TRY(rhs(ctx, band, atoms, n_atoms, derive(*prm), g));
+  return sync(ctx, "pb_ibim_rhs");
+}
+
+extern "C" pb_status pb_solvation_energy(pb_ctx* ctx, const pb_band* band, const double* atoms, int n_atoms,
+                                         const pb_params* prm, const double* p, pb_energy* out, double* psi_rxn) {
+  using namespace pb;
+  if (!ctx) return PB_EINVAL;
+  PB_TRY(check_params(ctx, prm));
+  PB_TRY(check_band(ctx, band));
+  if (!atoms || n_atoms <= 0 || !p || !out) return ctx->fail(PB_EINVAL, "pb_solvation_energy: NULL or empty input");
+  PB_HIP(ctx, hipSetDevice(ctx->device));
+  Derived d = derive(*prm);
+  const int n = (int)band->n;
+  double* psi = psi_rxn ? psi_rxn : (double*)workspace(ctx, "en_psi", sizeof(double) * n_atoms);
+  double* res = (double*)workspace(ctx, "en_out", 2 * sizeof(double));
+  if (!psi || !res) return PB_ENOMEM;
+  {
+    Scope t(ctx, "energy");
+    k_psi_rxn<<<n_atoms, kBlock, 0, ctx->stream>>>(n, band->px, band->py, band->pz, band->nx, band->ny, band->nz,
+                                                   band->w, p, atoms, d.th1, d.kappa, d.h3, psi);
+    k_finish<<<1, kBlock, 0, ctx->stream>>>(n_atoms, atoms, psi, n, band->w, d.h3, res);
+  }
+  PB_TRY(launch_ok(ctx, "energy"));
+  double h[2];
+  PB_HIP(ctx, hipMemcpyAsync(h, res, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+  PB_TRY(sync(ctx, "pb_solvation_energy"));
+  out->g_pol = h[0];
+  out->g_pol_kcal = h[0] * 4.0 * kPi * 332.0637;
+  out->area = h[1];
+  return PB_OK;
+}

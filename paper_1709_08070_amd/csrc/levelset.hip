@@ -1,0 +1,306 @@
+// Stage 1: level set of the solvent excluded surface on the Cartesian grid.
+//
+// vdW union F (eq. vdW-levelset-fn), SAS = F − ρ0, inward eikonal flow φ_t = |∇φ| to
+// t = ρ0, cavity removal by flood fill from the grid boundary, and reinitialization
+// φ_t + sgn_h(φ0)(|∇φ| − 1) = 0 (eqs. reinit, signum). Time stepping is third-order TVD
+// Runge–Kutta; |∇φ| is the Godunov Hamiltonian on fifth-order WENO one-sided derivatives.
+//
+// Layout: φ is one FP64 array, k fastest. Each stencil kernel maps one thread to one node;
+// consecutive threads are consecutive k, so the ±k neighbours are coalesced and the ±i/±j
+// neighbours are served from L2. Products and sums are rounded as written (no FMA
+// contraction) so that the grid values are reproducible to the last bit.
+#include <cmath>
+
+#include "pb_internal.hpp"
+
+#pragma clang fp contract(off)
+
+namespace pb {
+namespace {
+
+constexpr int kBlock = 256;
+
+struct GridDev {
+  int nx, ny, nz;
+  double ox, oy, oz, h;
+};
+
+__device__ __forceinline__ int64_t lin(const GridDev& g, int64_t i, int64_t j, int64_t k) {
+  return (i * g.ny + j) * g.nz + k;
+}
+
+// Even reflection about the boundary node: −m ↦ m, n−1+m ↦ n−1−m (zero Neumann).
+__device__ __forceinline__ int64_t refl(int64_t i, int64_t n) {
+  if (i < 0) return -i;
+  if (i > n - 1) return 2 * (n - 1) - i;
+  return i;
+}
+
+__device__ __forceinline__ double sq(double a) { return a * a; }
+
+// F(x) − shift over all atoms, atoms staged through LDS in tiles.
+__global__ void __launch_bounds__(kBlock) k_vdw(GridDev g, const double* __restrict__ atoms, int n_atoms,
+                                                double shift, double* __restrict__ phi) {
+  __shared__ double4 tile[kBlock];
+  int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  int64_t total = (int64_t)g.nx * g.ny * g.nz;
+  int64_t k = id % g.nz, j = (id / g.nz) % g.ny, i = id / ((int64_t)g.ny * g.nz);
+  double x = g.ox + g.h * (double)i, y = g.oy + g.h * (double)j, z = g.oz + g.h * (double)k;
+  double best = INFINITY;
+  for (int base = 0; base < n_atoms; base += kBlock) {
+    int a = base + threadIdx.x;
+    if (a < n_atoms) tile[threadIdx.x] = make_double4(atoms[5 * a], atoms[5 * a + 1], atoms[5 * a + 2], atoms[5 * a + 3]);
+    __syncthreads();
+    int m = min(kBlock, n_atoms - base);
+    for (int q = 0; q < m; ++q) {
+      double4 at = tile[q];
+      double dist = sqrt((sq(x - at.x) + sq(y - at.y)) + sq(z - at.z)) - at.w;
+      best = dist < best ? dist : best;
+    }
+    __syncthreads();
+  }
+  if (id < total) phi[id] = best - shift;
+}
+
+__device__ double weno5(double v1, double v2, double v3, double v4, double v5) {
+  const double e = 1e-6;
+  double s1 = 13.0 / 12.0 * sq(v1 - 2.0 * v2 + v3) + 0.25 * sq(v1 - 4.0 * v2 + 3.0 * v3);
+  double s2 = 13.0 / 12.0 * sq(v2 - 2.0 * v3 + v4) + 0.25 * sq(v2 - v4);
+  double s3 = 13.0 / 12.0 * sq(v3 - 2.0 * v4 + v5) + 0.25 * sq(3.0 * v3 - 4.0 * v4 + v5);
+  double a1 = 0.1 / sq(s1 + e), a2 = 0.6 / sq(s2 + e), a3 = 0.3 / sq(s3 + e);
+  double p1 = v1 / 3.0 - 7.0 * v2 / 6.0 + 11.0 * v3 / 6.0;
+  double p2 = -v2 / 6.0 + 5.0 * v3 / 6.0 + v4 / 3.0;
+  double p3 = v3 / 3.0 + 5.0 * v4 / 6.0 - v5 / 6.0;
+  return (a1 * p1 + a2 * p2 + a3 * p3) / (a1 + a2 + a3);
+}
+
+// Godunov |∇φ| for the Hamiltonian s·|∇φ| at one node.
+__device__ double godunov(const GridDev& g, const double* __restrict__ phi, int64_t i, int64_t j, int64_t k,
+                          double s) {
+  double acc = 0.0;
+  int64_t n3[3] = {g.nx, g.ny, g.nz};
+  int64_t c[3] = {i, j, k};
+  for (int ax = 0; ax < 3; ++ax) {
+    double f[7];
+    for (int sft = -3; sft <= 3; ++sft) {
+      int64_t q[3] = {c[0], c[1], c[2]};
+      q[ax] = refl(c[ax] + sft, n3[ax]);
+      f[sft + 3] = phi[lin(g, q[0], q[1], q[2])];
+    }
+    double D[6];
+    for (int m = 0; m < 6; ++m) D[m] = (f[m + 1] - f[m]) / g.h;
+    double a = weno5(D[0], D[1], D[2], D[3], D[4]);
+    double b = weno5(D[5], D[4], D[3], D[2], D[1]);
+    if (s >= 0.0) acc += fmax(sq(fmax(a, 0.0)), sq(fmin(b, 0.0)));
+    else acc += fmax(sq(fmin(a, 0.0)), sq(fmax(b, 0.0)));
+  }
+  return sqrt(acc);
+}
+
+// One TVD-RK3 stage: L = L(φ_in), then
+//   stage 0: out = φ_in + dt·L
+//   stage 1: out = 0.75 φ_n + 0.25 (φ_in + dt·L)
+//   stage 2: out = φ_n / 3 + (2/3)(φ_in + dt·L)
+// mode 0: eikonal flow (L = |∇φ| with Hamiltonian −|∇φ|); mode 1: reinit (L = −S(|∇φ| − 1)).
+__global__ void __launch_bounds__(kBlock) k_rk_stage(GridDev g, const double* __restrict__ phi_in,
+                                                     const double* __restrict__ phi_n, const double* __restrict__ S,
+                                                     double* __restrict__ out, int mode, int stage, double dt) {
+  int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  int64_t total = (int64_t)g.nx * g.ny * g.nz;
+  if (id >= total) return;
+  int64_t k = id % g.nz, j = (id / g.nz) % g.ny, i = id / ((int64_t)g.ny * g.nz);
+  double L;
+  if (mode == 0) {
+    L = godunov(g, phi_in, i, j, k, -1.0);
+  } else {
+    double s = S[id];
+    L = -s * (godunov(g, phi_in, i, j, k, s) - 1.0);
+  }
+  double v;
+  if (stage == 0) v = phi_in[id] + dt * L;
+  else if (stage == 1) v = 0.75 * phi_n[id] + 0.25 * (phi_in[id] + dt * L);
+  else v = phi_n[id] / 3.0 + (2.0 / 3.0) * (phi_in[id] + dt * L);
+  out[id] = v;
+}
+
+__global__ void __launch_bounds__(kBlock) k_sign(int64_t total, const double* __restrict__ phi, double h,
+                                                 double* __restrict__ S) {
+  int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (id < total) S[id] = phi[id] / sqrt(phi[id] * phi[id] + h * h);
+}
+
+// ---- cavity removal
+
+__global__ void __launch_bounds__(kBlock) k_cav_init(GridDev g, const double* __restrict__ phi,
+                                                     uint8_t* __restrict__ outside) {
+  int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  int64_t total = (int64_t)g.nx * g.ny * g.nz;
+  if (id >= total) return;
+  int64_t k = id % g.nz, j = (id / g.nz) % g.ny, i = id / ((int64_t)g.ny * g.nz);
+  bool edge = i == 0 || j == 0 || k == 0 || i == g.nx - 1 || j == g.ny - 1 || k == g.nz - 1;
+  outside[id] = (edge && phi[id] > 0.0) ? 1 : 0;
+}
+
+// One thread per grid line along `axis`: a forward and a backward pass, each node joining
+// the exterior if φ > 0 and any 6-neighbour is exterior. Labels only go 0 → 1, so reads of
+// neighbours being updated by other lines are harmless; repeated sweeps reach the unique
+// fixed point, the 6-connected component of {φ > 0} that touches the boundary.
+__global__ void __launch_bounds__(kBlock) k_cav_sweep(GridDev g, const double* __restrict__ phi,
+                                                      uint8_t* outside, int axis, int* changed) {
+  int64_t line = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  int64_t n3[3] = {g.nx, g.ny, g.nz};
+  int a1 = axis == 0 ? 1 : 0, a2 = axis == 2 ? 1 : 2;
+  if (line >= n3[a1] * n3[a2]) return;
+  int64_t c[3];
+  c[a1] = line / n3[a2];
+  c[a2] = line % n3[a2];
+  int any = 0;
+  for (int dir = 0; dir < 2; ++dir) {
+    for (int64_t t = 0; t < n3[axis]; ++t) {
+      c[axis] = dir == 0 ? t : n3[axis] - 1 - t;
+      int64_t id = lin(g, c[0], c[1], c[2]);
+      if (outside[id] || !(phi[id] > 0.0)) continue;
+      bool hit = false;
+      for (int ax = 0; ax < 3 && !hit; ++ax)
+        for (int s = -1; s <= 1 && !hit; s += 2) {
+          int64_t q[3] = {c[0], c[1], c[2]};
+          q[ax] += s;
+          if (q[ax] < 0 || q[ax] >= n3[ax]) continue;
+          if (outside[lin(g, q[0], q[1], q[2])]) hit = true;
+        }
+      if (hit) {
+        outside[id] = 1;
+        any = 1;
+      }
+    }
+  }
+  if (any) *changed = 1;
+}
+
+// Unreached nodes within (ε + h) of a cavity node (unreached, φ > 0) get −ε.
+__global__ void __launch_bounds__(kBlock) k_cav_dilate(GridDev g, const double* __restrict__ phi,
+                                                       const uint8_t* __restrict__ outside, double eps, int m,
+                                                       double rr2, double* __restrict__ out, int* n_set) {
+  int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  int64_t total = (int64_t)g.nx * g.ny * g.nz;
+  if (id >= total) return;
+  double v = phi[id];
+  if (!outside[id]) {
+    int64_t k = id % g.nz, j = (id / g.nz) % g.ny, i = id / ((int64_t)g.ny * g.nz);
+    bool hit = v > 0.0;
+    for (int a = -m; a <= m && !hit; ++a)
+      for (int b = -m; b <= m && !hit; ++b)
+        for (int c = -m; c <= m && !hit; ++c) {
+          if ((double)(a * a + b * b + c * c) > rr2) continue;
+          int64_t ii = i + a, jj = j + b, kk = k + c;
+          if (ii < 0 || jj < 0 || kk < 0 || ii >= g.nx || jj >= g.ny || kk >= g.nz) continue;
+          int64_t q = lin(g, ii, jj, kk);
+          if (!outside[q] && phi[q] > 0.0) hit = true;
+        }
+    if (hit) {
+      v = -eps;
+      atomicAdd(n_set, 1);
+    }
+  }
+  out[id] = v;
+}
+
+unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+// Three-stage TVD-RK3 for `steps` steps of size dt; φ is updated in place.
+pb_status tvd_rk3(pb_ctx* ctx, const GridDev& g, double* phi, double* p1, double* p2, const double* S, int mode,
+                  int steps, double dt) {
+  int64_t total = (int64_t)g.nx * g.ny * g.nz;
+  unsigned nb = blocks_for(total);
+  for (int s = 0; s < steps; ++s) {
+    Scope t(ctx, "levelset");
+    k_rk_stage<<<nb, kBlock, 0, ctx->stream>>>(g, phi, phi, S, p1, mode, 0, dt);
+    k_rk_stage<<<nb, kBlock, 0, ctx->stream>>>(g, p1, phi, S, p2, mode, 1, dt);
+    k_rk_stage<<<nb, kBlock, 0, ctx->stream>>>(g, p2, phi, S, p1, mode, 2, dt);
+    PB_HIP(ctx, hipMemcpyAsync(phi, p1, sizeof(double) * total, hipMemcpyDeviceToDevice, ctx->stream));
+  }
+  return launch_ok(ctx, "levelset rk3");
+}
+
+}  // namespace
+}  // namespace pb
+
+extern "C" pb_status pb_build_levelset(pb_ctx* ctx, const double* atoms, int n_atoms, const pb_params* prm,
+                                       const pb_grid* grid, double* phi) {
+  using namespace pb;
+  if (!ctx) return PB_EINVAL;
+  PB_TRY(check_params(ctx, prm));
+  if (!atoms || n_atoms <= 0 || !grid || !phi) return ctx->fail(PB_EINVAL, "pb_build_levelset: NULL or empty input");
+  if (grid->nx < 7 || grid->ny < 7 || grid->nz < 7)
+    return ctx->fail(PB_EINVAL, "pb_build_levelset: grid must be at least 7 nodes per axis");
+  if (std::fabs(grid->h - prm->h) > 1e-12 * prm->h)
+    return ctx->fail(PB_EINVAL, "pb_build_levelset: grid spacing differs from params.h");
+  PB_HIP(ctx, hipSetDevice(ctx->device));
+  GridDev g{grid->nx, grid->ny, grid->nz, grid->origin[0], grid->origin[1], grid->origin[2], grid->h};
+  int64_t total = (int64_t)g.nx * g.ny * g.nz;
+  unsigned nb = blocks_for(total);
+  const double h = prm->h;
+  const bool ses = prm->ls_mode == PB_LS_SES;
+  {
+    Scope t(ctx, "levelset");
+    k_vdw<<<nb, kBlock, 0, ctx->stream>>>(g, atoms, n_atoms, ses ? prm->probe : 0.0, phi);
+  }
+  PB_TRY(launch_ok(ctx, "vdw"));
+  if (!ses) return sync(ctx, "pb_build_levelset");
+
+  double* p1 = (double*)workspace(ctx, "ls_p1", sizeof(double) * total);
+  double* p2 = (double*)workspace(ctx, "ls_p2", sizeof(double) * total);
+  double* S = (double*)workspace(ctx, "ls_S", sizeof(double) * total);
+  uint8_t* outside = (uint8_t*)workspace(ctx, "ls_outside", (size_t)total);
+  int* flags = (int*)workspace(ctx, "ls_flags", 4 * sizeof(int));
+  if (!p1 || !p2 || !S || !outside || !flags) return PB_ENOMEM;
+
+  // inward eikonal flow to t = ρ0 in equal steps no longer than cfl·h
+  if (prm->probe > 0.0) {
+    int n_e = (int)std::ceil(prm->probe / (prm->cfl * h) - 1e-9);
+    PB_TRY(tvd_rk3(ctx, g, phi, p1, p2, nullptr, 0, n_e, prm->probe / n_e));
+  }
+
+  // cavity removal
+  {
+    Scope t(ctx, "levelset");
+    k_cav_init<<<nb, kBlock, 0, ctx->stream>>>(g, phi, outside);
+  }
+  PB_TRY(launch_ok(ctx, "cavity init"));
+  int64_t n3[3] = {g.nx, g.ny, g.nz};
+  int it = 0;
+  for (;; ++it) {
+    if (it > 100000) return ctx->fail(PB_EDEVICE, "cavity flood fill did not converge");
+    PB_HIP(ctx, hipMemsetAsync(flags, 0, sizeof(int), ctx->stream));
+    for (int ax = 0; ax < 3; ++ax) {
+      int a1 = ax == 0 ? 1 : 0, a2 = ax == 2 ? 1 : 2;
+      Scope t(ctx, "levelset");
+      k_cav_sweep<<<blocks_for(n3[a1] * n3[a2]), kBlock, 0, ctx->stream>>>(g, phi, outside, ax, flags);
+    }
+    PB_TRY(launch_ok(ctx, "cavity sweep"));
+    int changed = 0;
+    PB_HIP(ctx, hipMemcpyAsync(&changed, flags, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    PB_TRY(sync(ctx, "cavity sweep"));
+    if (!changed) break;
+  }
+  const double eps = prm->band_k * h;
+  const double rr = (eps + h) / h;
+  PB_HIP(ctx, hipMemsetAsync(flags + 1, 0, sizeof(int), ctx->stream));
+  {
+    Scope t(ctx, "levelset");
+    k_cav_dilate<<<nb, kBlock, 0, ctx->stream>>>(g, phi, outside, eps, (int)std::floor(rr), rr * rr, p1, flags + 1);
+  }
+  PB_TRY(launch_ok(ctx, "cavity dilate"));
+  PB_HIP(ctx, hipMemcpyAsync(phi, p1, sizeof(double) * total, hipMemcpyDeviceToDevice, ctx->stream));
+
+  // reinitialization with the frozen smoothed sign of the post-removal φ
+  int steps = prm->reinit_steps > 0 ? prm->reinit_steps
+                                    : 2 * (int)std::ceil((prm->band_k + 4.0) / prm->cfl - 1e-9);
+  {
+    Scope t(ctx, "levelset");
+    k_sign<<<nb, kBlock, 0, ctx->stream>>>(total, phi, h, S);
+  }
+  PB_TRY(launch_ok(ctx, "sign"));
+  PB_TRY(tvd_rk3(ctx, g, phi, p1, p2, S, 1, steps, prm->cfl * h));
+  return sync(ctx, "pb_build_levelset");
+}

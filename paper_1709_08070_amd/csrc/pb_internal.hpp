@@ -1,0 +1,119 @@
+// Internal declarations of the MI355X IBIM library (not part of the C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/pb.h"
+
+namespace pb {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// Parameters derived once per call from pb_params, in the form the kernels consume.
+struct Derived {
+  double h, h3, eps, tau, tau2, four_tau2;
+  double th1, th2;        // ε_E/ε_I, ε_I/ε_E
+  double lam1, lam2;      // ½(1+ε_E/ε_I), ½(1+ε_I/ε_E)
+  double kappa;
+  double eps_in;
+  double k12bar;          // disc average of G0 − Gκ over radius τ
+  double rc;              // mixed path: near-field radius
+  int metric;
+};
+
+Derived derive(const pb_params& p);
+
+// Growable device buffer owned by the context.
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+// Geometry of the mixed-precision operator for one band: centre of the FP32 coordinates
+// and the cell list of the near field.
+struct MixedPlan {
+  const void* band_key = nullptr;
+  int64_t n = 0;
+  double cx = 0, cy = 0, cz = 0;
+  double rc = 0;
+  float rc2f = 0;
+  double cell = 0;
+  int ncx = 0, ncy = 0, ncz = 0;
+};
+
+// Per-kernel-family event timing.
+struct Timer {
+  double ms = 0.0;
+  int64_t launches = 0;
+};
+
+}  // namespace pb
+
+struct pb_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  std::map<std::string, pb::DevBuf> bufs;
+  bool timing = false;
+  std::map<std::string, pb::Timer> timers;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;  // per launch, resolved at sync
+  std::vector<std::string> pending_name;
+  std::vector<hipEvent_t> event_pool;
+  int n_cu = 256;
+  pb::MixedPlan mixed;
+  // status of the last allocation/launch
+  pb_status fail(pb_status s, const char* fmt, ...);
+};
+
+namespace pb {
+
+// Returns a device buffer of at least `bytes` under `name` (reallocated if smaller).
+void* workspace(pb_ctx* ctx, const char* name, size_t bytes);
+
+// Event timing around kernel launches on the context stream.
+struct Scope {
+  pb_ctx* ctx;
+  const char* name;
+  hipEvent_t a{}, b{};
+  Scope(pb_ctx* c, const char* n);
+  ~Scope();
+};
+void flush_timers(pb_ctx* ctx);  // after a stream synchronize
+
+pb_status check_params(pb_ctx* ctx, const pb_params* p);
+pb_status check_band(pb_ctx* ctx, const pb_band* b);
+pb_status sync(pb_ctx* ctx, const char* where);
+pb_status launch_ok(pb_ctx* ctx, const char* where);
+
+// Scans and reductions shared by the stages.
+// Exclusive scan of n int64 values in place on the context stream; returns the total on host.
+pb_status exclusive_scan_i64(pb_ctx* ctx, int64_t* data, int64_t n, int64_t* total_host);
+
+// Operator internals used by the solver.
+pb_status matvec_fp64(pb_ctx* ctx, const pb_band* band, const Derived& d, const double* p, double* y);
+pb_status mixed_prepare(pb_ctx* ctx, const pb_band* band, const Derived& d);
+pb_status matvec_mixed(pb_ctx* ctx, const pb_band* band, const Derived& d, const double* p, double* y);
+pb_status rhs(pb_ctx* ctx, const pb_band* band, const double* atoms, int n_atoms, const Derived& d, double* g);
+
+}  // namespace pb
+
+#define PB_HIP(ctx, call)                                                                   \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return (ctx)->fail(PB_EDEVICE, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                         __FILE__, __LINE__);                                               \
+  } while (0)
+
+#define PB_TRY(expr)              \
+  do {                            \
+    pb_status s_ = (expr);        \
+    if (s_ != PB_OK) return s_;   \
+  } while (0)

@@ -1,0 +1,323 @@
+// Stage 3: GMRES on Λp + KWp = g (section "Fast linear solvers").
+//
+// Restarted GMRES with classical Gram–Schmidt applied twice (CGS2). The Krylov basis and
+// every vector operation live in FP64 device memory; each Arnoldi step copies one
+// Hessenberg column (2(j+1)+1 doubles) to the host, where the Givens rotations and the
+// residual estimate are updated. Dot products are two-stage fixed-order reductions.
+//
+// Initial guess: Λ⁻¹g by default, the paper's "solution of the diagonal part" with D = 0.
+// Mixed precision: iterative refinement. Each outer step forms the true FP64 residual
+// r = g − A₆₄x and solves A_mixed d = r by GMRES to an absolute residual of ½·tol·‖g‖, then
+// x ← x + d; the loop ends when the FP64 residual meets tol.
+#include <chrono>
+#include <cmath>
+#include <functional>
+#include <vector>
+
+#include "pb_internal.hpp"
+
+namespace pb {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kDotBlocks = 512;
+constexpr int kGroup = 8;
+
+// partial[q·nb + block] = Σ_{e in block's stride} w[e]·V[q][e], q < k, in groups of 8
+// vectors so that w is read once per group.
+__global__ void __launch_bounds__(kBlock) k_dots(int64_t M, const double* __restrict__ V, int64_t ldv, int k,
+                                                 const double* __restrict__ w, double* __restrict__ partial) {
+  __shared__ double red[kGroup][kBlock];
+  for (int q0 = 0; q0 < k; q0 += kGroup) {
+    double acc[kGroup];
+#pragma unroll
+    for (int g = 0; g < kGroup; ++g) acc[g] = 0.0;
+    const int nq = min(kGroup, k - q0);
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < M; e += (int64_t)gridDim.x * kBlock) {
+      const double we = w[e];
+#pragma unroll
+      for (int g = 0; g < kGroup; ++g)
+        if (g < nq) acc[g] += we * V[(int64_t)(q0 + g) * ldv + e];
+    }
+#pragma unroll
+    for (int g = 0; g < kGroup; ++g) red[g][threadIdx.x] = acc[g];
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+      if (threadIdx.x < off)
+#pragma unroll
+        for (int g = 0; g < kGroup; ++g) red[g][threadIdx.x] += red[g][threadIdx.x + off];
+      __syncthreads();
+    }
+    if (threadIdx.x < nq) partial[(int64_t)(q0 + threadIdx.x) * gridDim.x + blockIdx.x] = red[threadIdx.x][0];
+    __syncthreads();
+  }
+}
+
+// out[q] = Σ_b partial[q·nb + b] (one block per q, fixed tree); if sq, out[q] = sqrt(out[q]).
+__global__ void __launch_bounds__(kBlock) k_dots_finish(const double* __restrict__ partial, int nb,
+                                                        double* __restrict__ out, int sqrt_out) {
+  __shared__ double red[kBlock];
+  const int q = blockIdx.x;
+  double a = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kBlock) a += partial[(int64_t)q * nb + b];
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[q] = sqrt_out ? sqrt(red[0]) : red[0];
+}
+
+// w[e] += sign · Σ_q c[q] V[q][e]
+__global__ void __launch_bounds__(kBlock) k_axpy_multi(int64_t M, const double* __restrict__ V, int64_t ldv, int k,
+                                                       const double* __restrict__ c, double sign,
+                                                       double* __restrict__ w) {
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < M; e += (int64_t)gridDim.x * kBlock) {
+    double s = 0.0;
+    for (int q = 0; q < k; ++q) s += c[q] * V[(int64_t)q * ldv + e];
+    w[e] += sign * s;
+  }
+}
+
+// out = in / *nrm
+__global__ void __launch_bounds__(kBlock) k_scale(int64_t M, const double* __restrict__ in,
+                                                  const double* __restrict__ nrm, double* __restrict__ out) {
+  const double s = 1.0 / *nrm;
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < M; e += (int64_t)gridDim.x * kBlock)
+    out[e] = in[e] * s;
+}
+
+// r = b − r
+__global__ void __launch_bounds__(kBlock) k_residual(int64_t M, const double* __restrict__ b, double* __restrict__ r) {
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < M; e += (int64_t)gridDim.x * kBlock)
+    r[e] = b[e] - r[e];
+}
+
+// x = Λ⁻¹ g
+__global__ void __launch_bounds__(kBlock) k_diag_solve(int64_t n, const double* __restrict__ g, double lam1, double lam2,
+                                                       double* __restrict__ x) {
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < 2 * n; e += (int64_t)gridDim.x * kBlock)
+    x[e] = g[e] / (e < n ? lam1 : lam2);
+}
+
+__global__ void __launch_bounds__(kBlock) k_add(int64_t M, const double* __restrict__ d, double* __restrict__ x) {
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < M; e += (int64_t)gridDim.x * kBlock) x[e] += d[e];
+}
+
+__global__ void __launch_bounds__(kBlock) k_zero(int64_t M, double* __restrict__ x) {
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < M; e += (int64_t)gridDim.x * kBlock) x[e] = 0.0;
+}
+
+unsigned vec_blocks(int64_t M) { return (unsigned)std::min<int64_t>(2048, (M + kBlock - 1) / kBlock); }
+
+using OpFn = std::function<pb_status(const double*, double*)>;
+
+struct Krylov {
+  pb_ctx* ctx;
+  int64_t M;
+  double* partial;  // kDotBlocks × (m+1)
+  double* hcol;     // device: [pass1 (m+1) | pass2 (m+1) | norm]
+  int m;
+};
+
+// ‖v‖₂ to host
+pb_status norm2(pb_ctx* ctx, Krylov& K, const double* v, double* out) {
+  k_dots<<<kDotBlocks, kBlock, 0, ctx->stream>>>(K.M, v, 0, 1, v, K.partial);
+  k_dots_finish<<<1, kBlock, 0, ctx->stream>>>(K.partial, kDotBlocks, K.hcol + 2 * (K.m + 1), 1);
+  PB_TRY(launch_ok(ctx, "norm"));
+  PB_HIP(ctx, hipMemcpyAsync(out, K.hcol + 2 * (K.m + 1), sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  return sync(ctx, "norm");
+}
+
+// Restarted GMRES(m) for A x = b from the given x until ‖b − Ax‖ ≤ tol_abs (estimate, then
+// confirmed with the operator at each restart) or max_iter operator applications.
+pb_status gmres(pb_ctx* ctx, Krylov& K, const OpFn& op, const double* b, double* x, double tol_abs, int max_iter,
+                int* iters, double* res_out) {
+  const int64_t M = K.M;
+  const int m = K.m;
+  double* V = (double*)workspace(ctx, "kr_V", sizeof(double) * (size_t)M * (m + 1));
+  double* r = (double*)workspace(ctx, "kr_r", sizeof(double) * (size_t)M);
+  double* ydev = (double*)workspace(ctx, "kr_y", sizeof(double) * (size_t)(m + 1));
+  if (!V || !r || !ydev) return PB_ENOMEM;
+  const unsigned vb = vec_blocks(M);
+  std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), s(m + 1), y(m), col(2 * (m + 1) + 1);
+  PB_TRY(op(x, r));
+  k_residual<<<vb, kBlock, 0, ctx->stream>>>(M, b, r);
+  double beta = 0.0;
+  PB_TRY(norm2(ctx, K, r, &beta));
+  int it = 0;
+  for (;;) {
+    if (!(beta > tol_abs) || it >= max_iter) break;
+    {
+      Scope t(ctx, "gmres");
+      k_scale<<<vb, kBlock, 0, ctx->stream>>>(M, r, K.hcol + 2 * (m + 1), V);  // norm2 left ‖r‖ there
+    }
+    std::fill(s.begin(), s.end(), 0.0);
+    s[0] = beta;
+    int k = 0;
+    for (; k < m && it < max_iter; ++k) {
+      double* w = V + (size_t)(k + 1) * M;
+      PB_TRY(op(V + (size_t)k * M, w));
+      ++it;
+      {
+        Scope t(ctx, "gmres");
+        for (int pass = 0; pass < 2; ++pass) {
+          double* hv = K.hcol + pass * (m + 1);
+          k_dots<<<kDotBlocks, kBlock, 0, ctx->stream>>>(M, V, M, k + 1, w, K.partial);
+          k_dots_finish<<<k + 1, kBlock, 0, ctx->stream>>>(K.partial, kDotBlocks, hv, 0);
+          k_axpy_multi<<<vb, kBlock, 0, ctx->stream>>>(M, V, M, k + 1, hv, -1.0, w);
+        }
+        k_dots<<<kDotBlocks, kBlock, 0, ctx->stream>>>(M, w, 0, 1, w, K.partial);
+        k_dots_finish<<<1, kBlock, 0, ctx->stream>>>(K.partial, kDotBlocks, K.hcol + 2 * (m + 1), 1);
+      }
+      PB_TRY(launch_ok(ctx, "arnoldi"));
+      PB_HIP(ctx, hipMemcpyAsync(col.data(), K.hcol, sizeof(double) * col.size(), hipMemcpyDeviceToHost, ctx->stream));
+      PB_TRY(sync(ctx, "arnoldi"));
+      const double hn = col[2 * (m + 1)];
+      for (int i = 0; i <= k; ++i) H[(size_t)i * m + k] = col[i] + col[(m + 1) + i];
+      H[(size_t)(k + 1) * m + k] = hn;
+      if (hn > 0.0) {
+        Scope t(ctx, "gmres");
+        k_scale<<<vb, kBlock, 0, ctx->stream>>>(M, w, K.hcol + 2 * (m + 1), w);
+      }
+      for (int i = 0; i < k; ++i) {
+        double a = H[(size_t)i * m + k], bb = H[(size_t)(i + 1) * m + k];
+        H[(size_t)i * m + k] = cs[i] * a + sn[i] * bb;
+        H[(size_t)(i + 1) * m + k] = -sn[i] * a + cs[i] * bb;
+      }
+      double a = H[(size_t)k * m + k], bb = H[(size_t)(k + 1) * m + k];
+      double den = std::sqrt(a * a + bb * bb);
+      cs[k] = den > 0 ? a / den : 1.0;
+      sn[k] = den > 0 ? bb / den : 0.0;
+      H[(size_t)k * m + k] = den;
+      H[(size_t)(k + 1) * m + k] = 0.0;
+      s[k + 1] = -sn[k] * s[k];
+      s[k] = cs[k] * s[k];
+      if (std::fabs(s[k + 1]) <= tol_abs || !(hn > 0.0)) {
+        ++k;
+        break;
+      }
+    }
+    for (int i = k - 1; i >= 0; --i) {
+      double acc = s[i];
+      for (int j = i + 1; j < k; ++j) acc -= H[(size_t)i * m + j] * y[j];
+      y[i] = acc / H[(size_t)i * m + i];
+    }
+    PB_HIP(ctx, hipMemcpyAsync(ydev, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, ctx->stream));
+    k_axpy_multi<<<vb, kBlock, 0, ctx->stream>>>(M, V, M, k, ydev, 1.0, x);
+    PB_TRY(launch_ok(ctx, "update"));
+    PB_TRY(op(x, r));
+    k_residual<<<vb, kBlock, 0, ctx->stream>>>(M, b, r);
+    PB_TRY(norm2(ctx, K, r, &beta));
+  }
+  *iters = it;
+  *res_out = beta;
+  return PB_OK;
+}
+
+}  // namespace
+}  // namespace pb
+
+extern "C" pb_status pb_ibim_solve(pb_ctx* ctx, const pb_band* band, const double* atoms, int n_atoms,
+                                   const pb_params* prm, const pb_solve_opts* opts_in, double* p,
+                                   pb_solve_stats* stats) {
+  using namespace pb;
+  auto t0 = std::chrono::steady_clock::now();
+  if (!ctx) return PB_EINVAL;
+  PB_TRY(check_params(ctx, prm));
+  PB_TRY(check_band(ctx, band));
+  pb_solve_opts opts;
+  if (opts_in) opts = *opts_in;
+  else pb_default_solve_opts(&opts);
+  if (!atoms || n_atoms <= 0 || !p) return ctx->fail(PB_EINVAL, "pb_ibim_solve: NULL or empty input");
+  if (!(opts.tol > 0.0) || !std::isfinite(opts.tol)) return ctx->fail(PB_EINVAL, "tolerance must be positive");
+  if (opts.max_iter < 1 || opts.restart < 1 || opts.restart > 2000) return ctx->fail(PB_EINVAL, "bad iteration limits");
+  if (opts.precision != PB_FP64 && opts.precision != PB_MIXED) return ctx->fail(PB_EINVAL, "unknown precision");
+  if (opts.precision == PB_MIXED && prm->reg_metric == PB_REG_TANGENT)
+    return ctx->fail(PB_EINVAL, "the mixed path needs a bounded regularization radius");
+  if (opts.x0 < PB_X0_ZERO || opts.x0 > PB_X0_USER)
+    return ctx->fail(PB_EINVAL, "x0 mode %d not available in this call", opts.x0);
+  if (opts.precond != PB_PRECOND_NONE) return ctx->fail(PB_EINVAL, "preconditioner not available in this call");
+  PB_HIP(ctx, hipSetDevice(ctx->device));
+  PB_TRY(sync(ctx, "pb_ibim_solve"));
+  auto matvec_ms = [&]() {
+    double tm = 0.0;
+    for (const char* nm : {"p2p_f64", "p2p_f32", "near_f64", "reduce"}) {
+      auto itt = ctx->timers.find(nm);
+      if (itt != ctx->timers.end()) tm += itt->second.ms;
+    }
+    return tm;
+  };
+  const double tm0 = matvec_ms();
+  const Derived d = derive(*prm);
+  const int64_t n = band->n, M = 2 * n;
+  const int m = opts.restart;
+  Krylov K{ctx, M, (double*)workspace(ctx, "kr_partial", sizeof(double) * kDotBlocks * (size_t)(m + 1)),
+           (double*)workspace(ctx, "kr_hcol", sizeof(double) * (size_t)(2 * (m + 1) + 1)), m};
+  double* g = (double*)workspace(ctx, "sv_g", sizeof(double) * M);
+  double* r = (double*)workspace(ctx, "sv_r", sizeof(double) * M);
+  double* dx = (double*)workspace(ctx, "sv_d", sizeof(double) * M);
+  if (!K.partial || !K.hcol || !g || !r || !dx) return PB_ENOMEM;
+  const unsigned vb = vec_blocks(M);
+
+  PB_TRY(rhs(ctx, band, atoms, n_atoms, d, g));
+  double gnorm = 0.0;
+  PB_TRY(norm2(ctx, K, g, &gnorm));
+  if (!std::isfinite(gnorm)) return ctx->fail(PB_EINVAL, "non-finite right-hand side");
+  if (gnorm == 0.0) gnorm = 1.0;
+  if (opts.x0 == PB_X0_DIAG) k_diag_solve<<<vb, kBlock, 0, ctx->stream>>>(n, g, d.lam1, d.lam2, p);
+  else if (opts.x0 == PB_X0_ZERO) k_zero<<<vb, kBlock, 0, ctx->stream>>>(M, p);
+  PB_TRY(launch_ok(ctx, "x0"));
+
+  int n64 = 0, nmx = 0;
+  OpFn op64 = [&](const double* in, double* out) {
+    ++n64;
+    return matvec_fp64(ctx, band, d, in, out);
+  };
+  OpFn opmx = [&](const double* in, double* out) {
+    ++nmx;
+    return matvec_mixed(ctx, band, d, in, out);
+  };
+  int iters = 0, outer = 0;
+  double relres = 0.0;
+  if (opts.precision == PB_FP64) {
+    double res = 0.0;
+    PB_TRY(gmres(ctx, K, op64, g, p, opts.tol * gnorm, opts.max_iter, &iters, &res));
+    relres = res / gnorm;
+    outer = 1;
+  } else {
+    for (;;) {
+      PB_TRY(op64(p, r));
+      k_residual<<<vb, kBlock, 0, ctx->stream>>>(M, g, r);
+      double rn = 0.0;
+      PB_TRY(norm2(ctx, K, r, &rn));
+      relres = rn / gnorm;
+      if (!(relres > opts.tol) || outer >= opts.max_outer || iters >= opts.max_iter) break;
+      k_zero<<<vb, kBlock, 0, ctx->stream>>>(M, dx);
+      int it = 0;
+      double res = 0.0;
+      PB_TRY(gmres(ctx, K, opmx, r, dx, 0.5 * opts.tol * gnorm, opts.max_iter - iters, &it, &res));
+      iters += it;
+      k_add<<<vb, kBlock, 0, ctx->stream>>>(M, dx, p);
+      PB_TRY(launch_ok(ctx, "refine"));
+      ++outer;
+    }
+  }
+  PB_TRY(sync(ctx, "pb_ibim_solve"));
+  if (stats) {
+    stats->iters = iters;
+    stats->outer = outer;
+    stats->converged = relres <= opts.tol;
+    stats->fallback_used = 0;
+    stats->matvecs_fp64 = n64;
+    stats->matvecs_mixed = nmx;
+    stats->true_relres = relres;
+    stats->pairs = (double)(n64 + nmx) * (double)n * (double)n;
+    stats->t_matvec_s = (matvec_ms() - tm0) * 1e-3;
+    stats->t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (!std::isfinite(relres)) return ctx->fail(PB_ENOCONV, "solver produced a non-finite residual");
+  if (relres > opts.tol) return ctx->fail(PB_ENOCONV, "GMRES stopped at relative residual %.3e", relres);
+  return PB_OK;
+}
