@@ -39,6 +39,35 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def kernel_source_hash(path: str, name: str) -> str:
+    import hashlib
+
+    text = open(path).read()
+    i = text.index(f"__global__ void __launch_bounds__(kBlock) {name}(")
+    j = text.index("\n}\n", i)
+    return hashlib.sha256(text[i:j].encode()).hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None when the
+    kernel's source has changed since the counters were taken (or none were taken)."""
+    path = os.path.join(ROOT, "profiles", f"{kernel.replace('k_', '')}_{workload}_hbm.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    src = os.path.join(ROOT, kv.get("source", ""))
+    try:
+        if kernel_source_hash(src, kernel) != kv.get("kernel_source_sha256_16"):
+            return None
+    except (OSError, ValueError):
+        return None
+    return float(kv["traffic_bytes"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -48,6 +77,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 time-to-solution comparison")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first run one device-to-device copy of this many MiB (a reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is "
@@ -58,6 +89,15 @@ def main():
     import torch
 
     from paper_1709_08070_amd import pb, synth
+
+    if args.calibrate_copy:
+        src = torch.ones(args.calibrate_copy * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calibrate_copy} MiB read + {args.calibrate_copy} MiB written")
+        del src, dst
 
     n_atoms, seed, h = WORKLOADS[args.workload]
     atoms = synth.globule(n_atoms, seed)
@@ -105,7 +145,8 @@ def main():
     per_launch_s = f32_ms * 1e-3 / max(f32_n, 1)
     achieved = FLOP_PER_PAIR * float(n) * float(n) / per_launch_s if f32_n else 0.0
     roofline = {"kernel": "k_p2p_f32", "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32,
+                "traffic": measured_traffic("k_p2p_f32", args.workload),
                 "avg_launch_ms": per_launch_s * 1e3, "launches": f32_n,
                 "pairs_per_s": float(n) * float(n) / per_launch_s if f32_n else 0.0,
                 "p2p_f64_avg_ms": f64_ms / max(f64_n, 1), "near_f64_avg_ms": near_ms / max(near_n, 1)}

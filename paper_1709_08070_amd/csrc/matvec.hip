@@ -40,11 +40,12 @@ KParams kparams(const Derived& d) {
 
 // ----------------------------------------------------------------- FP64 pair
 
-// Accumulates one pair in FP64. The regularization predicate uses the products and sums
-// exactly as written (no contraction) so that it is decided as in a plain evaluation.
-__device__ __forceinline__ void pair_f64(double xi, double yi, double zi, double nxi, double nyi, double nzi,
-                                         double xj, double yj, double zj, double nxj, double nyj, double nzj,
-                                         double wpsi, double wpsn, const KParams& kp, double& s1, double& s2) {
+// The four kernels times 4π for one pair in FP64: k[0] = 4πK11, k[1] = 4πK12, k[2] = 4πK21,
+// k[3] = 4πK22. The regularization predicate uses the products and sums exactly as written
+// (no contraction) so that it is decided as in a plain evaluation.
+__device__ __forceinline__ void kern4_f64(double xi, double yi, double zi, double nxi, double nyi, double nzi,
+                                          double xj, double yj, double zj, double nxj, double nyj, double nzj,
+                                          const KParams& kp, double k[4]) {
   double dx = xi - xj, dy = yi - yj, dz = zi - zj;
   double r2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
   double dnx = __dadd_rn(__dadd_rn(__dmul_rn(dx, nxi), __dmul_rn(dy, nyi)), __dmul_rn(dz, nzi));
@@ -54,21 +55,41 @@ __device__ __forceinline__ void pair_f64(double xi, double yi, double zi, double
   else if (kp.metric == PB_REG_TANGENT) reg = t2 < kp.tau2;
   else reg = t2 < kp.tau2 && r2 < kp.four_tau2;
   if (reg) {
-    s1 -= kp.k12bar4pi * wpsn;
+    k[0] = 0.0;
+    k[1] = kp.k12bar4pi;
+    k[2] = 0.0;
+    k[3] = 0.0;
     return;
   }
   double dny = dx * nxj + dy * nyj + dz * nzj;
   double nn = nxi * nxj + nyi * nyj + nzi * nzj;
-  double r = sqrt(r2);
-  double rinv = 1.0 / r;
+  // 1/r from the hardware reciprocal square root refined by two Newton steps
+  double rinv = __builtin_amdgcn_rsq(r2);
+  double e = fma(-r2 * rinv, rinv, 1.0);
+  rinv = fma(0.5 * rinv, e, rinv);
+  e = fma(-r2 * rinv, rinv, 1.0);
+  rinv = fma(0.5 * rinv, e, rinv);
+  double r = r2 * rinv;
   double r3 = rinv * rinv * rinv;
   double r5 = r3 * rinv * rinv;
   double z = kp.kappa * r;
   double E = exp(-z);
   double a = E * (1.0 + z);
   double b = E * (3.0 + 3.0 * z + z * z);
-  s1 += dny * (1.0 - kp.th1 * a) * r3 * wpsi - (1.0 - E) * rinv * wpsn;
-  s2 += (nn * (1.0 - a) * r3 - dnx * dny * (3.0 - b) * r5) * wpsi + dnx * (1.0 - kp.th2 * a) * r3 * wpsn;
+  k[0] = dny * (1.0 - kp.th1 * a) * r3;
+  k[1] = (1.0 - E) * rinv;
+  k[2] = nn * (1.0 - a) * r3 - dnx * dny * (3.0 - b) * r5;
+  k[3] = -dnx * (1.0 - kp.th2 * a) * r3;
+}
+
+// Accumulates one pair: s1 += 4πK11·wψ − 4πK12·wψn, s2 += 4πK21·wψ − 4πK22·wψn.
+__device__ __forceinline__ void pair_f64(double xi, double yi, double zi, double nxi, double nyi, double nzi,
+                                         double xj, double yj, double zj, double nxj, double nyj, double nzj,
+                                         double wpsi, double wpsn, const KParams& kp, double& s1, double& s2) {
+  double k[4];
+  kern4_f64(xi, yi, zi, nxi, nyi, nzi, xj, yj, zj, nxj, nyj, nzj, kp, k);
+  s1 += k[0] * wpsi - k[1] * wpsn;
+  s2 += k[2] * wpsi - k[3] * wpsn;
 }
 
 // Source weights h³ω_j ψ_j/(4π), h³ω_j ψn_j/(4π) in FP64.
@@ -149,14 +170,11 @@ __device__ __forceinline__ float r2_f32(float xi, float yi, float zi, float xj, 
 // Source records: A = (x, y, z, h³ωψ/4π), B = (n_x, n_y, n_z, h³ωψn/4π), centroid-relative FP32.
 __global__ void __launch_bounds__(kBlock) k_pack_f32(int n, BandDev b, const double* __restrict__ w,
                                                      const double* __restrict__ p, double scale, double cx, double cy,
-                                                     double cz, float4* __restrict__ A, float4* __restrict__ B,
-                                                     double* __restrict__ wpsi, double* __restrict__ wpsn) {
+                                                     double cz, float4* __restrict__ A, float4* __restrict__ B) {
   int j = blockIdx.x * kBlock + threadIdx.x;
   if (j >= n) return;
   double s = scale * w[j];
-  double w1 = s * p[j], w2 = s * p[n + j];
-  wpsi[j] = w1;
-  wpsn[j] = w2;
+  double w1 = p ? s * p[j] : 0.0, w2 = p ? s * p[n + j] : 0.0;
   A[j] = make_float4((float)(b.px[j] - cx), (float)(b.py[j] - cy), (float)(b.pz[j] - cz), (float)w1);
   B[j] = make_float4((float)b.nx[j], (float)b.ny[j], (float)b.nz[j], (float)w2);
 }
@@ -288,17 +306,13 @@ __global__ void __launch_bounds__(kBlock) k_cell_sort(int64_t ncell, const int64
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_near_f64(int n, BandDev b, const float4* __restrict__ A,
-                                                     const double* __restrict__ wpsi, const double* __restrict__ wpsn,
-                                                     CellsDev cells, float rc2, KParams kp,
-                                                     double* __restrict__ near) {
-  int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
+// Visits the near sources of target i (FP32 distance below r_c) in a fixed order: the
+// 27 neighbouring cells in lexicographic order, each cell's nodes in increasing index.
+template <typename F>
+__device__ __forceinline__ void for_near(int i, const float4* __restrict__ A, const CellsDev& cells, float rc2, F f) {
   const float4 ta = A[i];
-  const double xi = b.px[i], yi = b.py[i], zi = b.pz[i], nxi = b.nx[i], nyi = b.ny[i], nzi = b.nz[i];
   const int c = cells.cell_of[i];
   const int cz = c % cells.ncz, cy = (c / cells.ncz) % cells.ncy, cx = c / (cells.ncz * cells.ncy);
-  double s1 = 0.0, s2 = 0.0;
   for (int ax = max(cx - 1, 0); ax <= min(cx + 1, cells.ncx - 1); ++ax)
     for (int ay = max(cy - 1, 0); ay <= min(cy + 1, cells.ncy - 1); ++ay)
       for (int az = max(cz - 1, 0); az <= min(cz + 1, cells.ncz - 1); ++az) {
@@ -306,13 +320,69 @@ __global__ void __launch_bounds__(kBlock) k_near_f64(int n, BandDev b, const flo
         for (int64_t q = cells.start[cc]; q < cells.start[cc + 1]; ++q) {
           const int j = cells.nodes[q];
           const float4 sa = A[j];
-          if (!(r2_f32(ta.x, ta.y, ta.z, sa.x, sa.y, sa.z) < rc2)) continue;
-          pair_f64(xi, yi, zi, nxi, nyi, nzi, b.px[j], b.py[j], b.pz[j], b.nx[j], b.ny[j], b.nz[j], wpsi[j], wpsn[j],
-                   kp, s1, s2);
+          if (r2_f32(ta.x, ta.y, ta.z, sa.x, sa.y, sa.z) < rc2) f(j);
         }
       }
-  near[i] = s1;
-  near[n + i] = s2;
+}
+
+__global__ void __launch_bounds__(kBlock) k_near_count(int n, const float4* __restrict__ A, CellsDev cells, float rc2,
+                                                       int64_t* __restrict__ counts) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  int64_t c = 0;
+  for_near(i, A, cells, rc2, [&](int) { ++c; });
+  counts[i] = c;
+}
+
+// Near-field block matrix: for each near pair the FP64 coefficients of
+//   y1_i += c0 ψ_j + c1 ψn_j,  y2_i += c2 ψ_j + c3 ψn_j,  with s_j = h³ω_j/(4π)
+//   c0 = 4πK11 s_j, c1 = −4πK12 s_j, c2 = 4πK21 s_j, c3 = −4πK22 s_j.
+// The coefficients depend on geometry only, so they are built once per band.
+__global__ void __launch_bounds__(kBlock) k_near_fill(int n, BandDev b, const double* __restrict__ w, double scale,
+                                                      const float4* __restrict__ A, CellsDev cells, float rc2,
+                                                      KParams kp, const int64_t* __restrict__ row,
+                                                      int* __restrict__ col, double4* __restrict__ coef) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double xi = b.px[i], yi = b.py[i], zi = b.pz[i], nxi = b.nx[i], nyi = b.ny[i], nzi = b.nz[i];
+  int64_t q = row[i];
+  for_near(i, A, cells, rc2, [&](int j) {
+    double k[4];
+    kern4_f64(xi, yi, zi, nxi, nyi, nzi, b.px[j], b.py[j], b.pz[j], b.nx[j], b.ny[j], b.nz[j], kp, k);
+    const double sj = scale * w[j];
+    col[q] = j;
+    coef[q] = make_double4(k[0] * sj, -k[1] * sj, k[2] * sj, -k[3] * sj);
+    ++q;
+  });
+}
+
+constexpr int kRowLanes = 16;  // lanes cooperating on one CSR row
+
+// near = (near block matrix)·p, 16 lanes per row, fixed-order lane reduction.
+__global__ void __launch_bounds__(kBlock) k_near_spmv(int n, const int64_t* __restrict__ row,
+                                                      const int* __restrict__ col, const double4* __restrict__ coef,
+                                                      const double* __restrict__ p, double* __restrict__ near) {
+  const int i = (blockIdx.x * kBlock + threadIdx.x) / kRowLanes;
+  const int lane = threadIdx.x % kRowLanes;
+  double s1 = 0.0, s2 = 0.0;
+  if (i < n) {
+    const int64_t e = row[i + 1];
+    for (int64_t q = row[i] + lane; q < e; q += kRowLanes) {
+      const int j = col[q];
+      const double4 c = coef[q];
+      const double ps = p[j], pn = p[n + j];
+      s1 += c.x * ps + c.y * pn;
+      s2 += c.z * ps + c.w * pn;
+    }
+  }
+  for (int off = kRowLanes / 2; off > 0; off >>= 1) {
+    s1 += __shfl_down(s1, off, kRowLanes);
+    s2 += __shfl_down(s2, off, kRowLanes);
+  }
+  if (i < n && lane == 0) {
+    near[i] = s1;
+    near[n + i] = s2;
+  }
 }
 
 // Number of source chunks so that the launch has at least ~8 blocks per CU.
@@ -405,35 +475,54 @@ pb_status mixed_prepare(pb_ctx* ctx, const pb_band* band, const Derived& d) {
   PB_TRY(exclusive_scan_i64(ctx, start, ncell + 1, nullptr));
   k_cell_fill<<<nb, kBlock, 0, ctx->stream>>>(n, cell_of, start, cursor, nodes);
   k_cell_sort<<<(unsigned)((ncell + kBlock - 1) / kBlock), kBlock, 0, ctx->stream>>>(ncell, start, nodes);
-  return launch_ok(ctx, "cell list");
+  PB_TRY(launch_ok(ctx, "cell list"));
+
+  // FP32 coordinates (weights zero) for the near predicate, then the near-field block matrix
+  float4* A = (float4*)workspace(ctx, "mx_A", sizeof(float4) * n);
+  float4* B = (float4*)workspace(ctx, "mx_B", sizeof(float4) * n);
+  int64_t* row = (int64_t*)workspace(ctx, "mx_near_row", sizeof(int64_t) * (size_t)(n + 1));
+  if (!A || !B || !row) return PB_ENOMEM;
+  k_pack_f32<<<nb, kBlock, 0, ctx->stream>>>(n, band_dev(band), band->w, nullptr, 0.0, P.cx, P.cy, P.cz, A, B);
+  const CellsDev cells{start, nodes, cell_of, P.ncx, P.ncy, P.ncz};
+  PB_HIP(ctx, hipMemsetAsync(row + n, 0, sizeof(int64_t), ctx->stream));
+  k_near_count<<<nb, kBlock, 0, ctx->stream>>>(n, A, cells, P.rc2f, row);
+  PB_TRY(launch_ok(ctx, "near count"));
+  int64_t nnz = 0;
+  PB_TRY(exclusive_scan_i64(ctx, row, n + 1, &nnz));
+  P.nnz = nnz;
+  int* col = (int*)workspace(ctx, "mx_near_col", sizeof(int) * (size_t)std::max<int64_t>(nnz, 1));
+  double4* coef = (double4*)workspace(ctx, "mx_near_coef", sizeof(double4) * (size_t)std::max<int64_t>(nnz, 1));
+  if (!col || !coef) return PB_ENOMEM;
+  k_near_fill<<<nb, kBlock, 0, ctx->stream>>>(n, band_dev(band), band->w, d.h3 / (4.0 * kPi), A, cells, P.rc2f,
+                                              kparams(d), row, col, coef);
+  return launch_ok(ctx, "near fill");
 }
 
 pb_status matvec_mixed(pb_ctx* ctx, const pb_band* band, const Derived& d, const double* p, double* y) {
   const int n = (int)band->n;
-  auto& P = ctx->mixed;
-  if (P.band_key != band->px || P.n != n || P.rc != d.rc) PB_TRY(mixed_prepare(ctx, band, d));
+  const auto& P = ctx->mixed;
+  if (P.band_key != band->px || P.n != n || P.rc != d.rc)
+    return ctx->fail(PB_EINVAL, "mixed operator used before its geometry was prepared");
   int chunk = 0;
   const int S = choose_chunks(ctx, n, &chunk);
   float4* A = (float4*)workspace(ctx, "mx_A", sizeof(float4) * n);
   float4* B = (float4*)workspace(ctx, "mx_B", sizeof(float4) * n);
-  double* wpsi = (double*)workspace(ctx, "mv_wpsi", sizeof(double) * n);
-  double* wpsn = (double*)workspace(ctx, "mv_wpsn", sizeof(double) * n);
   double* partial = (double*)workspace(ctx, "mv_partial", sizeof(double) * 2 * (size_t)n * S);
   double* near = (double*)workspace(ctx, "mx_near", sizeof(double) * 2 * (size_t)n);
-  if (!A || !B || !wpsi || !wpsn || !partial || !near) return PB_ENOMEM;
+  if (!A || !B || !partial || !near) return PB_ENOMEM;
   const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
   k_pack_f32<<<nb, kBlock, 0, ctx->stream>>>(n, band_dev(band), band->w, p, d.h3 / (4.0 * kPi), P.cx, P.cy, P.cz, A,
-                                             B, wpsi, wpsn);
+                                             B);
   F32Params fp{(float)d.th1, (float)d.th2, (float)d.kappa, (float)(-d.kappa * 1.4426950408889634)};
   {
     Scope t(ctx, "p2p_f32");
     k_p2p_f32<<<dim3(nb, S), kBlock, 0, ctx->stream>>>(A, B, n, chunk, P.rc2f, fp, partial);
   }
-  CellsDev cells{(const int64_t*)ctx->bufs["mx_cell_start"].ptr, (const int*)ctx->bufs["mx_cell_nodes"].ptr,
-                 (const int*)ctx->bufs["mx_cell_of"].ptr, P.ncx, P.ncy, P.ncz};
   {
     Scope t(ctx, "near_f64");
-    k_near_f64<<<nb, kBlock, 0, ctx->stream>>>(n, band_dev(band), A, wpsi, wpsn, cells, P.rc2f, kparams(d), near);
+    k_near_spmv<<<(unsigned)(((int64_t)n * kRowLanes + kBlock - 1) / kBlock), kBlock, 0, ctx->stream>>>(
+        n, (const int64_t*)ctx->bufs["mx_near_row"].ptr, (const int*)ctx->bufs["mx_near_col"].ptr,
+        (const double4*)ctx->bufs["mx_near_coef"].ptr, p, near);
   }
   {
     Scope t(ctx, "reduce");
@@ -458,6 +547,7 @@ extern "C" pb_status pb_ibim_matvec(pb_ctx* ctx, const pb_band* band, const pb_p
     return ctx->fail(PB_EINVAL, "the mixed path needs a bounded regularization radius (guarded or Euclidean metric)");
   PB_HIP(ctx, hipSetDevice(ctx->device));
   Derived d = derive(*prm);
+  if (precision == PB_MIXED) PB_TRY(mixed_prepare(ctx, band, d));
   PB_TRY(precision == PB_FP64 ? matvec_fp64(ctx, band, d, p, y) : matvec_mixed(ctx, band, d, p, y));
   return sync(ctx, "pb_ibim_matvec");
 }

@@ -46,6 +46,7 @@ struct MixedPlan {
   float rc2f = 0;
   double cell = 0;
   int ncx = 0, ncy = 0, ncz = 0;
+  int64_t nnz = 0;  // near-field pairs
 };
 
 // Per-kernel-family event timing.

@@ -270,6 +270,7 @@ extern "C" pb_status pb_ibim_solve(pb_ctx* ctx, const pb_band* band, const doubl
   else if (opts.x0 == PB_X0_ZERO) k_zero<<<vb, kBlock, 0, ctx->stream>>>(M, p);
   PB_TRY(launch_ok(ctx, "x0"));
 
+  if (opts.precision == PB_MIXED) PB_TRY(mixed_prepare(ctx, band, d));
   int n64 = 0, nmx = 0;
   OpFn op64 = [&](const double* in, double* out) {
     ++n64;
