@@ -178,10 +178,69 @@ pb_status pb_ibim_solve(pb_ctx* ctx, const pb_band* band, const double* atoms, i
 pb_status pb_solvation_energy(pb_ctx* ctx, const pb_band* band, const double* atoms, int n_atoms,
                               const pb_params* prm, const double* p, pb_energy* out, double* psi_rxn);
 
+/* Batched solve statistics (host). */
+typedef struct {
+  double t_total_s;    /* wall time of the call, set-up included */
+  double t_p50_s;      /* median per-molecule time to solution, from the start of the solve */
+  double t_p99_s;      /* 99th percentile of the same */
+  double pairs;        /* pair-interactions evaluated over the whole batch */
+  int graph_replays;   /* replays of the captured Arnoldi-step graph */
+  int far_tile;        /* far-field sources per LDS tile chosen by the autotuner */
+  int far_tpl;         /* far-field targets per lane chosen by the autotuner */
+  int n_items;         /* work items of the persistent far-field launch */
+  int outer;           /* refinement steps */
+  int reserved;
+} pb_batch_stats;
+
+/* Solves n_mol independent molecules (section "Fast linear solvers" for each) in one batch,
+   mixed precision (opts->precision must be PB_MIXED): every operator application of the
+   batch is one persistent far-field launch over a largest-first list of equal-cost
+   (molecule, target block, source chunk) items plus one near-field/reduce launch; one
+   Arnoldi step of all molecules is a captured hipGraph replayed until every molecule has
+   converged. bands: host array of n_mol bands (device arrays inside). atoms: host array of
+   n_mol device pointers (n_atoms[m] × 5). p: host array of n_mol device pointers (2n_m
+   doubles each), input when opts->x0 == PB_X0_USER, output always. stats: host, n_mol
+   entries, may be NULL; bstats: host, may be NULL. PB_ENOCONV if any molecule misses the
+   tolerance (all results still written). */
+pb_status pb_ibim_solve_batched(pb_ctx* ctx, int n_mol, const pb_band* bands, const double* const* atoms,
+                                const int* n_atoms, const pb_params* prm, const pb_solve_opts* opts,
+                                double* const* p, pb_solve_stats* stats, pb_batch_stats* bstats);
+
+/* ---- Learned initial guess / right preconditioner (not part of the paper's method).
+   A point-convolution network over the band nodes (16 neighbour slots: the node and its 15
+   nearest band nodes by projection distance; widths 16 → 64 → 64 → 64 → 2; leaky ReLU),
+   BF16 weights and MFMA products with FP32 accumulation. Applied to a vector v it returns
+   M(v) = Λ⁻¹(v + s ⊙ O(v)), s = per-half RMS of v: the paper's diagonal solve plus a learned
+   correction (an untrained network is exactly Λ⁻¹). pb_ibim_solve uses it as x0 = M(g)
+   (PB_X0_LEARNED) and as a right preconditioner inside FGMRES (PB_PRECOND_LEARNED), with plain
+   GMRES as the fallback. */
+typedef struct pb_nn pb_nn;
+/* Network with He-uniform weights from a SplitMix64 stream of `seed`, last layer zero. */
+pb_status pb_nn_create(pb_ctx* ctx, uint64_t seed, pb_nn** out);
+void pb_nn_destroy(pb_nn* net);
+/* Number of FP32 parameters (per layer W[K][Cout] row-major, then b[Cout]). */
+int64_t pb_nn_param_count(void);
+/* Host copies of the FP32 master parameters and/or the last gradients (either may be NULL). */
+pb_status pb_nn_get_params(pb_ctx* ctx, const pb_nn* net, float* params_host, float* grads_host);
+pb_status pb_nn_set_params(pb_ctx* ctx, pb_nn* net, const float* params_host);
+/* Neighbour lists and geometry features of a band (needs band->phi); required before
+   pb_nn_apply / pb_nn_train_step on that band (the solve does it itself). */
+pb_status pb_nn_prepare(pb_ctx* ctx, const pb_band* band, const pb_params* prm);
+/* p = M(v); v, p: device, 2n. */
+pb_status pb_nn_apply(pb_ctx* ctx, const pb_nn* net, const pb_band* band, const pb_params* prm, const double* v,
+                      double* p);
+/* One Adam step (lr > 0; lr = 0 only computes gradients) on the pair (v, u = A⁻¹v): loss
+   Σ|O − T|²/Σ|T|² with T = (Λu − v)/s. v, u: device, 2n. loss: host, may be NULL. */
+pb_status pb_nn_train_step(pb_ctx* ctx, pb_nn* net, const pb_band* band, const pb_params* prm, const double* v,
+                           const double* u, float lr, double* loss);
+/* Host copies of the prepared neighbour lists (n × 16 int) and node features (n × 5 float:
+   φ/ε, n, H·ε); either may be NULL. */
+pb_status pb_nn_geometry(pb_ctx* ctx, const pb_band* band, int* nbr_host, float* feat_host);
+
 /* Device time (ms) and launch count of one kernel family since the last reset, measured
    with HIP events around each launch on the context stream when timing is enabled.
    name: "p2p_f32", "p2p_f64", "near_f64", "reduce", "gmres", "levelset", "band", "rhs",
-   "energy". */
+   "energy", "nn". */
 pb_status pb_set_timing(pb_ctx* ctx, int enable);
 pb_status pb_kernel_time(pb_ctx* ctx, const char* name, double* total_ms, int64_t* launches);
 

@@ -231,6 +231,10 @@ void pb_destroy(pb_ctx* ctx) {
     (void)hipEventDestroy(e.second);
   }
   for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
+  if (ctx->batch_stream) {
+    (void)hipStreamSynchronize(ctx->batch_stream);
+    (void)hipStreamDestroy(ctx->batch_stream);
+  }
   delete ctx;
 }
 

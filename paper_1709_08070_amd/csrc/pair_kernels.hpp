@@ -1,0 +1,451 @@
+// Device code shared by the single-molecule and batched operators: the per-pair kernels
+// of eq. IBIM-PBE with the regularization subsection, and the LDS-tiled source loops.
+//
+// With d = x_i* − y_j*, r = |d|, E = e^{−κr}, a = E(1+κr), b = E(3+3κr+κ²r²), the four
+// kernels times 4π are
+//   4πK11 = (d·n_j)(1 − θ1 a)/r³            4πK12 = (1 − E)/r
+//   4πK21 = (n_i·n_j)(1 − a)/r³ − (d·n_i)(d·n_j)(3 − b)/r⁵
+//   4πK22 = −(d·n_i)(1 − θ2 a)/r³
+// and pairs inside the tangent disc of radius τ take the disc averages (0, K̄12, 0, 0).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "pb_internal.hpp"
+
+namespace pb {
+
+struct KParams {
+  double th1, th2, kappa, tau2, four_tau2, k12bar4pi;
+  int metric;
+};
+
+inline KParams kparams(const Derived& d) {
+  return KParams{d.th1, d.th2, d.kappa, d.tau2, d.four_tau2, 4.0 * kPi * d.k12bar, d.metric};
+}
+
+// ---------------------------------------------------------------- FP64
+
+// The four kernels times 4π for one pair in FP64. The regularization predicate uses the
+// products and sums exactly as written (no contraction).
+__device__ __forceinline__ void kern4_f64(double xi, double yi, double zi, double nxi, double nyi, double nzi,
+                                          double xj, double yj, double zj, double nxj, double nyj, double nzj,
+                                          const KParams& kp, double k[4]) {
+  double dx = xi - xj, dy = yi - yj, dz = zi - zj;
+  double r2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+  double dnx = __dadd_rn(__dadd_rn(__dmul_rn(dx, nxi), __dmul_rn(dy, nyi)), __dmul_rn(dz, nzi));
+  double t2 = __dadd_rn(r2, -__dmul_rn(dnx, dnx));
+  bool reg;
+  if (kp.metric == PB_REG_EUCLIDEAN) reg = r2 < kp.tau2;
+  else if (kp.metric == PB_REG_TANGENT) reg = t2 < kp.tau2;
+  else reg = t2 < kp.tau2 && r2 < kp.four_tau2;
+  if (reg) {
+    k[0] = 0.0;
+    k[1] = kp.k12bar4pi;
+    k[2] = 0.0;
+    k[3] = 0.0;
+    return;
+  }
+  double dny = dx * nxj + dy * nyj + dz * nzj;
+  double nn = nxi * nxj + nyi * nyj + nzi * nzj;
+  // 1/r from the hardware reciprocal square root refined by two Newton steps
+  double rinv = __builtin_amdgcn_rsq(r2);
+  double e = fma(-r2 * rinv, rinv, 1.0);
+  rinv = fma(0.5 * rinv, e, rinv);
+  e = fma(-r2 * rinv, rinv, 1.0);
+  rinv = fma(0.5 * rinv, e, rinv);
+  double r = r2 * rinv;
+  double r3 = rinv * rinv * rinv;
+  double r5 = r3 * rinv * rinv;
+  double z = kp.kappa * r;
+  double E = exp(-z);
+  double a = E * (1.0 + z);
+  double b = E * (3.0 + 3.0 * z + z * z);
+  k[0] = dny * (1.0 - kp.th1 * a) * r3;
+  k[1] = (1.0 - E) * rinv;
+  k[2] = nn * (1.0 - a) * r3 - dnx * dny * (3.0 - b) * r5;
+  k[3] = -dnx * (1.0 - kp.th2 * a) * r3;
+}
+
+// s1 += 4πK11·wψ − 4πK12·wψn, s2 += 4πK21·wψ − 4πK22·wψn.
+__device__ __forceinline__ void pair_f64(double xi, double yi, double zi, double nxi, double nyi, double nzi,
+                                         double xj, double yj, double zj, double nxj, double nyj, double nzj,
+                                         double wpsi, double wpsn, const KParams& kp, double& s1, double& s2) {
+  double k[4];
+  kern4_f64(xi, yi, zi, nxi, nyi, nzi, xj, yj, zj, nxj, nyj, nzj, kp, k);
+  s1 += k[0] * wpsi - k[1] * wpsn;
+  s2 += k[2] * wpsi - k[3] * wpsn;
+}
+
+// ---------------------------------------------------------------- FP32
+
+// FP32 records: A = (σx, σy, σz, σ·h³ωψ/4π), B = (n_x, n_y, n_z, h³ωψn/4π), with the
+// coordinates centred on the band and scaled by σ = κ (σ = 1 when κ = 0). In scaled
+// coordinates r' = κr = z, so e^{−κr} = exp2(−log2(e)·r') needs no extra product, and the
+// sums come out as y1 = σ·S1, y2 = σ²·S2 (the scale is applied in FP64 afterwards).
+struct F32Params {
+  float th1, th2, mlog2e, rc2;  // rc2: squared near-field radius in scaled units
+};
+
+// Squared distance in FP32 with a fixed operation sequence; every kernel that separates
+// near from far pairs calls it on the same FP32 records.
+__device__ __forceinline__ float r2_f32(float xi, float yi, float zi, float xj, float yj, float zj) {
+  float dx = xi - xj, dy = yi - yj, dz = zi - zj;
+  return __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, __fmul_rn(dx, dx)));
+}
+
+// One far pair in FP32. Near pairs (r'² < rc2, which includes the self pair and every
+// regularized pair) contribute exactly zero: 1/r' is replaced by 0 and every term carries a
+// factor of it.
+//   K21·r'³ = f1 (n_i·n_j − 3u) + u E z²,  u = (d·n_i)(d·n_j)/r'², f1 = 1 − E(1+z),
+// which is (n_i·n_j) f1 − u (3 − b) rewritten with 3 − b = 3 f1 − E z².
+template <bool kScreened>
+__device__ __forceinline__ void pair_f32(const float4& ta, const float4& tb, const float4& sa, const float4& sb,
+                                         const F32Params& fp, float& a1, float& a2) {
+  const float dx = ta.x - sa.x, dy = ta.y - sa.y, dz = ta.z - sa.z;
+  const float r2 = r2_f32(ta.x, ta.y, ta.z, sa.x, sa.y, sa.z);
+  const bool near = r2 < fp.rc2;
+  const float rinv = near ? 0.f : __builtin_amdgcn_rsqf(r2);
+  float E = 1.f, Ez = 0.f, z = 0.f;
+  if (kScreened) {
+    z = r2 * rinv;
+    E = __builtin_amdgcn_exp2f(fp.mlog2e * z);
+    Ez = E * z;
+  }
+  const float a = E + Ez;
+  const float f1 = 1.f - a;
+  const float f0 = 1.f - E;
+  const float c1 = __fmaf_rn(-fp.th1, a, 1.f);
+  const float c2 = __fmaf_rn(-fp.th2, a, 1.f);
+  const float dnx = __fmaf_rn(dz, tb.z, __fmaf_rn(dy, tb.y, dx * tb.x));
+  const float dny = __fmaf_rn(dz, sb.z, __fmaf_rn(dy, sb.y, dx * sb.x));
+  const float nn = __fmaf_rn(tb.z, sb.z, __fmaf_rn(tb.y, sb.y, tb.x * sb.x));
+  const float ri2 = rinv * rinv;
+  const float r3 = ri2 * rinv;
+  const float u = dnx * dny * ri2;
+  float v = __fmaf_rn(-3.f, u, nn) * f1;
+  if (kScreened) v = __fmaf_rn(u, Ez * z, v);
+  a1 = __fmaf_rn(dny * c1 * r3, sa.w, a1);
+  a1 = __fmaf_rn(-f0 * rinv, sb.w, a1);
+  a2 = __fmaf_rn(__fmaf_rn(v, sa.w, dnx * c2 * sb.w), r3, a2);
+}
+
+// Targets [t0, t0 + kBlk·TPL) against sources [j0, j1) of the same record arrays; per-tile
+// FP32 partial sums flushed into FP64. out1/out2 receive σ·S1 and σ²·S2 for each live target
+// (index relative to t0). Every thread of the block must call it (it synchronizes).
+template <int kBlk, int TILE, int TPL, bool kScreened>
+__device__ __forceinline__ void far_tile_loop(const float4* __restrict__ A, const float4* __restrict__ B, int t0,
+                                              int t_end, int j0, int j1, const F32Params& fp, double sig1, double sig2,
+                                              float4* sA, float4* sB, double* __restrict__ out1,
+                                              double* __restrict__ out2) {
+  float4 ta[TPL], tb[TPL];
+#pragma unroll
+  for (int t = 0; t < TPL; ++t) {
+    const int i = t0 + t * kBlk + (int)threadIdx.x;
+    ta[t] = i < t_end ? A[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    tb[t] = i < t_end ? B[i] : make_float4(0.f, 0.f, 1.f, 0.f);
+  }
+  double acc1[TPL], acc2[TPL];
+#pragma unroll
+  for (int t = 0; t < TPL; ++t) acc1[t] = acc2[t] = 0.0;
+  for (int base = j0; base < j1; base += TILE) {
+    for (int q = threadIdx.x; q < TILE; q += kBlk) {
+      const int j = base + q;
+      if (j < j1) {
+        sA[q] = A[j];
+        sB[q] = B[j];
+      } else {  // padding: zero weights, every value they meet is finite
+        sA[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+        sB[q] = make_float4(0.f, 0.f, 1.f, 0.f);
+      }
+    }
+    __syncthreads();
+    float a1[TPL], a2[TPL];
+#pragma unroll
+    for (int t = 0; t < TPL; ++t) a1[t] = a2[t] = 0.f;
+#pragma unroll 4
+    for (int q = 0; q < TILE; ++q) {
+      const float4 sa = sA[q], sb = sB[q];
+#pragma unroll
+      for (int t = 0; t < TPL; ++t) pair_f32<kScreened>(ta[t], tb[t], sa, sb, fp, a1[t], a2[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < TPL; ++t) {
+      acc1[t] += (double)a1[t];
+      acc2[t] += (double)a2[t];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int t = 0; t < TPL; ++t) {
+    const int i = t0 + t * kBlk + (int)threadIdx.x;
+    if (i < t_end) {
+      out1[i - t0] = sig1 * acc1[t];
+      out2[i - t0] = sig2 * acc2[t];
+    }
+  }
+}
+
+
+// ---------------------------------------------------------------- kernels
+
+constexpr int kBlock = 256;
+
+struct BandDev {
+  const double *px, *py, *pz, *nx, *ny, *nz;
+};
+
+inline BandDev band_dev(const pb_band* b) { return BandDev{b->px, b->py, b->pz, b->nx, b->ny, b->nz}; }
+
+// Source weights h³ω_j ψ_j/(4π), h³ω_j ψn_j/(4π) in FP64.
+static __global__ void __attribute__((unused)) __launch_bounds__(kBlock) k_weights_f64(int n, const double* __restrict__ w,
+                                                               const double* __restrict__ p, double scale,
+                                                               double* __restrict__ wpsi, double* __restrict__ wpsn) {
+  int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= n) return;
+  double s = scale * w[j];
+  wpsi[j] = s * p[j];
+  wpsn[j] = s * p[n + j];
+}
+
+// FP64 targets [t0, t0 + kBlk) against sources [j0, j1) of the band arrays b with source
+// weights wpsi/wpsn (h³ωψ/4π, h³ωψn/4π); out1/out2 receive the sums for each live target
+// (index relative to t0). Every thread of the block must call it (it synchronizes).
+template <int kBlk>
+__device__ __forceinline__ void far64_tile_loop(const BandDev& b, const double* __restrict__ wpsi,
+                                                const double* __restrict__ wpsn, int t0, int t_end, int j0, int j1,
+                                                const KParams& kp, double* smem, double* __restrict__ out1,
+                                                double* __restrict__ out2) {
+  double *sx = smem, *sy = sx + kBlk, *sz = sy + kBlk, *snx = sz + kBlk, *sny = snx + kBlk, *snz = sny + kBlk,
+         *sw1 = snz + kBlk, *sw2 = sw1 + kBlk;
+  const int i = t0 + (int)threadIdx.x;
+  const bool live = i < t_end;
+  double xi = 0, yi = 0, zi = 0, nxi = 0, nyi = 0, nzi = 1;
+  if (live) {
+    xi = b.px[i]; yi = b.py[i]; zi = b.pz[i];
+    nxi = b.nx[i]; nyi = b.ny[i]; nzi = b.nz[i];
+  }
+  double s1 = 0.0, s2 = 0.0;
+  for (int base = j0; base < j1; base += kBlk) {
+    const int j = base + (int)threadIdx.x;
+    if (j < j1) {
+      sx[threadIdx.x] = b.px[j]; sy[threadIdx.x] = b.py[j]; sz[threadIdx.x] = b.pz[j];
+      snx[threadIdx.x] = b.nx[j]; sny[threadIdx.x] = b.ny[j]; snz[threadIdx.x] = b.nz[j];
+      sw1[threadIdx.x] = wpsi[j]; sw2[threadIdx.x] = wpsn[j];
+    }
+    __syncthreads();
+    const int m = min(kBlk, j1 - base);
+    if (live)
+      for (int q = 0; q < m; ++q)
+        pair_f64(xi, yi, zi, nxi, nyi, nzi, sx[q], sy[q], sz[q], snx[q], sny[q], snz[q], sw1[q], sw2[q], kp, s1, s2);
+    __syncthreads();
+  }
+  if (live) {
+    out1[i - t0] = s1;
+    out2[i - t0] = s2;
+  }
+}
+
+// FP64 operator, one target per lane; block (x: target block, y: source chunk).
+static __global__ void __attribute__((unused)) __launch_bounds__(kBlock) k_p2p_f64(BandDev b, const double* __restrict__ wpsi,
+                                                           const double* __restrict__ wpsn, int n, int chunk,
+                                                           double* __restrict__ partial, KParams kp) {
+  __shared__ double smem[8 * kBlock];
+  const int t0 = blockIdx.x * kBlock;
+  const int j0 = blockIdx.y * chunk;
+  const int j1 = min(n, j0 + chunk);
+  double* out = partial + (size_t)blockIdx.y * 2 * n;
+  far64_tile_loop<kBlock>(b, wpsi, wpsn, t0, n, j0, j1, kp, smem, out + t0, out + n + t0);
+}
+
+// y = Λp + Σ_chunks partial (+ near), in a fixed order.
+static __global__ void __attribute__((unused)) __launch_bounds__(kBlock) k_reduce(int n, int n_chunks, const double* __restrict__ partial,
+                                                          const double* __restrict__ near,
+                                                          const double* __restrict__ p, double lam1, double lam2,
+                                                          double* __restrict__ y) {
+  int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= 2 * n) return;
+  double s = 0.0;
+  for (int c = 0; c < n_chunks; ++c) s += partial[(size_t)c * 2 * n + e];
+  if (near) s += near[e];
+  y[e] = (e < n ? lam1 : lam2) * p[e] + s;
+}
+
+// FP32 records (see F32Params): A = (σ(x−c), σ·s_j·ψ_j), B = (n, s_j·ψn_j), s_j = h³ω_j/(4π).
+// With p == nullptr only the geometry is written (weights zero).
+static __global__ void __attribute__((unused)) __launch_bounds__(kBlock) k_pack_f32(int n, BandDev b, const double* __restrict__ w,
+                                                            const double* __restrict__ p, double scale, double cx,
+                                                            double cy, double cz, double sigma,
+                                                            float4* __restrict__ A, float4* __restrict__ B) {
+  int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= n) return;
+  double s = scale * w[j];
+  double w1 = p ? s * p[j] : 0.0, w2 = p ? s * p[n + j] : 0.0;
+  A[j] = make_float4((float)(sigma * (b.px[j] - cx)), (float)(sigma * (b.py[j] - cy)), (float)(sigma * (b.pz[j] - cz)),
+                     (float)(sigma * w1));
+  B[j] = make_float4((float)b.nx[j], (float)b.ny[j], (float)b.nz[j], (float)w2);
+}
+
+// FP32 far field of one band: block (x: kBlock·TPL targets, y: source chunk).
+template <int TILE, int TPL, bool kScreened>
+static __global__ void __attribute__((unused)) __launch_bounds__(kBlock) k_p2p_f32(const float4* __restrict__ A, const float4* __restrict__ B,
+                                                           int n, int chunk, F32Params fp, double sig1, double sig2,
+                                                           double* __restrict__ partial) {
+  __shared__ float4 sA[TILE], sB[TILE];
+  const int t0 = blockIdx.x * kBlock * TPL;
+  const int j0 = blockIdx.y * chunk;
+  const int j1 = min(n, j0 + chunk);
+  double* out = partial + (size_t)blockIdx.y * 2 * n;
+  far_tile_loop<kBlock, TILE, TPL, kScreened>(A, B, t0, n, j0, j1, fp, sig1, sig2, sA, sB, out + t0, out + n + t0);
+}
+
+// ----------------------------------------------------------------- near field (cell list)
+
+struct CellsDev {
+  const int64_t* start;  // ncell + 1
+  const int* nodes;      // n, sorted within each cell
+  const int* cell_of;    // n
+  int ncx, ncy, ncz;
+};
+
+static __global__ void __attribute__((unused)) __launch_bounds__(kBlock) k_bbox(int n, BandDev b, double* __restrict__ out /*6 per block*/) {
+  __shared__ double s[6][kBlock];
+  double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+  for (int j = blockIdx.x * kBlock + threadIdx.x; j < n; j += gridDim.x * kBlock) {
+    v[0] = fmin(v[0], b.px[j]); v[1] = fmin(v[1], b.py[j]); v[2] = fmin(v[2], b.pz[j]);
+    v[3] = fmax(v[3], b.px[j]); v[4] = fmax(v[4], b.py[j]); v[5] = fmax(v[5], b.pz[j]);
+  }
+  for (int q = 0; q < 6; ++q) s[q][threadIdx.x] = v[q];
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off)
+      for (int q = 0; q < 6; ++q)
+        s[q][threadIdx.x] = q < 3 ? fmin(s[q][threadIdx.x], s[q][threadIdx.x + off])
+                                  : fmax(s[q][threadIdx.x], s[q][threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 6; ++q) out[6 * blockIdx.x + q] = s[q][0];
+}
+
+static __global__ void __attribute__((unused)) __launch_bounds__(kBlock) k_cell_count(int n, BandDev b, double lx, double ly, double lz,
+                                                       double inv_cell, int ncx, int ncy, int ncz,
+                                                       int* __restrict__ cell_of, int64_t* __restrict__ counts) {
+  int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= n) return;
+  int cx = min(ncx - 1, max(0, (int)((b.px[j] - lx) * inv_cell)));
+  int cy = min(ncy - 1, max(0, (int)((b.py[j] - ly) * inv_cell)));
+  int cz = min(ncz - 1, max(0, (int)((b.pz[j] - lz) * inv_cell)));
+  int c = (cx * ncy + cy) * ncz + cz;
+  cell_of[j] = c;
+  atomicAdd((unsigned long long*)&counts[c], 1ull);
+}
+
+static __global__ void __attribute__((unused)) __launch_bounds__(kBlock) k_cell_fill(int n, const int* __restrict__ cell_of,
+                                                      const int64_t* __restrict__ start, int* __restrict__ cursor,
+                                                      int* __restrict__ nodes) {
+  int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= n) return;
+  int c = cell_of[j];
+  int slot = atomicAdd(&cursor[c], 1);
+  nodes[start[c] + slot] = j;
+}
+
+// Insertion sort of each cell's node list, so the near-field sums run in a fixed order.
+static __global__ void __attribute__((unused)) __launch_bounds__(kBlock) k_cell_sort(int64_t ncell, const int64_t* __restrict__ start,
+                                                      int* __restrict__ nodes) {
+  int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (c >= ncell) return;
+  int64_t s = start[c], e = start[c + 1];
+  for (int64_t q = s + 1; q < e; ++q) {
+    int v = nodes[q];
+    int64_t t = q - 1;
+    while (t >= s && nodes[t] > v) {
+      nodes[t + 1] = nodes[t];
+      --t;
+    }
+    nodes[t + 1] = v;
+  }
+}
+
+// Visits the near sources of target i (FP32 distance below r_c) in a fixed order: the
+// 27 neighbouring cells in lexicographic order, each cell's nodes in increasing index.
+template <typename F>
+__device__ __forceinline__ void for_near(int i, const float4* __restrict__ A, const CellsDev& cells, float rc2, F f) {
+  const float4 ta = A[i];
+  const int c = cells.cell_of[i];
+  const int cz = c % cells.ncz, cy = (c / cells.ncz) % cells.ncy, cx = c / (cells.ncz * cells.ncy);
+  for (int ax = max(cx - 1, 0); ax <= min(cx + 1, cells.ncx - 1); ++ax)
+    for (int ay = max(cy - 1, 0); ay <= min(cy + 1, cells.ncy - 1); ++ay)
+      for (int az = max(cz - 1, 0); az <= min(cz + 1, cells.ncz - 1); ++az) {
+        const int cc = (ax * cells.ncy + ay) * cells.ncz + az;
+        for (int64_t q = cells.start[cc]; q < cells.start[cc + 1]; ++q) {
+          const int j = cells.nodes[q];
+          const float4 sa = A[j];
+          if (r2_f32(ta.x, ta.y, ta.z, sa.x, sa.y, sa.z) < rc2) f(j);
+        }
+      }
+}
+
+static __global__ void __attribute__((unused)) __launch_bounds__(kBlock) k_near_count(int n, const float4* __restrict__ A, CellsDev cells, float rc2,
+                                                       int64_t* __restrict__ counts) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  int64_t c = 0;
+  for_near(i, A, cells, rc2, [&](int) { ++c; });
+  counts[i] = c;
+}
+
+// Near-field block matrix: for each near pair the FP64 coefficients of
+//   y1_i += c0 ψ_j + c1 ψn_j,  y2_i += c2 ψ_j + c3 ψn_j,  with s_j = h³ω_j/(4π)
+//   c0 = 4πK11 s_j, c1 = −4πK12 s_j, c2 = 4πK21 s_j, c3 = −4πK22 s_j.
+// The coefficients depend on geometry only, so they are built once per band.
+static __global__ void __attribute__((unused)) __launch_bounds__(kBlock) k_near_fill(int n, BandDev b, const double* __restrict__ w, double scale,
+                                                      const float4* __restrict__ A, CellsDev cells, float rc2,
+                                                      KParams kp, const int64_t* __restrict__ row,
+                                                      int* __restrict__ col, double4* __restrict__ coef) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double xi = b.px[i], yi = b.py[i], zi = b.pz[i], nxi = b.nx[i], nyi = b.ny[i], nzi = b.nz[i];
+  int64_t q = row[i];
+  for_near(i, A, cells, rc2, [&](int j) {
+    double k[4];
+    kern4_f64(xi, yi, zi, nxi, nyi, nzi, b.px[j], b.py[j], b.pz[j], b.nx[j], b.ny[j], b.nz[j], kp, k);
+    const double sj = scale * w[j];
+    col[q] = j;
+    coef[q] = make_double4(k[0] * sj, -k[1] * sj, k[2] * sj, -k[3] * sj);
+    ++q;
+  });
+}
+
+constexpr int kRowLanes = 16;  // lanes cooperating on one CSR row
+
+// near = (near block matrix)·p, 16 lanes per row, fixed-order lane reduction.
+static __global__ void __attribute__((unused)) __launch_bounds__(kBlock) k_near_spmv(int n, const int64_t* __restrict__ row,
+                                                      const int* __restrict__ col, const double4* __restrict__ coef,
+                                                      const double* __restrict__ p, double* __restrict__ near) {
+  const int i = (blockIdx.x * kBlock + threadIdx.x) / kRowLanes;
+  const int lane = threadIdx.x % kRowLanes;
+  double s1 = 0.0, s2 = 0.0;
+  if (i < n) {
+    const int64_t e = row[i + 1];
+    for (int64_t q = row[i] + lane; q < e; q += kRowLanes) {
+      const int j = col[q];
+      const double4 c = coef[q];
+      const double ps = p[j], pn = p[n + j];
+      s1 += c.x * ps + c.y * pn;
+      s2 += c.z * ps + c.w * pn;
+    }
+  }
+  for (int off = kRowLanes / 2; off > 0; off >>= 1) {
+    s1 += __shfl_down(s1, off, kRowLanes);
+    s2 += __shfl_down(s2, off, kRowLanes);
+  }
+  if (i < n && lane == 0) {
+    near[i] = s1;
+    near[n + i] = s2;
+  }
+}
+
+
+}  // namespace pb

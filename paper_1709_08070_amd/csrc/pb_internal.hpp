@@ -41,12 +41,19 @@ struct DevBuf {
 struct MixedPlan {
   const void* band_key = nullptr;
   int64_t n = 0;
-  double cx = 0, cy = 0, cz = 0;
-  double rc = 0;
-  float rc2f = 0;
+  double cx = 0, cy = 0, cz = 0;  // centre of the FP32 coordinates
+  double sigma = 1;               // FP32 coordinates are scaled by σ (= κ when κ > 0)
+  double rc = 0;                  // near-field radius (unscaled)
+  float rc2f = 0;                 // (σ r_c)² in FP32
   double cell = 0;
   int ncx = 0, ncy = 0, ncz = 0;
-  int64_t nnz = 0;  // near-field pairs
+  int64_t nnz = 0;                // near-field pairs
+  float4* A = nullptr;            // FP32 records (x, ψ weight), (n, ψn weight)
+  float4* B = nullptr;
+  int64_t* row = nullptr;         // near-field CSR
+  int* col = nullptr;
+  double4* coef = nullptr;
+  int far_cfg = 0;                // far-field tile shape chosen by the autotuner
 };
 
 // Per-kernel-family event timing.
@@ -69,6 +76,11 @@ struct pb_ctx {
   std::vector<hipEvent_t> event_pool;
   int n_cu = 256;
   pb::MixedPlan mixed;
+  std::map<int, int> far_cfg;          // autotuned far-field tile shape per band size
+  std::map<int64_t, int> batch_cfg;    // the same for batches, per (nodes, molecules)
+  hipStream_t batch_stream = nullptr;  // capture stream of the batched solve
+  const void* nn_key = nullptr;        // band prepared for the learned preconditioner
+  int64_t nn_n = 0;
   // status of the last allocation/launch
   pb_status fail(pb_status s, const char* fmt, ...);
 };
@@ -100,6 +112,13 @@ pb_status exclusive_scan_i64(pb_ctx* ctx, int64_t* data, int64_t n, int64_t* tot
 // Operator internals used by the solver.
 pb_status matvec_fp64(pb_ctx* ctx, const pb_band* band, const Derived& d, const double* p, double* y);
 pb_status mixed_prepare(pb_ctx* ctx, const pb_band* band, const Derived& d);
+pb_status near_build(pb_ctx* ctx, const pb_band* band, const Derived& d, const char* pfx, MixedPlan& P,
+                     bool cells_only = false);
+struct F32Params;
+F32Params f32params(const Derived& d, double sigma);
+// learned preconditioner (nn.hip)
+pb_status nn_prepare(pb_ctx* ctx, const pb_band* band, const Derived& d);
+pb_status nn_apply(pb_ctx* ctx, const pb_nn* net, const pb_band* band, const Derived& d, const double* v, double* p);
 pb_status matvec_mixed(pb_ctx* ctx, const pb_band* band, const Derived& d, const double* p, double* y);
 pb_status rhs(pb_ctx* ctx, const pb_band* band, const double* atoms, int n_atoms, const Derived& d, double* g);
 

@@ -132,14 +132,17 @@ pb_status norm2(pb_ctx* ctx, Krylov& K, const double* v, double* out) {
 
 // Restarted GMRES(m) for A x = b from the given x until ‖b − Ax‖ ≤ tol_abs (estimate, then
 // confirmed with the operator at each restart) or max_iter operator applications.
-pb_status gmres(pb_ctx* ctx, Krylov& K, const OpFn& op, const double* b, double* x, double tol_abs, int max_iter,
-                int* iters, double* res_out) {
+// With prec (flexible GMRES, right preconditioning): z_k = prec(v_k), w = A z_k, and the
+// update is x += Z y; the preconditioner may change from step to step (it may be nonlinear).
+pb_status gmres(pb_ctx* ctx, Krylov& K, const OpFn& op, const OpFn* prec, const double* b, double* x, double tol_abs,
+                int max_iter, int* iters, double* res_out) {
   const int64_t M = K.M;
   const int m = K.m;
   double* V = (double*)workspace(ctx, "kr_V", sizeof(double) * (size_t)M * (m + 1));
+  double* Z = prec ? (double*)workspace(ctx, "kr_Z", sizeof(double) * (size_t)M * m) : nullptr;
   double* r = (double*)workspace(ctx, "kr_r", sizeof(double) * (size_t)M);
   double* ydev = (double*)workspace(ctx, "kr_y", sizeof(double) * (size_t)(m + 1));
-  if (!V || !r || !ydev) return PB_ENOMEM;
+  if (!V || !r || !ydev || (prec && !Z)) return PB_ENOMEM;
   const unsigned vb = vec_blocks(M);
   std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), s(m + 1), y(m), col(2 * (m + 1) + 1);
   PB_TRY(op(x, r));
@@ -158,7 +161,12 @@ pb_status gmres(pb_ctx* ctx, Krylov& K, const OpFn& op, const double* b, double*
     int k = 0;
     for (; k < m && it < max_iter; ++k) {
       double* w = V + (size_t)(k + 1) * M;
-      PB_TRY(op(V + (size_t)k * M, w));
+      if (prec) {
+        PB_TRY((*prec)(V + (size_t)k * M, Z + (size_t)k * M));
+        PB_TRY(op(Z + (size_t)k * M, w));
+      } else {
+        PB_TRY(op(V + (size_t)k * M, w));
+      }
       ++it;
       {
         Scope t(ctx, "gmres");
@@ -205,7 +213,7 @@ pb_status gmres(pb_ctx* ctx, Krylov& K, const OpFn& op, const double* b, double*
       y[i] = acc / H[(size_t)i * m + i];
     }
     PB_HIP(ctx, hipMemcpyAsync(ydev, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, ctx->stream));
-    k_axpy_multi<<<vb, kBlock, 0, ctx->stream>>>(M, V, M, k, ydev, 1.0, x);
+    k_axpy_multi<<<vb, kBlock, 0, ctx->stream>>>(M, prec ? Z : V, M, k, ydev, 1.0, x);
     PB_TRY(launch_ok(ctx, "update"));
     PB_TRY(op(x, r));
     k_residual<<<vb, kBlock, 0, ctx->stream>>>(M, b, r);
@@ -236,9 +244,13 @@ extern "C" pb_status pb_ibim_solve(pb_ctx* ctx, const pb_band* band, const doubl
   if (opts.precision != PB_FP64 && opts.precision != PB_MIXED) return ctx->fail(PB_EINVAL, "unknown precision");
   if (opts.precision == PB_MIXED && prm->reg_metric == PB_REG_TANGENT)
     return ctx->fail(PB_EINVAL, "the mixed path needs a bounded regularization radius");
-  if (opts.x0 < PB_X0_ZERO || opts.x0 > PB_X0_USER)
-    return ctx->fail(PB_EINVAL, "x0 mode %d not available in this call", opts.x0);
-  if (opts.precond != PB_PRECOND_NONE) return ctx->fail(PB_EINVAL, "preconditioner not available in this call");
+  if (opts.x0 < PB_X0_ZERO || opts.x0 > PB_X0_LEARNED) return ctx->fail(PB_EINVAL, "unknown x0 mode %d", opts.x0);
+  if (opts.precond != PB_PRECOND_NONE && opts.precond != PB_PRECOND_LEARNED)
+    return ctx->fail(PB_EINVAL, "unknown preconditioner %d", opts.precond);
+  const bool learned = opts.x0 == PB_X0_LEARNED || opts.precond == PB_PRECOND_LEARNED;
+  if (learned && !opts.nn) return ctx->fail(PB_EINVAL, "the learned path needs opts->nn");
+  if (learned && !band->phi) return ctx->fail(PB_EINVAL, "the learned path needs band->phi");
+  const pb_nn* net = (const pb_nn*)opts.nn;
   PB_HIP(ctx, hipSetDevice(ctx->device));
   PB_TRY(sync(ctx, "pb_ibim_solve"));
   auto matvec_ms = [&]() {
@@ -266,12 +278,14 @@ extern "C" pb_status pb_ibim_solve(pb_ctx* ctx, const pb_band* band, const doubl
   PB_TRY(norm2(ctx, K, g, &gnorm));
   if (!std::isfinite(gnorm)) return ctx->fail(PB_EINVAL, "non-finite right-hand side");
   if (gnorm == 0.0) gnorm = 1.0;
+  if (learned) PB_TRY(nn_prepare(ctx, band, d));
   if (opts.x0 == PB_X0_DIAG) k_diag_solve<<<vb, kBlock, 0, ctx->stream>>>(n, g, d.lam1, d.lam2, p);
   else if (opts.x0 == PB_X0_ZERO) k_zero<<<vb, kBlock, 0, ctx->stream>>>(M, p);
+  else if (opts.x0 == PB_X0_LEARNED) PB_TRY(nn_apply(ctx, net, band, d, g, p));
   PB_TRY(launch_ok(ctx, "x0"));
 
   if (opts.precision == PB_MIXED) PB_TRY(mixed_prepare(ctx, band, d));
-  int n64 = 0, nmx = 0;
+  int n64 = 0, nmx = 0, nnn = 0;
   OpFn op64 = [&](const double* in, double* out) {
     ++n64;
     return matvec_fp64(ctx, band, d, in, out);
@@ -280,37 +294,59 @@ extern "C" pb_status pb_ibim_solve(pb_ctx* ctx, const pb_band* band, const doubl
     ++nmx;
     return matvec_mixed(ctx, band, d, in, out);
   };
+  OpFn opnn = [&](const double* in, double* out) {
+    ++nnn;
+    return nn_apply(ctx, net, band, d, in, out);
+  };
   int iters = 0, outer = 0;
   double relres = 0.0;
-  if (opts.precision == PB_FP64) {
-    double res = 0.0;
-    PB_TRY(gmres(ctx, K, op64, g, p, opts.tol * gnorm, opts.max_iter, &iters, &res));
-    relres = res / gnorm;
-    outer = 1;
-  } else {
+  // one solve from the current p; prec = learned right preconditioner or none
+  auto run = [&](const OpFn* prec, int iter_budget) -> pb_status {
+    if (opts.precision == PB_FP64) {
+      double res = 0.0;
+      int it = 0;
+      PB_TRY(gmres(ctx, K, op64, prec, g, p, opts.tol * gnorm, iter_budget, &it, &res));
+      iters += it;
+      relres = res / gnorm;
+      outer += 1;
+      return PB_OK;
+    }
+    int used = 0, steps = 0;
     for (;;) {
       PB_TRY(op64(p, r));
       k_residual<<<vb, kBlock, 0, ctx->stream>>>(M, g, r);
       double rn = 0.0;
       PB_TRY(norm2(ctx, K, r, &rn));
       relres = rn / gnorm;
-      if (!(relres > opts.tol) || outer >= opts.max_outer || iters >= opts.max_iter) break;
+      if (!(relres > opts.tol) || steps >= opts.max_outer || used >= iter_budget) break;
       k_zero<<<vb, kBlock, 0, ctx->stream>>>(M, dx);
       int it = 0;
       double res = 0.0;
-      PB_TRY(gmres(ctx, K, opmx, r, dx, 0.5 * opts.tol * gnorm, opts.max_iter - iters, &it, &res));
-      iters += it;
+      PB_TRY(gmres(ctx, K, opmx, prec, r, dx, 0.5 * opts.tol * gnorm, iter_budget - used, &it, &res));
+      used += it;
       k_add<<<vb, kBlock, 0, ctx->stream>>>(M, dx, p);
       PB_TRY(launch_ok(ctx, "refine"));
-      ++outer;
+      ++steps;
     }
+    iters += used;
+    outer += steps;
+    return PB_OK;
+  };
+  bool fallback = false;
+  PB_TRY(run(opts.precond == PB_PRECOND_LEARNED ? &opnn : nullptr, opts.max_iter));
+  if (opts.precond == PB_PRECOND_LEARNED && (!std::isfinite(relres) || relres > opts.tol)) {
+    // plain GMRES judges the learned path: restart without the network from the last
+    // iterate (or from Λ⁻¹g if that iterate is not finite)
+    fallback = true;
+    if (!std::isfinite(relres)) k_diag_solve<<<vb, kBlock, 0, ctx->stream>>>(n, g, d.lam1, d.lam2, p);
+    PB_TRY(run(nullptr, opts.max_iter));
   }
   PB_TRY(sync(ctx, "pb_ibim_solve"));
   if (stats) {
     stats->iters = iters;
     stats->outer = outer;
     stats->converged = relres <= opts.tol;
-    stats->fallback_used = 0;
+    stats->fallback_used = fallback;
     stats->matvecs_fp64 = n64;
     stats->matvecs_mixed = nmx;
     stats->true_relres = relres;

@@ -1,0 +1,81 @@
+"""Training driver of the learned initial guess / right preconditioner.
+
+Orchestration only: molecules come from synth, every level set, band, solve, operator
+application, forward and backward pass and Adam step runs in the library's HIP kernels
+through the C-ABI. A training example is a pair (v, u = A⁻¹v) on one band:
+  * (g, p*) — the right-hand side of a molecule and its solution (mixed solve to 1e-8);
+  * (A·e, e) — a smooth random field e on the band and its image under the operator
+    (one mixed operator application), so the network also sees residual-like inputs.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+import torch
+
+from . import pb, synth
+
+
+def smooth_field(band: pb.Band, rng: np.random.Generator, n_bumps: int = 8) -> torch.Tensor:
+    """Sum of Gaussian bumps of random sign over the band's projections, for ψ and for ψ_n."""
+    x = torch.stack([band.px[: band.n], band.py[: band.n], band.pz[: band.n]], 1)
+    out = []
+    for scale in (1.0, 0.02):
+        f = torch.zeros(band.n, dtype=torch.float64, device=x.device)
+        idx = rng.integers(0, band.n, n_bumps)
+        for i in idx:
+            c = x[int(i)]
+            w = float(rng.uniform(2.0, 8.0))
+            f += float(rng.normal()) * torch.exp(-((x - c) ** 2).sum(1) / (w * w))
+        out.append(scale * f)
+    return torch.cat(out)
+
+
+def make_example(ctx: pb.Context, n_atoms: int, seed: int, h: float, n_random: int, rng: np.random.Generator):
+    """One molecule: (prm, band, list of (v, u) pairs)."""
+    atoms = synth.globule(n_atoms, seed)
+    prm = pb.params(h, ls_mode=pb.PB_LS_SES)
+    grid = pb.pb_grid_for_atoms(atoms, prm)
+    at = torch.tensor(atoms, dtype=torch.float64, device="cuda")
+    phi = pb.pb_build_levelset(ctx, at, prm, grid)
+    band = pb.pb_narrowband_compact(ctx, grid, phi, prm)
+    g = pb.pb_ibim_rhs(ctx, band, at, prm)
+    u, st = pb.pb_ibim_solve(ctx, band, at, prm, pb.solve_opts(tol=1e-8, precision=pb.PB_MIXED))
+    pairs = [(g, u)]
+    for _ in range(n_random):
+        e = smooth_field(band, rng)
+        pairs.append((pb.pb_ibim_matvec(ctx, band, prm, e, pb.PB_MIXED), e))
+    return prm, band, pairs
+
+
+def train(ctx: pb.Context, net: pb.Net, n_mol: int = 2000, lo: int = 200, hi: int = 1500, h: float = 0.5,
+          seed0: int = 100000, epochs: int = 2, lr: float = 1e-3, n_random: int = 1, log=None) -> dict:
+    """Builds the training set (n_mol molecules, atom counts uniform in [lo, hi]) and trains."""
+    rng = np.random.default_rng(seed0)
+    t0 = time.perf_counter()
+    data = []
+    for i in range(n_mol):
+        na = int(rng.integers(lo, hi + 1))
+        data.append(make_example(ctx, na, seed0 + i, h, n_random, rng))
+        if log and (i + 1) % max(1, n_mol // 10) == 0:
+            log(f"training set: {i + 1}/{n_mol} molecules")
+    t_data = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    history = []
+    for ep in range(epochs):
+        order = rng.permutation(len(data))
+        tot, cnt = 0.0, 0
+        for k in order:
+            prm, band, pairs = data[k]
+            pb.pb_nn_prepare(ctx, band, prm)
+            for v, u in pairs:
+                step_lr = lr * 0.5 * (1 + math.cos(math.pi * (ep + cnt / max(1, len(data))) / epochs))
+                tot += pb.pb_nn_train_step(ctx, net, band, prm, v, u, step_lr)
+                cnt += 1
+        history.append(tot / max(cnt, 1))
+        if log:
+            log(f"epoch {ep}: mean loss {history[-1]:.4f}")
+    return {"molecules": n_mol, "epochs": epochs, "t_data_s": t_data, "t_train_s": time.perf_counter() - t1,
+            "loss": history}

@@ -27,7 +27,9 @@ KCAL_PER_UNIT = 4.0 * np.pi * 332.0637
 EXPORTS = [
     "pb_create", "pb_destroy", "pb_last_error", "pb_default_params", "pb_default_solve_opts",
     "pb_grid_for_atoms", "pb_build_levelset", "pb_narrowband_compact", "pb_ibim_rhs", "pb_ibim_matvec",
-    "pb_ibim_solve", "pb_solvation_energy", "pb_set_timing", "pb_kernel_time",
+    "pb_ibim_solve", "pb_solvation_energy", "pb_set_timing", "pb_kernel_time", "pb_ibim_solve_batched",
+    "pb_nn_create", "pb_nn_destroy", "pb_nn_param_count", "pb_nn_get_params", "pb_nn_set_params", "pb_nn_prepare",
+    "pb_nn_apply", "pb_nn_train_step", "pb_nn_geometry",
 ]
 
 
@@ -56,6 +58,12 @@ class pb_solve_stats(C.Structure):
     _fields_ = [("iters", C.c_int), ("outer", C.c_int), ("converged", C.c_int), ("fallback_used", C.c_int),
                 ("matvecs_fp64", C.c_int), ("matvecs_mixed", C.c_int), ("true_relres", C.c_double),
                 ("t_total_s", C.c_double), ("t_matvec_s", C.c_double), ("pairs", C.c_double)]
+
+
+class pb_batch_stats(C.Structure):
+    _fields_ = [("t_total_s", C.c_double), ("t_p50_s", C.c_double), ("t_p99_s", C.c_double), ("pairs", C.c_double),
+                ("graph_replays", C.c_int), ("far_tile", C.c_int), ("far_tpl", C.c_int), ("n_items", C.c_int),
+                ("outer", C.c_int), ("reserved", C.c_int)]
 
 
 class pb_energy(C.Structure):
@@ -90,10 +98,24 @@ def load(path: str = LIB_PATH):
     L.pb_ibim_matvec.argtypes = [vp, P(pb_band), P(pb_params), C.c_int, vp, vp]
     L.pb_ibim_solve.argtypes = [vp, P(pb_band), vp, C.c_int, P(pb_params), P(pb_solve_opts), vp, P(pb_solve_stats)]
     L.pb_solvation_energy.argtypes = [vp, P(pb_band), vp, C.c_int, P(pb_params), vp, P(pb_energy), vp]
+    L.pb_ibim_solve_batched.argtypes = [vp, C.c_int, P(pb_band), P(vp), P(C.c_int), P(pb_params), P(pb_solve_opts),
+                                        P(vp), P(pb_solve_stats), P(pb_batch_stats)]
+    L.pb_nn_create.argtypes = [vp, C.c_uint64, P(vp)]
+    L.pb_nn_destroy.argtypes = [vp]
+    L.pb_nn_destroy.restype = None
+    L.pb_nn_param_count.argtypes = []
+    L.pb_nn_param_count.restype = C.c_int64
+    L.pb_nn_get_params.argtypes = [vp, vp, vp, vp]
+    L.pb_nn_set_params.argtypes = [vp, vp, vp]
+    L.pb_nn_prepare.argtypes = [vp, P(pb_band), P(pb_params)]
+    L.pb_nn_apply.argtypes = [vp, vp, P(pb_band), P(pb_params), vp, vp]
+    L.pb_nn_train_step.argtypes = [vp, vp, P(pb_band), P(pb_params), vp, vp, C.c_float, P(C.c_double)]
+    L.pb_nn_geometry.argtypes = [vp, P(pb_band), vp, vp]
     L.pb_set_timing.argtypes = [vp, C.c_int]
     L.pb_kernel_time.argtypes = [vp, C.c_char_p, P(C.c_double), P(C.c_int64)]
     for name in EXPORTS:
-        if name not in ("pb_destroy", "pb_last_error", "pb_default_params", "pb_default_solve_opts"):
+        if name not in ("pb_destroy", "pb_last_error", "pb_default_params", "pb_default_solve_opts", "pb_nn_destroy",
+                        "pb_nn_param_count"):
             getattr(L, name).restype = C.c_int
     return L
 
@@ -260,6 +282,27 @@ def pb_ibim_solve(ctx: Context, band: Band, atoms: torch.Tensor, prm: pb_params,
     return p, stats
 
 
+def pb_ibim_solve_batched(ctx: Context, bands: list, atoms: list, prm: pb_params, opts: pb_solve_opts | None = None,
+                          ps: list | None = None, allow_noconv: bool = False):
+    """Batched mixed-precision solve of several molecules. Returns (list of p, list of stats, batch stats)."""
+    n = len(bands)
+    if opts is None:
+        opts = solve_opts(precision=PB_MIXED)
+    if ps is None:
+        ps = [torch.zeros(2 * b.n, dtype=torch.float64, device=a.device) for b, a in zip(bands, atoms)]
+    barr = (pb_band * n)(*[b.struct() for b in bands])
+    aarr = (C.c_void_p * n)(*[a.data_ptr() for a in atoms])
+    narr = (C.c_int * n)(*[a.shape[0] for a in atoms])
+    parr = (C.c_void_p * n)(*[q.data_ptr() for q in ps])
+    stats = (pb_solve_stats * n)()
+    bst = pb_batch_stats()
+    st = lib.pb_ibim_solve_batched(ctx.handle, n, barr, aarr, narr, C.byref(prm), C.byref(opts), parr, stats,
+                                   C.byref(bst))
+    if not (allow_noconv and st == PB_ENOCONV):
+        ctx.check(st)
+    return ps, list(stats), bst
+
+
 def pb_solvation_energy(ctx: Context, band: Band, atoms: torch.Tensor, prm: pb_params, p: torch.Tensor,
                         psi_rxn: torch.Tensor | None = None) -> pb_energy:
     out = pb_energy()
@@ -267,3 +310,97 @@ def pb_solvation_energy(ctx: Context, band: Band, atoms: torch.Tensor, prm: pb_p
     ctx.check(lib.pb_solvation_energy(ctx.handle, C.byref(s), _ptr(atoms), atoms.shape[0], C.byref(prm), _ptr(p),
                                       C.byref(out), _ptr(psi_rxn) if psi_rxn is not None else None))
     return out
+
+
+# ---------------------------------------------------------------- learned preconditioner
+
+NN_FORMAT = 1
+NN_LAYERS = ((256, 64), (1024, 64), (1024, 64), (1024, 16))  # (K, Cout) per layer
+
+
+class Net:
+    """pb_nn handle: the point-convolution network on the device."""
+
+    def __init__(self, ctx: Context, seed: int = 0):
+        self.ctx = ctx
+        self.handle = C.c_void_p()
+        ctx.check(lib.pb_nn_create(ctx.handle, seed, C.byref(self.handle)))
+
+    @staticmethod
+    def param_count() -> int:
+        return int(lib.pb_nn_param_count())
+
+    def close(self):
+        if self.handle:
+            lib.pb_nn_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self) -> np.ndarray:
+        out = np.empty(self.param_count(), dtype=np.float32)
+        self.ctx.check(lib.pb_nn_get_params(self.ctx.handle, self.handle, out.ctypes.data_as(C.c_void_p), None))
+        return out
+
+    def grads(self) -> np.ndarray:
+        out = np.empty(self.param_count(), dtype=np.float32)
+        self.ctx.check(lib.pb_nn_get_params(self.ctx.handle, self.handle, None, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def set_params(self, w: np.ndarray):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        assert w.size == self.param_count()
+        self.ctx.check(lib.pb_nn_set_params(self.ctx.handle, self.handle, w.ctypes.data_as(C.c_void_p)))
+
+    def save(self, path: str):
+        """Weights file: format version, layer shapes, FP32 parameters and their SHA-256."""
+        import hashlib
+        w = self.params()
+        np.savez(path, format=np.int64(NN_FORMAT), layers=np.array(NN_LAYERS, dtype=np.int64), params=w,
+                 sha256=np.frombuffer(hashlib.sha256(w.tobytes()).digest(), dtype=np.uint8))
+
+    def load(self, path: str):
+        import hashlib
+        z = np.load(path, allow_pickle=False)
+        if int(z["format"]) != NN_FORMAT or tuple(map(tuple, z["layers"])) != NN_LAYERS:
+            raise ValueError(f"{path}: unsupported network format")
+        w = z["params"].astype(np.float32)
+        if hashlib.sha256(w.tobytes()).digest() != z["sha256"].tobytes():
+            raise ValueError(f"{path}: parameter hash mismatch")
+        self.set_params(w)
+
+
+def pb_nn_prepare(ctx: Context, band: Band, prm: pb_params):
+    s = band.struct()
+    ctx.check(lib.pb_nn_prepare(ctx.handle, C.byref(s), C.byref(prm)))
+
+
+def pb_nn_apply(ctx: Context, net: Net, band: Band, prm: pb_params, v: torch.Tensor,
+                out: torch.Tensor | None = None) -> torch.Tensor:
+    if out is None:
+        out = torch.empty_like(v)
+    s = band.struct()
+    ctx.check(lib.pb_nn_apply(ctx.handle, net.handle, C.byref(s), C.byref(prm), _ptr(v), _ptr(out)))
+    return out
+
+
+def pb_nn_train_step(ctx: Context, net: Net, band: Band, prm: pb_params, v: torch.Tensor, u: torch.Tensor,
+                     lr: float) -> float:
+    s = band.struct()
+    loss = C.c_double()
+    ctx.check(lib.pb_nn_train_step(ctx.handle, net.handle, C.byref(s), C.byref(prm), _ptr(v), _ptr(u), lr,
+                                   C.byref(loss)))
+    return loss.value
+
+
+def pb_nn_geometry(ctx: Context, band: Band):
+    nbr = np.empty((band.n, 16), dtype=np.int32)
+    feat = np.empty((band.n, 5), dtype=np.float32)
+    s = band.struct()
+    ctx.check(lib.pb_nn_geometry(ctx.handle, C.byref(s), nbr.ctypes.data_as(C.c_void_p),
+                                 feat.ctypes.data_as(C.c_void_p)))
+    return nbr, feat

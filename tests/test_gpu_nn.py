@@ -1,0 +1,183 @@
+"""GPU: the learned preconditioner's BF16 MFMA kernels against the FP64 CPU reference
+(oracle/nn_ref.py), its training, and what it gains over the method without it.
+
+Bars: neighbour lists bit-exact; features 1e-6; M(v) and the parameter gradients within a
+few BF16 units (2e-2 relative) of the reference evaluated with the same BF16 roundings;
+training lowers the loss; the learned solve never ends worse than plain GMRES (plain GMRES
+is the fallback) and reaches the same energy.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import nn_ref
+from paper_1709_08070_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pbm():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1709_08070_amd import pb
+
+    return pb
+
+
+@pytest.fixture(scope="module")
+def ctx(pbm):
+    return pbm.Context(0)
+
+
+def _band(pbm, ctx, atoms, h=0.5):
+    import torch
+
+    prm = pbm.params(h, ls_mode=pbm.PB_LS_SES)
+    grid = pbm.pb_grid_for_atoms(atoms, prm)
+    at = torch.tensor(atoms, dtype=torch.float64, device="cuda")
+    phi = pbm.pb_build_levelset(ctx, at, prm, grid)
+    return prm, at, pbm.pb_narrowband_compact(ctx, grid, phi, prm)
+
+
+@pytest.fixture(scope="module")
+def small(pbm, ctx):
+    say("case: nn geometry, globule 12 atoms seed 21 h=0.5")
+    atoms = synth.globule(12, 21)
+    prm, at, band = _band(pbm, ctx, atoms)
+    pbm.pb_nn_prepare(ctx, band, prm)
+    nodes = band.table()
+    ref_nbr = nn_ref.knn(nodes[:, :3])
+    return dict(atoms=atoms, prm=prm, at=at, band=band, nodes=nodes, ref_nbr=ref_nbr)
+
+
+def test_neighbours_and_features(pbm, ctx, small):
+    nbr, feat = pbm.pb_nn_geometry(ctx, small["band"])
+    say(f"n={small['band'].n}")
+    np.testing.assert_array_equal(nbr, small["ref_nbr"])
+    ref = nn_ref.features(small["nodes"], small["ref_nbr"], 1.0)
+    np.testing.assert_allclose(feat, ref, rtol=0, atol=2e-6)
+
+
+def _random_params(pbm, seed, scale_last=0.05):
+    rng = np.random.default_rng(seed)
+    w = np.zeros(pbm.Net.param_count(), dtype=np.float32)
+    off = 0
+    for K, C in nn_ref.layer_shapes():
+        a = np.sqrt(6.0 / K) * (scale_last if C == 16 else 1.0)
+        w[off:off + K * C] = rng.uniform(-a, a, K * C)
+        off += K * C
+        w[off:off + C] = rng.normal(0, 0.05, C)
+        off += C
+    return w
+
+
+def test_apply_matches_reference(pbm, ctx, small):
+    import torch
+
+    net = pbm.Net(ctx, seed=1)
+    w = _random_params(pbm, 2, scale_last=1.0)
+    net.set_params(w)
+    n = small["band"].n
+    v = np.random.default_rng(3).normal(size=2 * n)
+    p = pbm.pb_nn_apply(ctx, net, small["band"], small["prm"], torch.tensor(v, device="cuda")).cpu().numpy()
+    feat = nn_ref.features(small["nodes"], small["ref_nbr"], 1.0).astype(np.float32)
+    ref = nn_ref.apply(small["nodes"], small["ref_nbr"], feat, v, w, (40.5, 0.50625), 1.0)
+    diag = np.concatenate([v[:n] / 40.5, v[n:] / 0.50625])
+    err = np.linalg.norm(p - ref) / np.linalg.norm(ref - diag)
+    say(f"apply: correction rel err {err:.3e}")
+    assert err < 2e-2
+    # an untrained network is exactly the diagonal solve
+    net0 = pbm.Net(ctx, seed=5)
+    p0 = pbm.pb_nn_apply(ctx, net0, small["band"], small["prm"], torch.tensor(v, device="cuda")).cpu().numpy()
+    np.testing.assert_allclose(p0, diag, rtol=1e-15)
+
+
+def test_gradients_match_reference(pbm, ctx, small):
+    import torch
+
+    net = pbm.Net(ctx, seed=1)
+    w = _random_params(pbm, 7, scale_last=1.0)
+    net.set_params(w)
+    n = small["band"].n
+    rng = np.random.default_rng(8)
+    v, u = rng.normal(size=2 * n), rng.normal(size=2 * n)
+    loss = pbm.pb_nn_train_step(ctx, net, small["band"], small["prm"], torch.tensor(v, device="cuda"),
+                                torch.tensor(u, device="cuda"), 0.0)
+    g = net.grads().astype(np.float64)
+    feat = nn_ref.features(small["nodes"], small["ref_nbr"], 1.0).astype(np.float32)
+    rl, rg = nn_ref.loss_and_grads(small["nodes"], small["ref_nbr"], feat, v, u, w, (40.5, 0.50625), 1.0)
+    say(f"loss gpu {loss:.6e} ref {rl:.6e}")
+    assert loss == pytest.approx(rl, rel=1e-2)
+    off = 0
+    for K, C in nn_ref.layer_shapes():
+        for size in (K * C, C):
+            a, b = g[off:off + size], rg[off:off + size]
+            err = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+            say(f"grad block {off}:{off + size} rel err {err:.3e}")
+            assert err < 3e-2
+            off += size
+
+
+def _training_set(pbm, ctx, seeds, sizes):
+    import torch
+
+    data = []
+    for s, na in zip(seeds, sizes):
+        atoms = synth.globule(na, s)
+        prm, at, band = _band(pbm, ctx, atoms)
+        g = pbm.pb_ibim_rhs(ctx, band, at, prm)
+        u, st = pbm.pb_ibim_solve(ctx, band, at, prm, pbm.solve_opts(tol=1e-8, precision=pbm.PB_MIXED))
+        data.append((prm, at, band, g, u))
+    return data
+
+
+def test_training_and_gain(pbm, ctx):
+    import torch
+
+    say("case: nn training on 12 globules (40-120 atoms), held-out 2 globules (150 atoms)")
+    rng = np.random.default_rng(11)
+    train = _training_set(pbm, ctx, list(range(9100, 9112)), list(rng.integers(40, 121, 12)))
+    net = pbm.Net(ctx, seed=3)
+    losses = []
+    for epoch in range(25):
+        for prm, at, band, g, u in train:
+            pbm.pb_nn_prepare(ctx, band, prm)
+            losses.append(pbm.pb_nn_train_step(ctx, net, band, prm, g, u, 2e-3))
+    first, last = np.mean(losses[:12]), np.mean(losses[-12:])
+    say(f"loss first epoch {first:.4f} last epoch {last:.4f}")
+    assert last < 0.7 * first
+    gains = []
+    for s in (9900, 9901):
+        atoms = synth.globule(150, s)
+        prm, at, band = _band(pbm, ctx, atoms)
+        base, st0 = pbm.pb_ibim_solve(ctx, band, at, prm, pbm.solve_opts(tol=1e-6, precision=pbm.PB_MIXED))
+        q, st1 = pbm.pb_ibim_solve(ctx, band, at, prm, pbm.solve_opts(
+            tol=1e-6, precision=pbm.PB_MIXED, x0=pbm.PB_X0_LEARNED, precond=pbm.PB_PRECOND_LEARNED, nn=net.handle))
+        e0 = pbm.pb_solvation_energy(ctx, band, at, prm, base).g_pol
+        e1 = pbm.pb_solvation_energy(ctx, band, at, prm, q).g_pol
+        say(f"held-out {s}: plain iters {st0.iters} learned iters {st1.iters} fallback {st1.fallback_used} "
+            f"energies {e0:.8e} {e1:.8e}")
+        assert st1.converged and st1.true_relres <= 1e-6
+        assert e1 == pytest.approx(e0, rel=1e-5)
+        gains.append(st0.iters - st1.iters)
+    assert min(gains) >= 0
+
+
+def test_fallback_to_plain_gmres(pbm, ctx, small):
+    net = pbm.Net(ctx, seed=9)
+    w = _random_params(pbm, 10, scale_last=1.0) * 40.0  # a useless network
+    net.set_params(w)
+    q, st = pbm.pb_ibim_solve(ctx, small["band"], small["at"], small["prm"], pbm.solve_opts(
+        tol=1e-8, precision=pbm.PB_MIXED, precond=pbm.PB_PRECOND_LEARNED, nn=net.handle, max_iter=60))
+    say(f"fallback: used={st.fallback_used} iters={st.iters} relres={st.true_relres:.2e}")
+    assert st.converged and st.true_relres <= 1e-8
