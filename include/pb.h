@@ -181,7 +181,10 @@ pb_status pb_solvation_energy(pb_ctx* ctx, const pb_band* band, const double* at
 /* Batched solve statistics (host). */
 typedef struct {
   double t_total_s;    /* wall time of the call, set-up included */
-  double t_p50_s;      /* median per-molecule time to solution, from the start of the solve */
+  double t_p50_s;      /* median per-molecule time to solution, from the start of the solve to
+                          the end of the molecule's last restart cycle (device clock); the
+                          FP64 residual that confirms it is formed at the batch's next outer
+                          step */
   double t_p99_s;      /* 99th percentile of the same */
   double pairs;        /* pair-interactions evaluated over the whole batch */
   int graph_replays;   /* replays of the captured Arnoldi-step graph */

@@ -16,7 +16,8 @@
 // replays.
 //
 // Mixed precision as in the single solve: each outer step forms the FP64 residual with the
-// persistent FP64 operator and solves the correction with the mixed operator.
+// persistent FP64 operator and solves the correction with the mixed operator, to
+// max(½·tol·‖g‖, η·‖r‖) or until a restart cycle stalls at the FP32 rounding level.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -40,8 +41,10 @@ struct MolDev {
   double cx, cy, cz;
   BandDev band;
   const double* w;
-  float4* A;
-  float4* B;
+  float4* A;  // FP32 records (σ(x − c), ψn weight), σ·(ψ weight)·n, n
+  float4* M;
+  const float4* N;
+  const float4* box;  // bounding boxes of groups of 256 records
   const int64_t* row;
   const int* col;
   const double4* coef;
@@ -58,8 +61,9 @@ struct KState {
   int active;      // still iterating in this cycle
   int k_used;      // Arnoldi steps taken in this cycle
   int iters;       // total steps
-  int pad;
-  unsigned long long t_done;
+  int early;       // the cycle ended on its residual estimate (not on the restart length)
+  unsigned long long t_inner;  // device clock when its last restart cycle ended
+  unsigned long long t_done;   // the same, for the cycle whose result met the tolerance
 };
 
 // ---------------------------------------------------------------- operator kernels
@@ -75,10 +79,10 @@ static __global__ void __launch_bounds__(kBlock) k_pack_batch(int ntot, const in
   const double* v = x + (kptr ? (int64_t)(*kptr) * ldv : 0);
   const int l = g - m.off;
   const double s = scale * m.w[l];
-  const double w1 = s * v[2 * (int64_t)m.off + l], w2 = s * v[2 * (int64_t)m.off + m.n + l];
+  const double w1 = sigma * s * v[2 * (int64_t)m.off + l], w2 = s * v[2 * (int64_t)m.off + m.n + l];
   m.A[l] = make_float4((float)(sigma * (m.band.px[l] - m.cx)), (float)(sigma * (m.band.py[l] - m.cy)),
-                       (float)(sigma * (m.band.pz[l] - m.cz)), (float)(sigma * w1));
-  m.B[l] = make_float4((float)m.band.nx[l], (float)m.band.ny[l], (float)m.band.nz[l], (float)w2);
+                       (float)(sigma * (m.band.pz[l] - m.cz)), (float)w2);
+  m.M[l] = make_float4((float)(w1 * m.band.nx[l]), (float)(w1 * m.band.ny[l]), (float)(w1 * m.band.nz[l]), 0.f);
 }
 
 template <int TILE, int TPL, bool kScreened>
@@ -86,7 +90,7 @@ static __global__ void __launch_bounds__(kBlock) k_far32_batch(const Item* __res
                                                                const MolDev* __restrict__ mols, int chunk,
                                                                const int* __restrict__ active, F32Params fp, double sig1,
                                                                double sig2, double* __restrict__ partial) {
-  __shared__ float4 sA[TILE], sB[TILE];
+  __shared__ float4 sA[TILE], sM[TILE];
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     const Item w = items[it];
     if (!active[w.mol]) continue;
@@ -95,8 +99,8 @@ static __global__ void __launch_bounds__(kBlock) k_far32_batch(const Item* __res
     const int j0 = w.ch * chunk;
     const int j1 = min(m.n, j0 + chunk);
     double* out = partial + m.poff32 + (int64_t)w.ch * 2 * m.n;
-    far_tile_loop<kBlock, TILE, TPL, kScreened>(m.A, m.B, t0, m.n, j0, j1, fp, sig1, sig2, sA, sB, out + t0,
-                                                out + m.n + t0);
+    far_tile_loop<kBlock, TILE, TPL, kScreened>(m.A, m.M, m.N, m.box, t0, m.n, j0, j1, fp, sig1, sig2, sA, sM,
+                                                out + t0, out + m.n + t0);
   }
 }
 
@@ -309,7 +313,10 @@ static __global__ void k_givens_batch(int n_mol, int m, const int* __restrict__ 
   sm[k] = csm[k] * sm[k];
   st[mol].k_used = k + 1;
   st[mol].iters += 1;
-  if (fabs(sm[k + 1]) <= st[mol].tol_abs || !(hn > 0.0) || k + 1 >= m) {
+  const bool reached = fabs(sm[k + 1]) <= st[mol].tol_abs || !(hn > 0.0);
+  if (reached || k + 1 >= m) {
+    st[mol].early = reached;
+    st[mol].t_inner = wall_clock64();
     active[mol] = 0;
     atomicSub(n_active, 1);
   }
@@ -358,20 +365,25 @@ static __global__ void k_trisolve_batch(int n_mol, int m, const int* __restrict_
   }
 }
 
-// Start of a cycle: s = [β, 0, …], active, tolerance; one thread per molecule.
-static __global__ void k_cycle_init(int n_mol, int m, const double* __restrict__ beta, const double* __restrict__ tol_abs,
-                                    const int* __restrict__ want, double* __restrict__ s, KState* __restrict__ st,
-                                    int* __restrict__ active, int* __restrict__ n_active, int* __restrict__ kptr) {
+// Start of a cycle: s = [β, 0, …], active, tolerance; one thread per molecule. After the
+// first cycle of an inner solve, a molecule whose last cycle ended on its residual estimate
+// but did not halve the true residual has stalled at the FP32 rounding level and stops.
+static __global__ void k_cycle_init(int n_mol, int m, int first, const double* __restrict__ beta,
+                                    const double* __restrict__ tol_abs, const int* __restrict__ want,
+                                    double* __restrict__ s, KState* __restrict__ st, int* __restrict__ active,
+                                    int* __restrict__ n_active, int* __restrict__ kptr) {
   const int mol = blockIdx.x * blockDim.x + threadIdx.x;
   if (mol == 0) *kptr = 0;
   if (mol >= n_mol) return;
+  const bool stalled = !first && st[mol].early && beta[mol] > 0.5 * st[mol].beta;
   double* sm = s + (int64_t)mol * (m + 1);
   for (int i = 0; i <= m; ++i) sm[i] = 0.0;
   sm[0] = beta[mol];
   st[mol].beta = beta[mol];
   st[mol].tol_abs = tol_abs[mol];
   st[mol].k_used = 0;
-  const int a = want[mol] && beta[mol] > tol_abs[mol];
+  st[mol].early = 0;
+  const int a = want[mol] && beta[mol] > tol_abs[mol] && !stalled;
   active[mol] = a;
   if (a) atomicAdd(n_active, 1);
 }
@@ -441,18 +453,20 @@ static __global__ void __launch_bounds__(kBlock) k_add_batch(int nseg, Segs sg, 
   for (int64_t e = sg.lo[b] + threadIdx.x; e < sg.hi[b]; e += kBlock) x[e] += d[e];
 }
 
-// relres per molecule and the outer-loop selection: sel[m] = relres > tol (done otherwise,
-// with a timestamp the first time).
+// relres per molecule and the outer-loop selection: sel[m] = relres > tol (done otherwise;
+// its time to solution is when its last restart cycle ended, or now if it ran none); the next
+// inner solve's target max(½·tol·‖g‖, η·‖r‖).
 static __global__ void k_outer_check(int n_mol, const double* __restrict__ rn, const double* __restrict__ gn,
-                                     double tol, int* __restrict__ sel, double* __restrict__ relres,
-                                     KState* __restrict__ st, int* __restrict__ n_sel) {
+                                     double tol, double eta, int* __restrict__ sel, double* __restrict__ relres,
+                                     double* __restrict__ tol_abs, KState* __restrict__ st, int* __restrict__ n_sel) {
   const int mol = blockIdx.x * blockDim.x + threadIdx.x;
   if (mol >= n_mol || !sel[mol]) return;
   const double rr = rn[mol] / gn[mol];
   relres[mol] = rr;
+  tol_abs[mol] = fmax(0.5 * tol * gn[mol], eta * rn[mol]);
   if (!(rr > tol)) {
     sel[mol] = 0;
-    st[mol].t_done = wall_clock64();
+    st[mol].t_done = st[mol].t_inner ? st[mol].t_inner : wall_clock64();
   } else {
     atomicAdd(n_sel, 1);
   }
@@ -676,7 +690,9 @@ extern "C" pb_status pb_ibim_solve_batched(pb_ctx* ctx, int n_mol, const pb_band
     md.band = band_dev(&bands[i]);
     md.w = bands[i].w;
     md.A = P.A;
-    md.B = P.B;
+    md.M = P.M;
+    md.N = P.N;
+    md.box = P.box;
     md.row = P.row;
     md.col = P.col;
     md.coef = P.coef;
@@ -835,11 +851,6 @@ extern "C" pb_status pb_ibim_solve_batched(pb_ctx* ctx, int n_mol, const pb_band
     }
   }
 
-  // tolerance of the inner solves: ½·tol·‖g_m‖ (mixed) or tol·‖g_m‖ (FP64 runs no inner solve)
-  std::vector<double> tol_h(n_mol);
-  for (int i = 0; i < n_mol; ++i) tol_h[i] = (opts.precision == PB_MIXED ? 0.5 : 1.0) * opts.tol * gn_h[i];
-  PB_HIP(ctx, hipMemcpyAsync(tolabs, tol_h.data(), sizeof(double) * n_mol, hipMemcpyHostToDevice, B.st));
-
   // the graph of one Arnoldi step of the batch
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -872,10 +883,10 @@ extern "C" pb_status pb_ibim_solve_batched(pb_ctx* ctx, int n_mol, const pb_band
     // sol = 0, so the first residual is the right-hand side itself
     k_copy<<<vb, kBlock, 0, B.st>>>(B.M, rhs_vec, rr);
     norms(B, rr, want, rn);
-    for (;;) {
+    for (int first = 1;; first = 0) {
       PB_HIP(ctx, hipMemsetAsync(B.n_active, 0, sizeof(int), B.st));
-      k_cycle_init<<<(n_mol + 63) / 64, 64, 0, B.st>>>(n_mol, m, rn, tolabs, want, B.s, B.kst, B.active, B.n_active,
-                                                      B.kptr);
+      k_cycle_init<<<(n_mol + 63) / 64, 64, 0, B.st>>>(n_mol, m, first, rn, tolabs, want, B.s, B.kst, B.active,
+                                                      B.n_active, B.kptr);
       PB_HIP(ctx, hipMemcpyAsync(B.cycle, B.active, sizeof(int) * n_mol, hipMemcpyDeviceToDevice, B.st));
       int nact = 0;
       PB_HIP(ctx, hipMemcpyAsync(&nact, B.n_active, sizeof(int), hipMemcpyDeviceToHost, B.st));
@@ -927,7 +938,8 @@ extern "C" pb_status pb_ibim_solve_batched(pb_ctx* ctx, int n_mol, const pb_band
       norms(B, r, sel, rn);
       PB_HIP(ctx, hipMemsetAsync(n_sel, 0, sizeof(int), B.st));
       PB_HIP(ctx, hipMemcpyAsync(sel_h.data(), sel, sizeof(int) * n_mol, hipMemcpyDeviceToHost, B.st));
-      k_outer_check<<<(n_mol + 63) / 64, 64, 0, B.st>>>(n_mol, rn, gn, opts.tol, sel, relres, B.kst, n_sel);
+      k_outer_check<<<(n_mol + 63) / 64, 64, 0, B.st>>>(n_mol, rn, gn, opts.tol, kInnerEta, sel, relres, tolabs,
+                                                        B.kst, n_sel);
       PB_TRY(launch_ok(ctx, "outer check"));
       int nsel = 0;
       PB_HIP(ctx, hipMemcpyAsync(&nsel, n_sel, sizeof(int), hipMemcpyDeviceToHost, B.st));

@@ -40,25 +40,25 @@ int far_chunks(pb_ctx* ctx, int n, int targets_per_block, int tile, int* chunk) 
 }
 
 template <int TILE, int TPL>
-int launch_far_t(pb_ctx* ctx, bool screened, const float4* A, const float4* B, int n, const F32Params& fp, double sig1,
-                 double sig2, double* partial) {
+int launch_far_t(pb_ctx* ctx, bool screened, const float4* A, const float4* M, const float4* N, const float4* box,
+                 int n, const F32Params& fp, double sig1, double sig2, double* partial) {
   int chunk = 0;
   const int S = far_chunks(ctx, n, kBlock * TPL, TILE, &chunk);
   dim3 grid((unsigned)((n + kBlock * TPL - 1) / (kBlock * TPL)), (unsigned)S);
   if (screened)
-    k_p2p_f32<TILE, TPL, true><<<grid, kBlock, 0, ctx->stream>>>(A, B, n, chunk, fp, sig1, sig2, partial);
+    k_p2p_f32<TILE, TPL, true><<<grid, kBlock, 0, ctx->stream>>>(A, M, N, box, n, chunk, fp, sig1, sig2, partial);
   else
-    k_p2p_f32<TILE, TPL, false><<<grid, kBlock, 0, ctx->stream>>>(A, B, n, chunk, fp, sig1, sig2, partial);
+    k_p2p_f32<TILE, TPL, false><<<grid, kBlock, 0, ctx->stream>>>(A, M, N, box, n, chunk, fp, sig1, sig2, partial);
   return S;
 }
 
-int launch_far(pb_ctx* ctx, int cfg, bool screened, const float4* A, const float4* B, int n, const F32Params& fp,
-               double sig1, double sig2, double* partial) {
+int launch_far(pb_ctx* ctx, int cfg, bool screened, const float4* A, const float4* M, const float4* N,
+               const float4* box, int n, const F32Params& fp, double sig1, double sig2, double* partial) {
   switch (cfg) {
-    case 0: return launch_far_t<256, 1>(ctx, screened, A, B, n, fp, sig1, sig2, partial);
-    case 1: return launch_far_t<512, 1>(ctx, screened, A, B, n, fp, sig1, sig2, partial);
-    case 2: return launch_far_t<256, 2>(ctx, screened, A, B, n, fp, sig1, sig2, partial);
-    default: return launch_far_t<512, 2>(ctx, screened, A, B, n, fp, sig1, sig2, partial);
+    case 0: return launch_far_t<256, 1>(ctx, screened, A, M, N, box, n, fp, sig1, sig2, partial);
+    case 1: return launch_far_t<512, 1>(ctx, screened, A, M, N, box, n, fp, sig1, sig2, partial);
+    case 2: return launch_far_t<256, 2>(ctx, screened, A, M, N, box, n, fp, sig1, sig2, partial);
+    default: return launch_far_t<512, 2>(ctx, screened, A, M, N, box, n, fp, sig1, sig2, partial);
   }
 }
 
@@ -74,8 +74,8 @@ int far_max_chunks(pb_ctx* ctx, int n) {
 // Picks the far-field tile shape for a band of n nodes by timing each candidate once on the
 // packed records (after one warm-up launch); the choice is cached per n on the context.
 // PB_FAR_CFG=<index> in the environment fixes the choice instead.
-pb_status far_autotune(pb_ctx* ctx, int n, bool screened, const float4* A, const float4* B, const F32Params& fp,
-                       double* partial, int* cfg_out) {
+pb_status far_autotune(pb_ctx* ctx, int n, bool screened, const float4* A, const float4* M, const float4* N,
+                       const float4* box, const F32Params& fp, double* partial, int* cfg_out) {
   auto it = ctx->far_cfg.find(n);
   if (it != ctx->far_cfg.end()) {
     *cfg_out = it->second;
@@ -95,9 +95,9 @@ pb_status far_autotune(pb_ctx* ctx, int n, bool screened, const float4* A, const
   int best = 0;
   float best_ms = 1e30f;
   for (int c = 0; c < kNumFarCfgs; ++c) {
-    launch_far(ctx, c, screened, A, B, n, fp, 1.0, 1.0, partial);
+    launch_far(ctx, c, screened, A, M, N, box, n, fp, 1.0, 1.0, partial);
     PB_HIP(ctx, hipEventRecord(e0, ctx->stream));
-    launch_far(ctx, c, screened, A, B, n, fp, 1.0, 1.0, partial);
+    launch_far(ctx, c, screened, A, M, N, box, n, fp, 1.0, 1.0, partial);
     PB_HIP(ctx, hipEventRecord(e1, ctx->stream));
     PB_TRY(launch_ok(ctx, "far autotune"));
     PB_HIP(ctx, hipEventSynchronize(e1));
@@ -139,7 +139,8 @@ pb_status matvec_fp64(pb_ctx* ctx, const pb_band* band, const Derived& d, const 
 
 F32Params f32params(const Derived& d, double sigma) {
   const double rcs = sigma * d.rc;
-  return F32Params{(float)d.th1, (float)d.th2, (float)(-1.4426950408889634), (float)(rcs * rcs)};
+  return F32Params{(float)d.th1, (float)d.th2, (float)(-1.4426950408889634), (float)(rcs * rcs),
+                   (float)(rcs * rcs * 1.001)};
 }
 
 // Geometry of the mixed operator for one band: centre and scale of the FP32 records, the
@@ -193,9 +194,12 @@ pb_status near_build(pb_ctx* ctx, const pb_band* band, const Derived& d, const c
   int* nodes = (int*)workspace(ctx, name("cell_nodes"), sizeof(int) * (size_t)n);
   int* cell_of = (int*)workspace(ctx, name("cell_of"), sizeof(int) * (size_t)n);
   float4* A = (float4*)workspace(ctx, name("A"), sizeof(float4) * n);
-  float4* B = (float4*)workspace(ctx, name("B"), sizeof(float4) * n);
+  float4* M = (float4*)workspace(ctx, name("M"), sizeof(float4) * n);
+  float4* N = (float4*)workspace(ctx, name("N"), sizeof(float4) * n);
+  const int ngroup = (n + kGroup - 1) / kGroup;
+  float4* box = (float4*)workspace(ctx, name("box"), sizeof(float4) * 2 * (size_t)ngroup);
   int64_t* row = (int64_t*)workspace(ctx, name("near_row"), sizeof(int64_t) * (size_t)(n + 1));
-  if (!start || !cursor || !nodes || !cell_of || !A || !B || !row) return PB_ENOMEM;
+  if (!start || !cursor || !nodes || !cell_of || !A || !M || !N || !box || !row) return PB_ENOMEM;
   PB_HIP(ctx, hipMemsetAsync(start, 0, sizeof(int64_t) * (size_t)(ncell + 1), ctx->stream));
   PB_HIP(ctx, hipMemsetAsync(cursor, 0, sizeof(int) * (size_t)ncell, ctx->stream));
   const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
@@ -209,7 +213,8 @@ pb_status near_build(pb_ctx* ctx, const pb_band* band, const Derived& d, const c
   if (cells_only) return PB_OK;
   // FP32 records (weights zero) for the near predicate, then the near-field block matrix
   k_pack_f32<<<nb, kBlock, 0, ctx->stream>>>(n, band_dev(band), band->w, nullptr, 0.0, P.cx, P.cy, P.cz, P.sigma, A,
-                                             B);
+                                             M, N);
+  k_group_box<<<(unsigned)ngroup, kGroup, 0, ctx->stream>>>(n, A, box);
   const CellsDev cells{start, nodes, cell_of, P.ncx, P.ncy, P.ncz};
   PB_HIP(ctx, hipMemsetAsync(row + n, 0, sizeof(int64_t), ctx->stream));
   k_near_count<<<nb, kBlock, 0, ctx->stream>>>(n, A, cells, P.rc2f, row);
@@ -224,7 +229,9 @@ pb_status near_build(pb_ctx* ctx, const pb_band* band, const Derived& d, const c
                                               kparams(d), row, col, coef);
   PB_TRY(launch_ok(ctx, "near fill"));
   P.A = A;
-  P.B = B;
+  P.M = M;
+  P.N = N;
+  P.box = box;
   P.row = row;
   P.col = col;
   P.coef = coef;
@@ -237,7 +244,7 @@ pb_status mixed_prepare(pb_ctx* ctx, const pb_band* band, const Derived& d) {
   MixedPlan& P = ctx->mixed;
   double* partial = (double*)workspace(ctx, "mv_partial", sizeof(double) * 2 * (size_t)n * far_max_chunks(ctx, n));
   if (!partial) return PB_ENOMEM;
-  return far_autotune(ctx, n, d.kappa > 0.0, P.A, P.B, f32params(d, P.sigma), partial, &P.far_cfg);
+  return far_autotune(ctx, n, d.kappa > 0.0, P.A, P.M, P.N, P.box, f32params(d, P.sigma), partial, &P.far_cfg);
 }
 
 pb_status matvec_mixed(pb_ctx* ctx, const pb_band* band, const Derived& d, const double* p, double* y) {
@@ -250,11 +257,12 @@ pb_status matvec_mixed(pb_ctx* ctx, const pb_band* band, const Derived& d, const
   if (!partial || !near) return PB_ENOMEM;
   const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
   k_pack_f32<<<nb, kBlock, 0, ctx->stream>>>(n, band_dev(band), band->w, p, d.h3 / (4.0 * kPi), P.cx, P.cy, P.cz,
-                                             P.sigma, P.A, P.B);
+                                             P.sigma, P.A, P.M, P.N);
   int S;
   {
     Scope t(ctx, "p2p_f32");
-    S = launch_far(ctx, P.far_cfg, d.kappa > 0.0, P.A, P.B, n, f32params(d, P.sigma), P.sigma, P.sigma * P.sigma,
+    S = launch_far(ctx, P.far_cfg, d.kappa > 0.0, P.A, P.M, P.N, P.box, n, f32params(d, P.sigma), P.sigma,
+                   P.sigma * P.sigma,
                    partial);
   }
   {

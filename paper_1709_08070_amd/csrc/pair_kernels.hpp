@@ -79,13 +79,38 @@ __device__ __forceinline__ void pair_f64(double xi, double yi, double zi, double
 
 // ---------------------------------------------------------------- FP32
 
-// FP32 records: A = (σx, σy, σz, σ·h³ωψ/4π), B = (n_x, n_y, n_z, h³ωψn/4π), with the
-// coordinates centred on the band and scaled by σ = κ (σ = 1 when κ = 0). In scaled
-// coordinates r' = κr = z, so e^{−κr} = exp2(−log2(e)·r') needs no extra product, and the
-// sums come out as y1 = σ·S1, y2 = σ²·S2 (the scale is applied in FP64 afterwards).
+// FP32 records, coordinates centred on the band and scaled by σ = κ (σ = 1 when κ = 0):
+//   A_j = (σ(x_j − c), w̃n_j),  M_j = σ·w̃_j·n_j,  N_j = n_j,
+// with w̃_j = h³ω_jψ_j/(4π) and w̃n_j = h³ω_jψn_j/(4π). In scaled coordinates r' = κr = z, so
+// e^{−κr} = exp2(−log2(e)·r') needs no extra product, and the sums come out as y1 = σ·S1,
+// y2 = σ²·S2 (the scale is applied in FP64 afterwards). Folding the ψ weight into the source
+// normal (M) lets one dot product give (d·n_j)·w̃_j and another (n_i·n_j)·w̃_j.
 struct F32Params {
   float th1, th2, mlog2e, rc2;  // rc2: squared near-field radius in scaled units
+  float far2;                   // rc2·(1 + 1e-3): a tile whose bounding box is at least this far
+                                // (squared) from the target block holds no near pair
 };
+
+constexpr int kGroup = 256;  // records per bounding box (groups aligned at multiples of kGroup)
+
+// Squared gap between two axis-aligned boxes (0 when they overlap).
+__device__ __forceinline__ float box_gap2(const float4& lo1, const float4& hi1, const float4& lo2, const float4& hi2) {
+  const float gx = fmaxf(0.f, fmaxf(lo2.x - hi1.x, lo1.x - hi2.x));
+  const float gy = fmaxf(0.f, fmaxf(lo2.y - hi1.y, lo1.y - hi2.y));
+  const float gz = fmaxf(0.f, fmaxf(lo2.z - hi1.z, lo1.z - hi2.z));
+  return gx * gx + gy * gy + gz * gz;
+}
+
+// Union of the boxes of groups [g0, g1).
+__device__ __forceinline__ void box_union(const float4* __restrict__ box, int g0, int g1, float4& lo, float4& hi) {
+  lo = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
+  hi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.f);
+  for (int g = g0; g < g1; ++g) {
+    const float4 l = box[2 * g], h = box[2 * g + 1];
+    lo.x = fminf(lo.x, l.x); lo.y = fminf(lo.y, l.y); lo.z = fminf(lo.z, l.z);
+    hi.x = fmaxf(hi.x, h.x); hi.y = fmaxf(hi.y, h.y); hi.z = fmaxf(hi.z, h.z);
+  }
+}
 
 // Squared distance in FP32 with a fixed operation sequence; every kernel that separates
 // near from far pairs calls it on the same FP32 records.
@@ -94,18 +119,22 @@ __device__ __forceinline__ float r2_f32(float xi, float yi, float zi, float xj, 
   return __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, __fmul_rn(dx, dx)));
 }
 
-// One far pair in FP32. Near pairs (r'² < rc2, which includes the self pair and every
-// regularized pair) contribute exactly zero: 1/r' is replaced by 0 and every term carries a
-// factor of it.
-//   K21·r'³ = f1 (n_i·n_j − 3u) + u E z²,  u = (d·n_i)(d·n_j)/r'², f1 = 1 − E(1+z),
-// which is (n_i·n_j) f1 − u (3 − b) rewritten with 3 − b = 3 f1 − E z².
-template <bool kScreened>
-__device__ __forceinline__ void pair_f32(const float4& ta, const float4& tb, const float4& sa, const float4& sb,
+// One far pair in FP32 (target record ta with normal tn, source records sa, sm). Near pairs
+// (r'² < rc2, which includes the self pair and every regularized pair) contribute exactly
+// zero: 1/r' is replaced by 0 and every term carries a factor of it. With d = x_i − x_j,
+// D = d·M_j = (d·n_j)σw̃_j, Nw = n_i·M_j = (n_i·n_j)σw̃_j, a = E(1+z):
+//   a1 += (1 − θ1 a) D/r'³ − (1 − E) w̃n_j/r'
+//   a2 += [(1 − a) Nw + (1 − θ2 a)(d·n_i) w̃n_j + (d·n_i) D (E z² − 3(1 − a))/r'²]/r'³,
+// the second line being K21 r'³ = (n_i·n_j)(1 − a) − (d·n_i)(d·n_j)(3 − b)/r'² with
+// 3 − b = 3(1 − a) − E z², b = E(3 + 3z + z²).
+// kCheck = false is for tiles known to hold no near pair (the predicate is then skipped).
+template <bool kScreened, bool kCheck = true>
+__device__ __forceinline__ void pair_f32(const float4& ta, const float4& tn, const float4& sa, const float4& sm,
                                          const F32Params& fp, float& a1, float& a2) {
   const float dx = ta.x - sa.x, dy = ta.y - sa.y, dz = ta.z - sa.z;
   const float r2 = r2_f32(ta.x, ta.y, ta.z, sa.x, sa.y, sa.z);
-  const bool near = r2 < fp.rc2;
-  const float rinv = near ? 0.f : __builtin_amdgcn_rsqf(r2);
+  float rinv = __builtin_amdgcn_rsqf(r2);
+  if (kCheck && r2 < fp.rc2) rinv = 0.f;
   float E = 1.f, Ez = 0.f, z = 0.f;
   if (kScreened) {
     z = r2 * rinv;
@@ -113,37 +142,48 @@ __device__ __forceinline__ void pair_f32(const float4& ta, const float4& tb, con
     Ez = E * z;
   }
   const float a = E + Ez;
-  const float f1 = 1.f - a;
-  const float f0 = 1.f - E;
-  const float c1 = __fmaf_rn(-fp.th1, a, 1.f);
-  const float c2 = __fmaf_rn(-fp.th2, a, 1.f);
-  const float dnx = __fmaf_rn(dz, tb.z, __fmaf_rn(dy, tb.y, dx * tb.x));
-  const float dny = __fmaf_rn(dz, sb.z, __fmaf_rn(dy, sb.y, dx * sb.x));
-  const float nn = __fmaf_rn(tb.z, sb.z, __fmaf_rn(tb.y, sb.y, tb.x * sb.x));
+  const float dnx = __fmaf_rn(dz, tn.z, __fmaf_rn(dy, tn.y, dx * tn.x));
+  const float D = __fmaf_rn(dz, sm.z, __fmaf_rn(dy, sm.y, dx * sm.x));
+  const float Nw = __fmaf_rn(tn.z, sm.z, __fmaf_rn(tn.y, sm.y, tn.x * sm.x));
   const float ri2 = rinv * rinv;
   const float r3 = ri2 * rinv;
-  const float u = dnx * dny * ri2;
-  float v = __fmaf_rn(-3.f, u, nn) * f1;
-  if (kScreened) v = __fmaf_rn(u, Ez * z, v);
-  a1 = __fmaf_rn(dny * c1 * r3, sa.w, a1);
-  a1 = __fmaf_rn(-f0 * rinv, sb.w, a1);
-  a2 = __fmaf_rn(__fmaf_rn(v, sa.w, dnx * c2 * sb.w), r3, a2);
+  const float c1 = __fmaf_rn(-fp.th1, a, 1.f);
+  const float c2 = __fmaf_rn(-fp.th2, a, 1.f);
+  a1 = __fmaf_rn(c1 * D, r3, a1);
+  float t;
+  if (kScreened) {
+    const float f0w = __fmaf_rn(-E, sa.w, sa.w);  // (1 − E) w̃n_j
+    a1 = __fmaf_rn(-f0w, rinv, a1);
+    const float g = __fmaf_rn(Ez, z, __fmaf_rn(3.f, a, -3.f));
+    t = __fmaf_rn(-a, Nw, Nw);
+    t = __fmaf_rn(c2 * dnx, sa.w, t);
+    t = __fmaf_rn(dnx * D * ri2, g, t);
+  } else {  // κ = 0: E = a = 1 and z = 0, so only the θ terms remain
+    t = c2 * dnx * sa.w;
+  }
+  a2 = __fmaf_rn(t, r3, a2);
 }
 
 // Targets [t0, t0 + kBlk·TPL) against sources [j0, j1) of the same record arrays; per-tile
 // FP32 partial sums flushed into FP64. out1/out2 receive σ·S1 and σ²·S2 for each live target
 // (index relative to t0). Every thread of the block must call it (it synchronizes).
+// box: bounding boxes of the record groups (k_group_box); full source tiles whose box is
+// farther than √far2 from the target block's box skip the near-pair predicate.
 template <int kBlk, int TILE, int TPL, bool kScreened>
-__device__ __forceinline__ void far_tile_loop(const float4* __restrict__ A, const float4* __restrict__ B, int t0,
-                                              int t_end, int j0, int j1, const F32Params& fp, double sig1, double sig2,
-                                              float4* sA, float4* sB, double* __restrict__ out1,
+__device__ __forceinline__ void far_tile_loop(const float4* __restrict__ A, const float4* __restrict__ M,
+                                              const float4* __restrict__ N, const float4* __restrict__ box, int t0,
+                                              int t_end, int j0, int j1, const F32Params& fp, double sig1,
+                                              double sig2, float4* sA, float4* sM, double* __restrict__ out1,
                                               double* __restrict__ out2) {
-  float4 ta[TPL], tb[TPL];
+  static_assert(TILE % kGroup == 0 && (kBlk * TPL) % kGroup == 0, "tiles are whole groups");
+  float4 tlo, thi;
+  box_union(box, t0 / kGroup, min(t0 + kBlk * TPL, t_end + kGroup - 1) / kGroup, tlo, thi);
+  float4 ta[TPL], tn[TPL];
 #pragma unroll
   for (int t = 0; t < TPL; ++t) {
     const int i = t0 + t * kBlk + (int)threadIdx.x;
     ta[t] = i < t_end ? A[i] : make_float4(0.f, 0.f, 0.f, 0.f);
-    tb[t] = i < t_end ? B[i] : make_float4(0.f, 0.f, 1.f, 0.f);
+    tn[t] = i < t_end ? N[i] : make_float4(0.f, 0.f, 1.f, 0.f);
   }
   double acc1[TPL], acc2[TPL];
 #pragma unroll
@@ -153,21 +193,38 @@ __device__ __forceinline__ void far_tile_loop(const float4* __restrict__ A, cons
       const int j = base + q;
       if (j < j1) {
         sA[q] = A[j];
-        sB[q] = B[j];
+        sM[q] = M[j];
       } else {  // padding: zero weights, every value they meet is finite
         sA[q] = make_float4(0.f, 0.f, 0.f, 0.f);
-        sB[q] = make_float4(0.f, 0.f, 1.f, 0.f);
+        sM[q] = make_float4(0.f, 0.f, 0.f, 0.f);
       }
     }
+    // block-uniform: the tile is full and its box is clear of the target block's box
+    int clear = 0;
+    if (base + TILE <= j1) {
+      float4 slo, shi;
+      box_union(box, base / kGroup, (base + TILE) / kGroup, slo, shi);
+      clear = box_gap2(tlo, thi, slo, shi) >= fp.far2;
+    }
+    clear = __builtin_amdgcn_readfirstlane(clear);
     __syncthreads();
     float a1[TPL], a2[TPL];
 #pragma unroll
     for (int t = 0; t < TPL; ++t) a1[t] = a2[t] = 0.f;
+    if (clear) {
 #pragma unroll 4
-    for (int q = 0; q < TILE; ++q) {
-      const float4 sa = sA[q], sb = sB[q];
+      for (int q = 0; q < TILE; ++q) {
+        const float4 sa = sA[q], sm = sM[q];
 #pragma unroll
-      for (int t = 0; t < TPL; ++t) pair_f32<kScreened>(ta[t], tb[t], sa, sb, fp, a1[t], a2[t]);
+        for (int t = 0; t < TPL; ++t) pair_f32<kScreened, false>(ta[t], tn[t], sa, sm, fp, a1[t], a2[t]);
+      }
+    } else {
+#pragma unroll 4
+      for (int q = 0; q < TILE; ++q) {
+        const float4 sa = sA[q], sm = sM[q];
+#pragma unroll
+        for (int t = 0; t < TPL; ++t) pair_f32<kScreened, true>(ta[t], tn[t], sa, sm, fp, a1[t], a2[t]);
+      }
     }
 #pragma unroll
     for (int t = 0; t < TPL; ++t) {
@@ -271,32 +328,65 @@ static __global__ void __attribute__((unused)) __launch_bounds__(kBlock) k_reduc
   y[e] = (e < n ? lam1 : lam2) * p[e] + s;
 }
 
-// FP32 records (see F32Params): A = (σ(x−c), σ·s_j·ψ_j), B = (n, s_j·ψn_j), s_j = h³ω_j/(4π).
-// With p == nullptr only the geometry is written (weights zero).
+// FP32 records of a band (layout above); with p == nullptr only the geometry is written
+// (weights zero).
 static __global__ void __attribute__((unused)) __launch_bounds__(kBlock) k_pack_f32(int n, BandDev b, const double* __restrict__ w,
                                                             const double* __restrict__ p, double scale, double cx,
                                                             double cy, double cz, double sigma,
-                                                            float4* __restrict__ A, float4* __restrict__ B) {
+                                                            float4* __restrict__ A, float4* __restrict__ M,
+                                                            float4* __restrict__ N) {
   int j = blockIdx.x * kBlock + threadIdx.x;
   if (j >= n) return;
-  double s = scale * w[j];
-  double w1 = p ? s * p[j] : 0.0, w2 = p ? s * p[n + j] : 0.0;
+  const double s = scale * w[j];
+  const double w1 = p ? sigma * s * p[j] : 0.0, w2 = p ? s * p[n + j] : 0.0;
   A[j] = make_float4((float)(sigma * (b.px[j] - cx)), (float)(sigma * (b.py[j] - cy)), (float)(sigma * (b.pz[j] - cz)),
-                     (float)(sigma * w1));
-  B[j] = make_float4((float)b.nx[j], (float)b.ny[j], (float)b.nz[j], (float)w2);
+                     (float)w2);
+  M[j] = make_float4((float)(w1 * b.nx[j]), (float)(w1 * b.ny[j]), (float)(w1 * b.nz[j]), 0.f);
+  N[j] = make_float4((float)b.nx[j], (float)b.ny[j], (float)b.nz[j], 0.f);
+}
+
+// Bounding box of each aligned group of kGroup records (one block per group):
+// box[2g] = (lo, 0), box[2g + 1] = (hi, 0) over the group's live records.
+static __global__ void __attribute__((unused)) __launch_bounds__(kGroup) k_group_box(int n, const float4* __restrict__ A,
+                                                                  float4* __restrict__ box) {
+  __shared__ float s[6][kGroup];
+  const int i = blockIdx.x * kGroup + threadIdx.x;
+  float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+  if (i < n) {
+    const float4 a = A[i];
+    v[0] = v[3] = a.x;
+    v[1] = v[4] = a.y;
+    v[2] = v[5] = a.z;
+  }
+  for (int q = 0; q < 6; ++q) s[q][threadIdx.x] = v[q];
+  __syncthreads();
+  for (int off = kGroup / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off)
+      for (int q = 0; q < 6; ++q)
+        s[q][threadIdx.x] = q < 3 ? fminf(s[q][threadIdx.x], s[q][threadIdx.x + off])
+                                  : fmaxf(s[q][threadIdx.x], s[q][threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    box[2 * blockIdx.x] = make_float4(s[0][0], s[1][0], s[2][0], 0.f);
+    box[2 * blockIdx.x + 1] = make_float4(s[3][0], s[4][0], s[5][0], 0.f);
+  }
 }
 
 // FP32 far field of one band: block (x: kBlock·TPL targets, y: source chunk).
 template <int TILE, int TPL, bool kScreened>
-static __global__ void __attribute__((unused)) __launch_bounds__(kBlock) k_p2p_f32(const float4* __restrict__ A, const float4* __restrict__ B,
-                                                           int n, int chunk, F32Params fp, double sig1, double sig2,
+static __global__ void __attribute__((unused)) __launch_bounds__(kBlock) k_p2p_f32(const float4* __restrict__ A, const float4* __restrict__ M,
+                                                           const float4* __restrict__ N,
+                                                           const float4* __restrict__ box, int n, int chunk,
+                                                           F32Params fp, double sig1, double sig2,
                                                            double* __restrict__ partial) {
-  __shared__ float4 sA[TILE], sB[TILE];
+  __shared__ float4 sA[TILE], sM[TILE];
   const int t0 = blockIdx.x * kBlock * TPL;
   const int j0 = blockIdx.y * chunk;
   const int j1 = min(n, j0 + chunk);
   double* out = partial + (size_t)blockIdx.y * 2 * n;
-  far_tile_loop<kBlock, TILE, TPL, kScreened>(A, B, t0, n, j0, j1, fp, sig1, sig2, sA, sB, out + t0, out + n + t0);
+  far_tile_loop<kBlock, TILE, TPL, kScreened>(A, M, N, box, t0, n, j0, j1, fp, sig1, sig2, sA, sM, out + t0,
+                                              out + n + t0);
 }
 
 // ----------------------------------------------------------------- near field (cell list)

@@ -15,6 +15,11 @@
 namespace pb {
 
 constexpr double kPi = 3.14159265358979323846;
+// Mixed-precision refinement: an inner solve on the FP32-far-field operator is asked for no
+// more than this reduction of its own right-hand side. Below about 1e-9 relative, the FP32
+// rounding of the far field dominates the residual and GMRES stops making progress; the
+// outer step with the FP64 residual supplies the remaining accuracy.
+constexpr double kInnerEta = 1e-7;
 
 // Parameters derived once per call from pb_params, in the form the kernels consume.
 struct Derived {
@@ -48,8 +53,10 @@ struct MixedPlan {
   double cell = 0;
   int ncx = 0, ncy = 0, ncz = 0;
   int64_t nnz = 0;                // near-field pairs
-  float4* A = nullptr;            // FP32 records (x, ψ weight), (n, ψn weight)
-  float4* B = nullptr;
+  float4* A = nullptr;            // FP32 records: (σ(x − c), ψn weight)
+  float4* M = nullptr;            //               σ·(ψ weight)·n
+  float4* N = nullptr;            //               n (the target side's normal)
+  float4* box = nullptr;          // bounding boxes of groups of 256 records (lo, hi)
   int64_t* row = nullptr;         // near-field CSR
   int* col = nullptr;
   double4* coef = nullptr;

@@ -6,9 +6,11 @@
 // residual estimate are updated. Dot products are two-stage fixed-order reductions.
 //
 // Initial guess: Λ⁻¹g by default, the paper's "solution of the diagonal part" with D = 0.
-// Mixed precision: iterative refinement. Each outer step forms the true FP64 residual
-// r = g − A₆₄x and solves A_mixed d = r by GMRES to an absolute residual of ½·tol·‖g‖, then
-// x ← x + d; the loop ends when the FP64 residual meets tol.
+// Mixed precision: GMRES on A_mixed x = g from the initial guess, then iterative refinement:
+// form the true FP64 residual r = g − A₆₄x and, while it misses tol, solve A_mixed d = r and
+// set x ← x + d. Each inner solve stops at max(½·tol·‖g‖, η·‖r₀‖), r₀ its initial residual
+// and η = kInnerEta, or when a restart cycle that ended on its residual estimate did not halve
+// the true residual (the estimate has reached the FP32 rounding level).
 #include <chrono>
 #include <cmath>
 #include <functional>
@@ -130,12 +132,14 @@ pb_status norm2(pb_ctx* ctx, Krylov& K, const double* v, double* out) {
   return sync(ctx, "norm");
 }
 
-// Restarted GMRES(m) for A x = b from the given x until ‖b − Ax‖ ≤ tol_abs (estimate, then
-// confirmed with the operator at each restart) or max_iter operator applications.
+// Restarted GMRES(m) for A x = b from the given x until ‖b − Ax‖ ≤ max(tol_abs, rel·‖b − Ax₀‖)
+// (estimate, then confirmed with the operator at each restart) or max_iter operator
+// applications. With rel > 0 (an inexact operator) the solve also ends when a cycle that
+// stopped on its estimate did not halve the true residual.
 // With prec (flexible GMRES, right preconditioning): z_k = prec(v_k), w = A z_k, and the
 // update is x += Z y; the preconditioner may change from step to step (it may be nonlinear).
 pb_status gmres(pb_ctx* ctx, Krylov& K, const OpFn& op, const OpFn* prec, const double* b, double* x, double tol_abs,
-                int max_iter, int* iters, double* res_out) {
+                double rel, int max_iter, int* iters, double* res_out) {
   const int64_t M = K.M;
   const int m = K.m;
   double* V = (double*)workspace(ctx, "kr_V", sizeof(double) * (size_t)M * (m + 1));
@@ -149,9 +153,15 @@ pb_status gmres(pb_ctx* ctx, Krylov& K, const OpFn& op, const OpFn* prec, const 
   k_residual<<<vb, kBlock, 0, ctx->stream>>>(M, b, r);
   double beta = 0.0;
   PB_TRY(norm2(ctx, K, r, &beta));
+  tol_abs = std::fmax(tol_abs, rel * beta);
   int it = 0;
+  bool early = false;  // the last cycle ended on its residual estimate
+  double beta_prev = 0.0;
   for (;;) {
     if (!(beta > tol_abs) || it >= max_iter) break;
+    if (rel > 0.0 && early && beta > 0.5 * beta_prev) break;  // stalled at the operator's rounding level
+    beta_prev = beta;
+    early = false;
     {
       Scope t(ctx, "gmres");
       k_scale<<<vb, kBlock, 0, ctx->stream>>>(M, r, K.hcol + 2 * (m + 1), V);  // norm2 left ‖r‖ there
@@ -204,6 +214,7 @@ pb_status gmres(pb_ctx* ctx, Krylov& K, const OpFn& op, const OpFn* prec, const 
       s[k] = cs[k] * s[k];
       if (std::fabs(s[k + 1]) <= tol_abs || !(hn > 0.0)) {
         ++k;
+        early = true;
         break;
       }
     }
@@ -305,13 +316,22 @@ extern "C" pb_status pb_ibim_solve(pb_ctx* ctx, const pb_band* band, const doubl
     if (opts.precision == PB_FP64) {
       double res = 0.0;
       int it = 0;
-      PB_TRY(gmres(ctx, K, op64, prec, g, p, opts.tol * gnorm, iter_budget, &it, &res));
+      PB_TRY(gmres(ctx, K, op64, prec, g, p, opts.tol * gnorm, 0.0, iter_budget, &it, &res));
       iters += it;
       relres = res / gnorm;
       outer += 1;
       return PB_OK;
     }
     int used = 0, steps = 0;
+    {
+      // first pass straight on A_mixed p = g from the initial guess; the FP64 residual below
+      // then decides whether a correction step is needed
+      int it = 0;
+      double res = 0.0;
+      PB_TRY(gmres(ctx, K, opmx, prec, g, p, 0.5 * opts.tol * gnorm, kInnerEta, iter_budget, &it, &res));
+      used += it;
+      ++steps;
+    }
     for (;;) {
       PB_TRY(op64(p, r));
       k_residual<<<vb, kBlock, 0, ctx->stream>>>(M, g, r);
@@ -322,7 +342,7 @@ extern "C" pb_status pb_ibim_solve(pb_ctx* ctx, const pb_band* band, const doubl
       k_zero<<<vb, kBlock, 0, ctx->stream>>>(M, dx);
       int it = 0;
       double res = 0.0;
-      PB_TRY(gmres(ctx, K, opmx, prec, r, dx, 0.5 * opts.tol * gnorm, iter_budget - used, &it, &res));
+      PB_TRY(gmres(ctx, K, opmx, prec, r, dx, 0.5 * opts.tol * gnorm, kInnerEta, iter_budget - used, &it, &res));
       used += it;
       k_add<<<vb, kBlock, 0, ctx->stream>>>(M, dx, p);
       PB_TRY(launch_ok(ctx, "refine"));
