@@ -11,8 +11,16 @@ time (one pair-interaction = one ordered (target, source) evaluation of the 2×2
 block, n² per operator application).
 
 Extra fields: the dominant kernel's roofline (FP32 pair kernel, HIP-event timed over the
-timed region), GMRES time-to-1e-6 of the mixed path against plain FP64 GMRES on the same
-GPU, and the FP64 CPU oracle timed on the host on a bounded sample.
+timed region), GMRES time-to-1e-6 of the mixed path and of the learned-preconditioned mixed
+path against plain FP64 GMRES on the same GPU, and the FP64 CPU oracle timed on the host
+on a bounded sample.
+
+Other workloads: globule5000 (the same step at 5000 atoms, h = 0.25), batch64 (64
+molecules per step through the batched solve, plain and learned), heldout5000 (time to
+1e-6 on held-out 5000-atom molecules at h = 0.5: FP64, mixed, learned + mixed).
+
+The learned network is the committed weights file (trained by `python -m
+paper_1709_08070_amd.learn`), or one trained in-process with --learned-train N.
 """
 from __future__ import annotations
 
@@ -28,12 +36,18 @@ sys.path.insert(0, ROOT)
 FLOP_PER_PAIR = 61  # algorithmic FP32 FLOPs per pair-interaction (FMA = 2)
 PEAK_FP32 = 157.3e12  # MI355X FP32 vector peak (packed), FLOP/s
 
+METRIC = "BIM pair-interactions/s; GMRES time-to-1e-6 (learned+mixed vs plain FP64)"
+
 WORKLOADS = {
-    # name: (atoms, seed, h); batch64 is 64 globules with atom counts log-uniform over 50-2000
+    # name: (atoms, seed, h); batch64 is 64 globules with atom counts log-uniform over 50-2000;
+    # heldout5000 is 8 globules of 5000 atoms, seeds 200000+i (never used in training)
     "globule500": (500, 500, 0.5),
     "globule5000": (5000, 5000, 0.25),
     "batch64": (None, 64000, 0.5),
+    "heldout5000": (5000, 200000, 0.5),
 }
+
+WEIGHTS = os.path.join(ROOT, "paper_1709_08070_amd", "weights", "learned_h0.5.npz")
 
 
 def log(*a):
@@ -65,6 +79,118 @@ def measured_traffic(kernel: str, workload: str):
     except OSError:
         return None
     return float(kv["traffic_bytes"])
+
+
+def load_net(ctx, args):
+    """(net, record) from --learned-train, else from the weights file; (None, None) if neither."""
+    from paper_1709_08070_amd import pb
+
+    if args.learned_train > 0:
+        from paper_1709_08070_amd import learn
+
+        net = pb.Net(ctx, seed=1)
+        info = learn.train(ctx, net, n_mol=args.learned_train, epochs=args.learned_epochs, log=log)
+        rec = {k: info[k] for k in ("molecules", "epochs", "t_data_s", "t_train_s")}
+        rec["final_loss"] = info["loss"][-1]
+        rec["source"] = "trained in this run"
+        return net, rec
+    path = args.learned_weights
+    if not path or not os.path.exists(path):
+        return None, None
+    net = pb.Net(ctx, seed=1)
+    net.load(path)
+    rec = {"source": os.path.relpath(path, ROOT)}
+    meta = path.rsplit(".", 1)[0] + ".json"
+    if os.path.exists(meta):
+        info = json.load(open(meta))
+        rec.update({k: info.get(k) for k in ("molecules", "epochs", "t_data_s", "t_train_s")})
+        rec["final_loss"] = info["loss"][-1] if info.get("loss") else None
+    return net, rec
+
+
+def timed_solve(ctx, band, at, prm, opts, q, warm=True):
+    """Wall time of one solve from x0 (after one untimed solve that warms the caches and the
+    far-field autotuner); returns (seconds, stats)."""
+    import torch
+
+    from paper_1709_08070_amd import pb
+
+    if warm:
+        pb.pb_ibim_solve(ctx, band, at, prm, opts, q)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    _, st = pb.pb_ibim_solve(ctx, band, at, prm, opts, q)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t1, st
+
+
+def bench_heldout(args):
+    """Time to 1e-6 on held-out 5000-atom globules (h = 0.5): plain FP64 GMRES, mixed
+    GMRES-IR, and mixed with the learned x0 and right preconditioner."""
+    import torch
+
+    from paper_1709_08070_amd import pb, synth
+
+    n_atoms, seed0, h = WORKLOADS["heldout5000"]
+    ctx = pb.Context(0)
+    net, rec = load_net(ctx, args)
+    if net is None:
+        log("heldout5000 needs a network: the weights file or --learned-train N")
+        sys.exit(2)
+    prm = pb.params(h, ls_mode=pb.PB_LS_SES)
+    n_mol = max(1, min(args.steps, 8))
+    rows, pairs, t_learned = [], 0.0, 0.0
+    for i in range(n_mol):
+        atoms = synth.globule(n_atoms, seed0 + i)
+        grid = pb.pb_grid_for_atoms(atoms, prm)
+        at = torch.tensor(atoms, dtype=torch.float64, device="cuda")
+        phi = pb.pb_build_levelset(ctx, at, prm, grid)
+        band = pb.pb_narrowband_compact(ctx, grid, phi, prm)
+        q = torch.zeros(2 * band.n, dtype=torch.float64, device="cuda")
+        row = {"seed": seed0 + i, "band_nodes": band.n}
+        for name, o in (("fp64", pb.solve_opts(tol=args.tol, precision=pb.PB_FP64)),
+                        ("mixed", pb.solve_opts(tol=args.tol, precision=pb.PB_MIXED)),
+                        ("learned_mixed", pb.solve_opts(tol=args.tol, precision=pb.PB_MIXED, x0=pb.PB_X0_LEARNED,
+                                                        precond=pb.PB_PRECOND_LEARNED, nn=net.handle))):
+            t, st = timed_solve(ctx, band, at, prm, o, q)
+            row[name + "_s"] = t
+            row[name + "_iters"] = st.iters
+            row[name + "_relres"] = st.true_relres
+            if name == "learned_mixed":
+                row["learned_fallback"] = st.fallback_used
+                pairs += st.pairs
+                t_learned += t
+            row[name + "_g_pol_kcal"] = pb.pb_solvation_energy(ctx, band, at, prm, q).g_pol_kcal
+        log(f"held-out {i}: n={band.n} fp64 {row['fp64_s']:.2f}s/{row['fp64_iters']} it, mixed "
+            f"{row['mixed_s']:.2f}s/{row['mixed_iters']} it, learned {row['learned_mixed_s']:.2f}s/"
+            f"{row['learned_mixed_iters']} it (fallback {row['learned_fallback']})")
+        rows.append(row)
+
+    def mean(k):
+        return sum(r[k] for r in rows) / len(rows)
+
+    ttsol = {k: mean(k) for k in ("fp64_s", "mixed_s", "learned_mixed_s", "fp64_iters", "mixed_iters",
+                                  "learned_mixed_iters")}
+    ttsol["speedup_mixed_vs_fp64"] = ttsol["fp64_s"] / ttsol["mixed_s"]
+    ttsol["speedup_learned_mixed_vs_fp64"] = ttsol["fp64_s"] / ttsol["learned_mixed_s"]
+    ttsol["speedup_learned_mixed_vs_mixed"] = ttsol["mixed_s"] / ttsol["learned_mixed_s"]
+    ttsol["max_energy_rel_diff_learned_vs_fp64"] = max(
+        abs(r["learned_mixed_g_pol_kcal"] / r["fp64_g_pol_kcal"] - 1) for r in rows)
+    ttsol["fallbacks"] = sum(r["learned_fallback"] for r in rows)
+    ttsol["per_molecule"] = rows
+    ttsol["network"] = rec
+    out = {
+        "metric": METRIC, "value": pairs / t_learned, "unit": "pair-interactions/s", "n_gpus": 1,
+        "steps": n_mol, "warmup": 1, "ms_per_step": 1e3 * t_learned / n_mol, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "accumulate": "f64", "data": "synthetic",
+        "config": {"workload": f"heldout5000: {n_mol} held-out synthetic globules of {n_atoms} atoms (seeds "
+                               f"{seed0}+i), h={h} A, SES; time to {args.tol:g} of FP64 GMRES, mixed GMRES-IR and "
+                               "learned-preconditioned mixed GMRES-IR (value: pair rate of the learned solves)",
+                   "parallelism": "single GPU"},
+        "time_to_tol": ttsol, "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
 
 
 def bench_batch(args):
@@ -122,8 +248,27 @@ def bench_batch(args):
             f"max relres={max(st.true_relres for st in stats):.2e}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    learned = None
+    net, rec = load_net(ctx, args)
+    if net is not None:
+        lopts = pb.solve_opts(tol=args.tol, precision=pb.PB_MIXED, x0=pb.PB_X0_LEARNED,
+                              precond=pb.PB_PRECOND_LEARNED, nn=net.handle)
+        lps = [torch.zeros_like(p) for p in ps]
+        pb.pb_ibim_solve_batched(ctx, bands, ats, prm, lopts, lps)  # warm
+        torch.cuda.synchronize()
+        _, lstats, lbst = pb.pb_ibim_solve_batched(ctx, bands, ats, prm, lopts, lps)
+        rel = max(abs(pb.pb_solvation_energy(ctx, b, at, prm, q).g_pol / pb.pb_solvation_energy(ctx, b, at, prm, p).g_pol
+                      - 1) for b, at, q, p in zip(bands, ats, lps, ps))
+        learned = {"solve_s": lbst.t_total_s, "p50_solve_s": lbst.t_p50_s, "p99_solve_s": lbst.t_p99_s,
+                   "graph_replays": lbst.graph_replays, "outer": lbst.outer,
+                   "fallbacks": sum(st.fallback_used for st in lstats),
+                   "max_relres": max(st.true_relres for st in lstats),
+                   "max_energy_rel_diff_vs_plain": rel,
+                   "speedup_vs_plain_batched": (sum(tsolve) / len(tsolve)) / lbst.t_total_s, "network": rec}
+        log(f"learned batch: replays={lbst.graph_replays} solve={lbst.t_total_s:.3f}s p50={lbst.t_p50_s:.3f}s "
+            f"p99={lbst.t_p99_s:.3f}s fallbacks={learned['fallbacks']} energy diff {rel:.2e}")
     out = {
-        "metric": "BIM pair-interactions/s", "value": pairs / elapsed, "unit": "pair-interactions/s", "n_gpus": 1,
+        "metric": METRIC, "value": pairs / elapsed, "unit": "pair-interactions/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed * 1e3 / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "accumulate": "f64",
         "data": "synthetic",
@@ -133,7 +278,8 @@ def bench_batch(args):
                    "parallelism": "single GPU"},
         "batch": {"solve_s_mean": sum(tsolve) / len(tsolve), "p50_solve_s": sum(p50) / len(p50),
                   "p99_solve_s": sum(p99) / len(p99), "graph_replays": bst.graph_replays,
-                  "far_tile": bst.far_tile, "far_targets_per_lane": bst.far_tpl, "work_items": bst.n_items},
+                  "far_tile": bst.far_tile, "far_targets_per_lane": bst.far_tpl, "work_items": bst.n_items,
+                  "learned": learned},
         "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
@@ -153,6 +299,8 @@ def main():
                     help="train the learned preconditioner on N generated molecules (200-1500 atoms, h=0.5) and "
                          "add its time-to-tolerance on the (held-out) workload molecule")
     ap.add_argument("--learned-epochs", type=int, default=2)
+    ap.add_argument("--learned-weights", default=WEIGHTS,
+                    help="weights file of the learned preconditioner (default: the committed one, if present)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of this many MiB (a reference for HBM counters)")
     args = ap.parse_args()
@@ -177,6 +325,8 @@ def main():
 
     if args.workload == "batch64":
         return bench_batch(args)
+    if args.workload == "heldout5000":
+        return bench_heldout(args)
 
     n_atoms, seed, h = WORKLOADS[args.workload]
     atoms = synth.globule(n_atoms, seed)
@@ -223,9 +373,11 @@ def main():
 
     per_launch_s = f32_ms * 1e-3 / max(f32_n, 1)
     achieved = FLOP_PER_PAIR * float(n) * float(n) / per_launch_s if f32_n else 0.0
-    roofline = {"kernel": "k_p2p_f32", "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
+    cfg = ctx.far_kernel(n)
+    kname = "k_p2p_f32_sym" if cfg == 4 else "k_p2p_f32<%d, %d>" % ((256, 1), (512, 1), (256, 2), (512, 2))[cfg]
+    roofline = {"kernel": kname, "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP32,
-                "traffic": measured_traffic("k_p2p_f32", args.workload),
+                "traffic": measured_traffic("k_p2p_f32_sym" if cfg == 4 else "k_p2p_f32", args.workload),
                 "avg_launch_ms": per_launch_s * 1e3, "launches": f32_n,
                 "pairs_per_s": float(n) * float(n) / per_launch_s if f32_n else 0.0,
                 "p2p_f64_avg_ms": f64_ms / max(f64_n, 1), "near_f64_avg_ms": near_ms / max(near_n, 1)}
@@ -236,39 +388,37 @@ def main():
         for name, prec in (("fp64", pb.PB_FP64), ("mixed", pb.PB_MIXED)):
             q = torch.zeros_like(p)
             o = pb.solve_opts(tol=args.tol, precision=prec)
+            log(f"time to {args.tol:g}: {name} solve (warm-up)")
             pb.pb_ibim_solve(ctx, band, at, prm, o, q)  # warm
             torch.cuda.synchronize()
+            log(f"time to {args.tol:g}: {name} solve (timed)")
             t1 = time.perf_counter()
             _, st2 = pb.pb_ibim_solve(ctx, band, at, prm, o, q)
             torch.cuda.synchronize()
             ttsol[name + "_s"] = time.perf_counter() - t1
+            log(f"time to {args.tol:g}: {name} {ttsol[name + '_s']:.3f} s, {st2.iters} iterations")
             ttsol[name + "_iters"] = st2.iters
             ttsol[name + "_relres"] = st2.true_relres
             ttsol[name + "_g_pol_kcal"] = pb.pb_solvation_energy(ctx, band, at, prm, q).g_pol_kcal
         ttsol["speedup_mixed_vs_fp64"] = ttsol["fp64_s"] / ttsol["mixed_s"]
         ttsol["energy_rel_diff_mixed_vs_fp64"] = abs(ttsol["mixed_g_pol_kcal"] / ttsol["fp64_g_pol_kcal"] - 1)
         ttsol["learned_mixed_s"] = None
-        if args.learned_train > 0:
-            from paper_1709_08070_amd import learn
-
-            net = pb.Net(ctx, seed=1)
-            info = learn.train(ctx, net, n_mol=args.learned_train, epochs=args.learned_epochs, log=log)
+        net, rec = load_net(ctx, args)
+        if net is not None:
             o = pb.solve_opts(tol=args.tol, precision=pb.PB_MIXED, x0=pb.PB_X0_LEARNED,
                               precond=pb.PB_PRECOND_LEARNED, nn=net.handle)
             q = torch.zeros_like(p)
-            pb.pb_ibim_solve(ctx, band, at, prm, o, q)  # warm
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            _, st3 = pb.pb_ibim_solve(ctx, band, at, prm, o, q)
-            torch.cuda.synchronize()
-            ttsol["learned_mixed_s"] = time.perf_counter() - t1
+            log(f"time to {args.tol:g}: learned mixed solve")
+            t3, st3 = timed_solve(ctx, band, at, prm, o, q)
+            ttsol["learned_mixed_s"] = t3
             ttsol["learned_mixed_iters"] = st3.iters
             ttsol["learned_mixed_relres"] = st3.true_relres
             ttsol["learned_fallback"] = st3.fallback_used
             ttsol["learned_g_pol_kcal"] = pb.pb_solvation_energy(ctx, band, at, prm, q).g_pol_kcal
-            ttsol["speedup_learned_mixed_vs_fp64"] = ttsol["fp64_s"] / ttsol["learned_mixed_s"]
-            ttsol["learned_training"] = {k: info[k] for k in ("molecules", "epochs", "t_data_s", "t_train_s")}
-            ttsol["learned_training"]["final_loss"] = info["loss"][-1]
+            ttsol["speedup_learned_mixed_vs_fp64"] = ttsol["fp64_s"] / t3
+            ttsol["speedup_learned_mixed_vs_mixed"] = ttsol["mixed_s"] / t3
+            ttsol["network"] = rec
+            log(f"time to {args.tol:g}: learned mixed {t3:.3f} s, {st3.iters} iterations")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -291,7 +441,7 @@ def main():
                          f"{t_cpu:.1f} s"}
 
     out = {
-        "metric": "BIM pair-interactions/s", "value": value, "unit": "pair-interactions/s", "n_gpus": 1,
+        "metric": METRIC, "value": value, "unit": "pair-interactions/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed * 1e3 / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "accumulate": "f64", "data": "synthetic",

@@ -143,7 +143,8 @@ pb_status pb_grid_for_atoms(const double* atoms_host, int n_atoms, const pb_para
    Hamiltonian, WENO5, zero-Neumann ghosts), cavity removal (flood fill from the grid
    boundary through φ > 0; unreached nodes within ε + h of a cavity set to −ε), then
    reinitialization φ_t + sgn_h(φ0)(|∇φ| − 1) = 0 (eqs. reinit, signum).
-   atoms: device, n_atoms × 5. phi: device, nx·ny·nz doubles. */
+   atoms: device, n_atoms × 5. phi: device, nx·ny·nz doubles. PB_EINVAL if an axis has
+   fewer than 7 nodes, grid->h differs from prm->h, or the grid has 2^31 nodes or more. */
 pb_status pb_build_levelset(pb_ctx* ctx, const double* atoms, int n_atoms, const pb_params* prm,
                             const pb_grid* grid, double* phi);
 
@@ -162,7 +163,14 @@ pb_status pb_ibim_rhs(pb_ctx* ctx, const pb_band* band, const double* atoms, int
 
 /* y = Λp + KWp (eq. final-lin-sys), the four regularized kernels of eq. IBIM-PBE and the
    regularization subsection, h³ and ω folded in. precision PB_FP64 or PB_MIXED.
-   p, y: device, 2n; they must not overlap. */
+   p, y: device, 2n; they must not overlap.
+   PB_MIXED: FP32 far field + FP64 near field (every pair closer than r_c, the regularized
+   ones included). The far-field kernel is chosen once per band size (per batch shape in
+   pb_ibim_solve_batched) by timing the candidates; the environment variable PB_FAR_CFG=k
+   fixes it instead: k = 0..3 the one-directional kernel with (sources per LDS tile, targets
+   per lane) = (256, 1), (512, 1), (256, 2), (512, 2); k = 4 the symmetric kernel (each
+   unordered pair evaluated once for both directions). All give the same operator up to
+   FP32 rounding; each is bitwise reproducible from run to run. */
 pb_status pb_ibim_matvec(pb_ctx* ctx, const pb_band* band, const pb_params* prm, int precision, const double* p,
                          double* y);
 
@@ -192,7 +200,9 @@ typedef struct {
   int far_tpl;         /* far-field targets per lane chosen by the autotuner */
   int n_items;         /* work items of the persistent far-field launch */
   int outer;           /* refinement steps */
-  int reserved;
+  int far_symmetric;   /* 1 if the autotuner chose the symmetric far-field kernel (each
+                          unordered pair once, both directions; far_tile/far_tpl then give
+                          its 512-node sub-block and 2 targets per lane) */
 } pb_batch_stats;
 
 /* Solves n_mol independent molecules (section "Fast linear solvers" for each) in one batch,
@@ -204,7 +214,14 @@ typedef struct {
    n_mol device pointers (n_atoms[m] × 5). p: host array of n_mol device pointers (2n_m
    doubles each), input when opts->x0 == PB_X0_USER, output always. stats: host, n_mol
    entries, may be NULL; bstats: host, may be NULL. PB_ENOCONV if any molecule misses the
-   tolerance (all results still written). */
+   tolerance (all results still written).
+   Learned path (opts->x0 == PB_X0_LEARNED and/or opts->precond == PB_PRECOND_LEARNED,
+   opts->nn set, every band's phi present): the network runs over all molecules at once;
+   as right preconditioner inside the captured step (flexible GMRES), as x0 = M(g). A
+   molecule that misses the tolerance on the learned path is solved again without the
+   network from its last iterate (from Λ⁻¹g if that is not finite); stats[m].fallback_used
+   reports it. PB_EINVAL: precision other than PB_MIXED, the literal tangent metric, an
+   unknown x0 or preconditioner mode, a learned mode without opts->nn or a band's phi. */
 pb_status pb_ibim_solve_batched(pb_ctx* ctx, int n_mol, const pb_band* bands, const double* const* atoms,
                                 const int* n_atoms, const pb_params* prm, const pb_solve_opts* opts,
                                 double* const* p, pb_solve_stats* stats, pb_batch_stats* bstats);
@@ -246,6 +263,12 @@ pb_status pb_nn_geometry(pb_ctx* ctx, const pb_band* band, int* nbr_host, float*
    "energy", "nn". */
 pb_status pb_set_timing(pb_ctx* ctx, int enable);
 pb_status pb_kernel_time(pb_ctx* ctx, const char* name, double* total_ms, int64_t* launches);
+
+/* The far-field kernel the mixed operator uses for bands of n nodes on this context (the
+   autotuner's choice or PB_FAR_CFG; see pb_ibim_matvec): *cfg = 0..3 the one-directional
+   kernel, 4 the symmetric one. PB_EINVAL if no mixed operator was applied to a band of that
+   size yet. */
+pb_status pb_far_kernel(pb_ctx* ctx, int64_t n, int* cfg);
 
 #ifdef __cplusplus
 }

@@ -5,7 +5,9 @@
 // first (LPT); each block strides through it, so molecules of very different n share the
 // CUs evenly. Items of molecules that have converged are skipped. The FP64 near field of
 // each molecule is its own CSR block matrix; one SpMV launch and one reduce launch cover all
-// molecules. The far-field tile shape is picked per batch by the autotuner (timed once).
+// molecules. The far-field kernel (one of the tile shapes of the one-directional kernel, or
+// the symmetric kernel over (molecule, chunk, chunk) items) is picked per batch by the
+// autotuner (each candidate timed once).
 //
 // Krylov: every molecule runs its own GMRES (FP64 Arnoldi with CGS2, Givens rotations on the
 // device, one thread per molecule). The vectors of all molecules are concatenated, molecule m
@@ -18,14 +20,22 @@
 // Mixed precision as in the single solve: each outer step forms the FP64 residual with the
 // persistent FP64 operator and solves the correction with the mixed operator, to
 // max(½·tol·‖g‖, η·‖r‖) or until a restart cycle stalls at the FP32 rounding level.
+//
+// Learned path: the network runs over all molecules at once (their nodes concatenated,
+// neighbour lists offset to global indices). As right preconditioner it is applied inside
+// the captured Arnoldi step (flexible GMRES: z_k = M(v_k), w = A z_k, x += Z y); as initial
+// guess x0 = M(g). Molecules that miss the tolerance on the learned path are solved again
+// from their last iterate (from Λ⁻¹g if it is not finite) without the network.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <vector>
 
 #include "pair_kernels.hpp"
+#include "sym_kernels.hpp"
 
 namespace pb {
 namespace {
@@ -36,8 +46,10 @@ struct MolDev {
   int off;          // first node in the concatenated node index
   int n;            // band nodes
   int S32, S64;     // source chunks of the FP32 / FP64 far field
+  int Ssym, nsub;   // chunks and sub-blocks per chunk of the symmetric FP32 far field
   int64_t poff32;   // offset of the molecule's FP32-path partial sums (doubles)
   int64_t poff64;   // offset of the FP64-path partial sums
+  int64_t poffsym;  // offset of the symmetric-kernel partial sums
   double cx, cy, cz;
   BandDev band;
   const double* w;
@@ -104,6 +116,22 @@ static __global__ void __launch_bounds__(kBlock) k_far32_batch(const Item* __res
   }
 }
 
+// Symmetric far field of every active molecule: items (molecule, Ic, Jc), persistent.
+template <bool kScreened>
+static __global__ void __launch_bounds__(kBlock) k_far32_sym_batch(const Item* __restrict__ items, int n_items,
+                                                                   const MolDev* __restrict__ mols,
+                                                                   const int* __restrict__ active, F32Params fp,
+                                                                   double sig1, double sig2,
+                                                                   double* __restrict__ partial) {
+  __shared__ SymShared sh;
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const Item w = items[it];
+    if (!active[w.mol]) continue;
+    const MolDev& m = mols[w.mol];
+    sym_item<kScreened>(m.A, m.M, m.N, m.box, m.n, w.tb, w.ch, m.nsub, fp, sig1, sig2, partial + m.poffsym, sh);
+  }
+}
+
 static __global__ void __launch_bounds__(kBlock) k_weights_batch(int ntot, const int* __restrict__ mol_of,
                                                                  const MolDev* __restrict__ mols,
                                                                  const double* __restrict__ x, double scale,
@@ -137,11 +165,14 @@ static __global__ void __launch_bounds__(kBlock) k_far64_batch(const Item* __res
   }
 }
 
+// Layout of the far-field partial sums read by k_reduce_batch.
+constexpr int kModeTiled = 0, kModeF64 = 1, kModeSym = 2;
+
 // y = Λx + Σ chunks (+ near), per molecule; x and y at step *kptr / *kptr + 1 of a basis
 // when kptr is given.
 static __global__ void __launch_bounds__(kBlock) k_reduce_batch(int ntot, const int* __restrict__ mol_of,
                                                                 const MolDev* __restrict__ mols,
-                                                                const int* __restrict__ active, int use64,
+                                                                const int* __restrict__ active, int mode,
                                                                 const double* __restrict__ partial,
                                                                 const double* __restrict__ x, double* __restrict__ y,
                                                                 const int* __restrict__ kptr, int kmax, int64_t ldv,
@@ -156,8 +187,9 @@ static __global__ void __launch_bounds__(kBlock) k_reduce_batch(int ntot, const 
   const double* xv = x + k * ldv;
   double* yv = y + (kptr ? (k + 1) * ldv : 0);
   const int l = g - m.off;
-  const int S = use64 ? m.S64 : m.S32;
-  const double* part = partial + (use64 ? m.poff64 : m.poff32);
+  const bool use64 = mode == kModeF64;
+  const int S = use64 ? m.S64 : mode == kModeSym ? m.Ssym : m.S32;
+  const double* part = partial + (use64 ? m.poff64 : mode == kModeSym ? m.poffsym : m.poff32);
   double s1 = 0.0, s2 = 0.0;
   for (int c = 0; c < S; ++c) {
     s1 += part[(int64_t)c * 2 * m.n + l];
@@ -445,6 +477,22 @@ static __global__ void __launch_bounds__(kBlock) k_diag_batch(int ntot, const in
   x[e2] = g[e2] / lam2;
 }
 
+// x = Λ⁻¹g over molecules whose last residual is not finite (before the plain-GMRES rerun).
+static __global__ void __launch_bounds__(kBlock) k_reset_nonfinite(int ntot, const int* __restrict__ mol_of,
+                                                                   const MolDev* __restrict__ mols,
+                                                                   const double* __restrict__ relres,
+                                                                   const double* __restrict__ g, double lam1,
+                                                                   double lam2, double* __restrict__ x) {
+  const int gi = blockIdx.x * kBlock + threadIdx.x;
+  if (gi >= ntot) return;
+  const int mi = mol_of[gi];
+  if (isfinite(relres[mi])) return;
+  const MolDev& m = mols[mi];
+  const int64_t e1 = 2 * (int64_t)m.off + (gi - m.off), e2 = e1 + m.n;
+  x[e1] = g[e1] / lam1;
+  x[e2] = g[e2] / lam2;
+}
+
 // x += d over molecules in sel
 static __global__ void __launch_bounds__(kBlock) k_add_batch(int nseg, Segs sg, const int* __restrict__ sel,
                                                              const double* __restrict__ d, double* __restrict__ x) {
@@ -464,7 +512,7 @@ static __global__ void k_outer_check(int n_mol, const double* __restrict__ rn, c
   const double rr = rn[mol] / gn[mol];
   relres[mol] = rr;
   tol_abs[mol] = fmax(0.5 * tol * gn[mol], eta * rn[mol]);
-  if (!(rr > tol)) {
+  if (rr <= tol) {  // a non-finite residual stays selected
     sel[mol] = 0;
     st[mol].t_done = st[mol].t_inner ? st[mol].t_inner : wall_clock64();
   } else {
@@ -481,7 +529,9 @@ static __global__ void k_stamp(unsigned long long* t) { *t = wall_clock64(); }
 
 namespace {
 
-constexpr int kNumCfgB = 4;
+constexpr int kNumTiledB = 4;           // tile shapes of the one-directional kernel
+constexpr int kSymB = kNumTiledB;        // the symmetric kernel
+constexpr int kNumCfgB = kNumTiledB + 1;
 constexpr int kChunk32 = 4096, kChunk64 = 2048;
 
 struct Batch {
@@ -505,6 +555,9 @@ struct Batch {
   double* dpart = nullptr;  // per-block partial dots, nseg × (m+1)
   // Krylov
   double* V = nullptr;
+  double* Z = nullptr;  // preconditioned basis (flexible GMRES), learned path only
+  const NNBatch* nb = nullptr;
+  const pb_nn* net = nullptr;
   double* H = nullptr;
   double* cs = nullptr;
   double* sn = nullptr;
@@ -529,10 +582,19 @@ void launch_far32_t(Batch& B, int c, const int* active, const F32Params& fp, dou
                                                                        active, fp, sig1, sig2, B.partial);
 }
 
-constexpr int kCfgTile[kNumCfgB] = {256, 512, 256, 512};
-constexpr int kCfgTpl[kNumCfgB] = {1, 1, 2, 2};
+constexpr int kCfgTile[kNumCfgB] = {256, 512, 256, 512, kSymSub};
+constexpr int kCfgTpl[kNumCfgB] = {1, 1, 2, 2, 2};
 
 void launch_far32(Batch& B, int c, const int* active, const F32Params& fp, double sig1, double sig2) {
+  if (c == kSymB) {
+    if (B.d.kappa > 0.0)
+      k_far32_sym_batch<true><<<B.grid32[c], kBlock, 0, B.st>>>(B.items32[c], B.n_items32[c], B.mols, active, fp,
+                                                                 sig1, sig2, B.partial);
+    else
+      k_far32_sym_batch<false><<<B.grid32[c], kBlock, 0, B.st>>>(B.items32[c], B.n_items32[c], B.mols, active, fp,
+                                                                  sig1, sig2, B.partial);
+    return;
+  }
   switch (c) {
     case 0: launch_far32_t<256, 1>(B, c, active, fp, sig1, sig2); break;
     case 1: launch_far32_t<512, 1>(B, c, active, fp, sig1, sig2); break;
@@ -550,6 +612,12 @@ int grid_for_t(pb_ctx* ctx, bool screened) {
 }
 
 int grid_for(pb_ctx* ctx, int c, bool screened) {
+  if (c == kSymB) {
+    int per_cu = 0;
+    const void* kern = screened ? (const void*)k_far32_sym_batch<true> : (const void*)k_far32_sym_batch<false>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, 0) != hipSuccess || per_cu < 1) per_cu = 2;
+    return per_cu * ctx->n_cu;
+  }
   switch (c) {
     case 0: return grid_for_t<256, 1>(ctx, screened);
     case 1: return grid_for_t<512, 1>(ctx, screened);
@@ -576,14 +644,32 @@ std::vector<Item> make_items(const std::vector<MolDev>& mols, int tpl, int chunk
   return out;
 }
 
+// Work items (molecule, Ic, Jc) of the symmetric kernel, ordered by cost (a diagonal chunk
+// pair costs about half an off-diagonal one), largest first.
+std::vector<Item> make_sym_items(const std::vector<MolDev>& mols) {
+  std::vector<std::pair<int64_t, Item>> v;
+  for (int mi = 0; mi < (int)mols.size(); ++mi) {
+    const int n = mols[mi].n, C = mols[mi].nsub * kSymSub, nc = mols[mi].Ssym;
+    for (int i = 0; i < nc; ++i)
+      for (int j = i; j < nc; ++j) {
+        const int64_t ni = std::min(C, n - i * C), nj = std::min(C, n - j * C);
+        v.push_back({i == j ? ni * nj / 2 : ni * nj, Item{mi, i, j}});
+      }
+  }
+  std::stable_sort(v.begin(), v.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+  std::vector<Item> out(v.size());
+  for (size_t i = 0; i < v.size(); ++i) out[i] = v[i].second;
+  return out;
+}
+
 // Molecules selected by `sel` get y = A x with the FP64 operator (persistent launch).
 void op64(Batch& B, const double* x, double* y, const int* sel) {
   const unsigned nbn = (unsigned)((B.ntot + kBlock - 1) / kBlock);
   k_weights_batch<<<nbn, kBlock, 0, B.st>>>(B.ntot, B.mol_of, B.mols, x, B.d.h3 / (4.0 * kPi), B.wpsi, B.wpsn);
   k_far64_batch<<<B.grid64, kBlock, 0, B.st>>>(B.items64, B.n_items64, B.mols, kChunk64, sel, B.wpsi, B.wpsn,
                                                kparams(B.d), B.partial);
-  k_reduce_batch<<<nbn, kBlock, 0, B.st>>>(B.ntot, B.mol_of, B.mols, sel, 1, B.partial, x, y, nullptr, 0, 0, B.d.lam1,
-                                           B.d.lam2);
+  k_reduce_batch<<<nbn, kBlock, 0, B.st>>>(B.ntot, B.mol_of, B.mols, sel, kModeF64, B.partial, x, y, nullptr, 0, 0,
+                                           B.d.lam1, B.d.lam2);
 }
 
 // Mixed operator: y = A x for molecules in `act`; with kptr, x = V[*kptr] and y = V[*kptr+1].
@@ -591,8 +677,8 @@ void op_mixed(Batch& B, const double* x, double* y, const int* kptr, int64_t ldv
   const unsigned nbn = (unsigned)((B.ntot + kBlock - 1) / kBlock);
   k_pack_batch<<<nbn, kBlock, 0, B.st>>>(B.ntot, B.mol_of, B.mols, x, kptr, B.m, ldv, B.d.h3 / (4.0 * kPi), B.sigma);
   launch_far32(B, B.cfg, act, f32params(B.d, B.sigma), B.sigma, B.sigma * B.sigma);
-  k_reduce_batch<<<nbn, kBlock, 0, B.st>>>(B.ntot, B.mol_of, B.mols, act, 0, B.partial, x, y, kptr, B.m, ldv,
-                                           B.d.lam1, B.d.lam2);
+  k_reduce_batch<<<nbn, kBlock, 0, B.st>>>(B.ntot, B.mol_of, B.mols, act, B.cfg == kSymB ? kModeSym : kModeTiled,
+                                           B.partial, x, y, kptr, B.m, ldv, B.d.lam1, B.d.lam2);
 }
 
 // Per-molecule 2-norms of v over the molecules in sel, into out[mol].
@@ -601,11 +687,17 @@ void norms(Batch& B, const double* v, const int* sel, double* out) {
   k_dots_finish_batch<<<dim3(B.n_mol, 1), 64, 0, B.st>>>(B.n_mol, B.segs, sel, B.dpart, 1, nullptr, 0, 1, out, 1, 1);
 }
 
-// One Arnoldi step of every active molecule (the graph body): w = A V[k], two classical
-// Gram–Schmidt passes, the norm, Givens, scaling, k += 1.
-void arnoldi_step(Batch& B) {
+// One Arnoldi step of every active molecule (the graph body): w = A V[k] (with prec:
+// Z[k] = M(V[k]), w = A Z[k]), two classical Gram–Schmidt passes, the norm, Givens,
+// scaling, k += 1.
+void arnoldi_step(Batch& B, bool prec) {
   const int m = B.m, hs = B.hstride;
-  op_mixed(B, B.V, B.V, B.kptr, B.M, B.active);
+  if (prec) {
+    nn_batch_apply(B.st, B.net, *B.nb, B.V, B.Z, B.M, B.kptr, m, B.d.lam1, B.d.lam2);
+    op_mixed(B, B.Z, B.V, B.kptr, B.M, B.active);
+  } else {
+    op_mixed(B, B.V, B.V, B.kptr, B.M, B.active);
+  }
   for (int pass = 0; pass < 2; ++pass) {
     double* hv = B.hbuf + pass * (m + 1);
     k_dots_batch<<<B.nseg, kBlock, 0, B.st>>>(B.nseg, B.segs, B.active, B.V, B.M, B.kptr, m, 0, nullptr, m + 1,
@@ -644,9 +736,11 @@ extern "C" pb_status pb_ibim_solve_batched(pb_ctx* ctx, int n_mol, const pb_band
   if (opts.precision != PB_FP64 && opts.precision != PB_MIXED) return ctx->fail(PB_EINVAL, "unknown precision");
   if (prm->reg_metric == PB_REG_TANGENT)
     return ctx->fail(PB_EINVAL, "the batched path needs a bounded regularization radius (guarded or Euclidean)");
-  if (opts.x0 != PB_X0_DIAG && opts.x0 != PB_X0_ZERO && opts.x0 != PB_X0_USER)
-    return ctx->fail(PB_EINVAL, "x0 mode not available in the batched solve");
-  if (opts.precond != PB_PRECOND_NONE) return ctx->fail(PB_EINVAL, "preconditioner not available in the batched solve");
+  if (opts.x0 < PB_X0_ZERO || opts.x0 > PB_X0_LEARNED) return ctx->fail(PB_EINVAL, "unknown x0 mode %d", opts.x0);
+  if (opts.precond != PB_PRECOND_NONE && opts.precond != PB_PRECOND_LEARNED)
+    return ctx->fail(PB_EINVAL, "unknown preconditioner %d", opts.precond);
+  const bool learned_x0 = opts.x0 == PB_X0_LEARNED, prec = opts.precond == PB_PRECOND_LEARNED;
+  if ((learned_x0 || prec) && !opts.nn) return ctx->fail(PB_EINVAL, "the learned path needs opts->nn");
   int64_t ntot64 = 0;
   for (int i = 0; i < n_mol; ++i) {
     PB_TRY(check_band(ctx, &bands[i]));
@@ -671,7 +765,7 @@ extern "C" pb_status pb_ibim_solve_batched(pb_ctx* ctx, int n_mol, const pb_band
 
   // per-molecule geometry: FP32 records and near-field CSR on the context stream
   B.mols_h.resize(n_mol);
-  int64_t off = 0, p32 = 0, p64 = 0;
+  int64_t off = 0, p32 = 0, p64 = 0, psym = 0;
   for (int i = 0; i < n_mol; ++i) {
     char pfx[32];
     snprintf(pfx, sizeof(pfx), "bt%d_", i);
@@ -682,8 +776,11 @@ extern "C" pb_status pb_ibim_solve_batched(pb_ctx* ctx, int n_mol, const pb_band
     md.n = (int)bands[i].n;
     md.S32 = (md.n + kChunk32 - 1) / kChunk32;
     md.S64 = (md.n + kChunk64 - 1) / kChunk64;
+    md.Ssym = sym_chunks(md.n);
+    md.nsub = sym_nsub(md.n);
     md.poff32 = p32;
     md.poff64 = p64;
+    md.poffsym = psym;
     md.cx = P.cx;
     md.cy = P.cy;
     md.cz = P.cz;
@@ -699,6 +796,7 @@ extern "C" pb_status pb_ibim_solve_batched(pb_ctx* ctx, int n_mol, const pb_band
     off += md.n;
     p32 += (int64_t)md.S32 * 2 * md.n;
     p64 += (int64_t)md.S64 * 2 * md.n;
+    psym += (int64_t)md.Ssym * 2 * md.n;
   }
   // segments of kSeg vector elements within each molecule
   std::vector<int> seg_mol, first(n_mol + 1);
@@ -722,11 +820,15 @@ extern "C" pb_status pb_ibim_solve_batched(pb_ctx* ctx, int n_mol, const pb_band
   int64_t* slo = (int64_t*)ws("bt_seg_lo", sizeof(int64_t) * B.nseg);
   int64_t* shi = (int64_t*)ws("bt_seg_hi", sizeof(int64_t) * B.nseg);
   int* sfirst = (int*)ws("bt_seg_first", sizeof(int) * (n_mol + 1));
-  B.partial = (double*)ws("bt_partial", sizeof(double) * (size_t)std::max(p32, p64));
+  B.partial = (double*)ws("bt_partial", sizeof(double) * (size_t)std::max(std::max(p32, p64), psym));
   B.wpsi = (double*)ws("bt_wpsi", sizeof(double) * B.ntot);
   B.wpsn = (double*)ws("bt_wpsn", sizeof(double) * B.ntot);
   B.dpart = (double*)ws("bt_dpart", sizeof(double) * (size_t)B.nseg * (m + 1));
   B.V = (double*)ws("bt_V", sizeof(double) * (size_t)B.M * (m + 1));
+  if (prec) {
+    B.Z = (double*)ws("bt_Z", sizeof(double) * (size_t)B.M * m);
+    if (!B.Z) return PB_ENOMEM;
+  }
   B.H = (double*)ws("bt_H", sizeof(double) * (size_t)n_mol * (m + 1) * m);
   B.cs = (double*)ws("bt_cs", sizeof(double) * (size_t)n_mol * m);
   B.sn = (double*)ws("bt_sn", sizeof(double) * (size_t)n_mol * m);
@@ -760,7 +862,8 @@ extern "C" pb_status pb_ibim_solve_batched(pb_ctx* ctx, int n_mol, const pb_band
   std::vector<Item> it64 = make_items(B.mols_h, 1, kChunk64);
   Item* items_all[kNumCfgB + 1];
   std::vector<std::vector<Item>> lists;
-  for (int c = 0; c < kNumCfgB; ++c) lists.push_back(make_items(B.mols_h, kCfgTpl[c], kChunk32));
+  for (int c = 0; c < kNumTiledB; ++c) lists.push_back(make_items(B.mols_h, kCfgTpl[c], kChunk32));
+  lists.push_back(make_sym_items(B.mols_h));
   lists.push_back(it64);
   for (int c = 0; c <= kNumCfgB; ++c) {
     char nm[32];
@@ -801,6 +904,14 @@ extern "C" pb_status pb_ibim_solve_batched(pb_ctx* ctx, int n_mol, const pb_band
       PB_HIP(ctx, hipMemcpyAsync(x + 2 * (int64_t)md.off, p[i], sizeof(double) * 2 * md.n, hipMemcpyDeviceToDevice,
                                  ctx->stream));
   }
+  NNBatch nb;
+  if (learned_x0 || prec) {
+    std::vector<int> off_h(n_mol);
+    for (int i = 0; i < n_mol; ++i) off_h[i] = B.mols_h[i].off;
+    PB_TRY(nn_batch_prepare(ctx, n_mol, bands, off_h.data(), B.mol_of, B.d, nb));
+    B.nb = &nb;
+    B.net = (const pb_nn*)opts.nn;
+  }
   PB_TRY(launch_ok(ctx, "batch setup"));
   PB_TRY(sync(ctx, "batch setup"));
 
@@ -810,6 +921,7 @@ extern "C" pb_status pb_ibim_solve_batched(pb_ctx* ctx, int n_mol, const pb_band
   k_stamp<<<1, 1, 0, B.st>>>(t0dev);
   if (opts.x0 == PB_X0_DIAG) k_diag_batch<<<nbn, kBlock, 0, B.st>>>(B.ntot, B.mol_of, B.mols, g, B.d.lam1, B.d.lam2, x);
   else if (opts.x0 == PB_X0_ZERO) k_zero_vec<<<vb, kBlock, 0, B.st>>>(B.M, x);
+  else if (learned_x0) nn_batch_apply(B.st, B.net, nb, g, x, 0, nullptr, 0, B.d.lam1, B.d.lam2);
   norms(B, g, all_on, gn);
   PB_TRY(launch_ok(ctx, "batch x0"));
   std::vector<double> gn_h(n_mol);
@@ -823,8 +935,12 @@ extern "C" pb_status pb_ibim_solve_batched(pb_ctx* ctx, int n_mol, const pb_band
   {
     const int64_t key = (int64_t)B.ntot * 4096 + n_mol;
     auto itc = ctx->batch_cfg.find(key);
+    const char* env = std::getenv("PB_FAR_CFG");
     if (itc != ctx->batch_cfg.end()) {
       B.cfg = itc->second;
+    } else if (env && std::atoi(env) >= 0 && std::atoi(env) < kNumCfgB) {
+      B.cfg = std::atoi(env);
+      ctx->batch_cfg[key] = B.cfg;
     } else {
       k_pack_batch<<<nbn, kBlock, 0, B.st>>>(B.ntot, B.mol_of, B.mols, x, nullptr, 0, 0, B.d.h3 / (4.0 * kPi), B.sigma);
       hipEvent_t e0, e1;
@@ -851,35 +967,41 @@ extern "C" pb_status pb_ibim_solve_batched(pb_ctx* ctx, int n_mol, const pb_band
     }
   }
 
-  // the graph of one Arnoldi step of the batch
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  PB_HIP(ctx, hipStreamSynchronize(B.st));
-  PB_HIP(ctx, hipStreamBeginCapture(B.st, hipStreamCaptureModeThreadLocal));
-  arnoldi_step(B);
-  hipError_t cap = hipStreamEndCapture(B.st, &graph);
-  if (cap != hipSuccess) return ctx->fail(PB_EDEVICE, "graph capture failed: %s", hipGetErrorString(cap));
-  if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
-    (void)hipGraphDestroy(graph);
-    return ctx->fail(PB_EDEVICE, "graph instantiation failed");
-  }
-  struct GraphGuard {
-    hipGraph_t g;
-    hipGraphExec_t e;
-    ~GraphGuard() {
+  // the graph of one Arnoldi step of the batch, captured on first use (with or without
+  // the learned preconditioner)
+  struct GraphPair {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t e = nullptr;
+    ~GraphPair() {
       if (e) (void)hipGraphExecDestroy(e);
       if (g) (void)hipGraphDestroy(g);
     }
-  } guard{graph, exec};
+  } graphs[2];
+  auto graph_for = [&](bool with_prec, hipGraphExec_t* out) -> pb_status {
+    GraphPair& gp = graphs[with_prec ? 1 : 0];
+    if (!gp.e) {
+      PB_HIP(ctx, hipStreamSynchronize(B.st));
+      PB_HIP(ctx, hipStreamBeginCapture(B.st, hipStreamCaptureModeThreadLocal));
+      arnoldi_step(B, with_prec);
+      hipError_t cap = hipStreamEndCapture(B.st, &gp.g);
+      if (cap != hipSuccess) return ctx->fail(PB_EDEVICE, "graph capture failed: %s", hipGetErrorString(cap));
+      if (hipGraphInstantiate(&gp.e, gp.g, nullptr, nullptr, 0) != hipSuccess)
+        return ctx->fail(PB_EDEVICE, "graph instantiation failed");
+    }
+    *out = gp.e;
+    return PB_OK;
+  };
 
-  int replays = 0, outer = 0, iters_total = 0;
+  int replays = 0, outer = 0, outer_run = 0, iters_total = 0;
   std::vector<int> mv64(n_mol, 0), mvmx(n_mol, 0), cyc_h(n_mol), sel_h(n_mol);
   PB_HIP(ctx, hipMemcpyAsync(sel, all_on, sizeof(int) * n_mol, hipMemcpyDeviceToDevice, B.st));
 
   // Inner GMRES on the mixed operator for the molecules in `want`, from d = 0 with residual r.
   double* rr = (double*)ws("bt_rr", sizeof(double) * B.M);
   if (!rr) return PB_ENOMEM;
-  auto inner = [&](const int* want, const double* rhs_vec, double* sol) -> pb_status {
+  auto inner = [&](const int* want, const double* rhs_vec, double* sol, bool with_prec) -> pb_status {
+    hipGraphExec_t exec = nullptr;
+    PB_TRY(graph_for(with_prec, &exec));
     // sol = 0, so the first residual is the right-hand side itself
     k_copy<<<vb, kBlock, 0, B.st>>>(B.M, rhs_vec, rr);
     norms(B, rr, want, rn);
@@ -909,8 +1031,8 @@ extern "C" pb_status pb_ibim_solve_batched(pb_ctx* ctx, int n_mol, const pb_band
       std::vector<KState> ks(n_mol);
       PB_HIP(ctx, hipMemcpyAsync(ks.data(), B.kst, sizeof(KState) * n_mol, hipMemcpyDeviceToHost, B.st));
       k_trisolve_batch<<<(n_mol + 63) / 64, 64, 0, B.st>>>(n_mol, m, B.cycle, B.H, B.s, B.kst, B.ybuf, B.nq);
-      k_axpy_batch<<<B.nseg, kBlock, 0, B.st>>>(B.nseg, B.segs, B.cycle, B.V, B.M, nullptr, m, B.nq, B.ybuf, m, 1.0,
-                                                sol);
+      k_axpy_batch<<<B.nseg, kBlock, 0, B.st>>>(B.nseg, B.segs, B.cycle, with_prec ? B.Z : B.V, B.M, nullptr, m, B.nq,
+                                                B.ybuf, m, 1.0, sol);
       PB_HIP(ctx, hipStreamSynchronize(B.st));
       int maxk = 0;
       for (int i = 0; i < n_mol; ++i)
@@ -931,7 +1053,10 @@ extern "C" pb_status pb_ibim_solve_batched(pb_ctx* ctx, int n_mol, const pb_band
     return PB_OK;
   };
 
-  if (opts.precision == PB_MIXED) {
+  if (opts.precision != PB_MIXED)
+    return ctx->fail(PB_EINVAL, "the batched solve runs the mixed path (precision PB_MIXED)");
+  // refinement over the molecules in sel: FP64 residual, inner solve, update
+  auto outer_loop = [&](bool with_prec) -> pb_status {
     for (;;) {
       op64(B, x, r, sel);
       k_resid_batch<<<nbn, kBlock, 0, B.st>>>(B.ntot, B.mol_of, B.mols, sel, g, r, dvec);
@@ -945,14 +1070,30 @@ extern "C" pb_status pb_ibim_solve_batched(pb_ctx* ctx, int n_mol, const pb_band
       PB_HIP(ctx, hipMemcpyAsync(&nsel, n_sel, sizeof(int), hipMemcpyDeviceToHost, B.st));
       PB_HIP(ctx, hipStreamSynchronize(B.st));
       for (int i = 0; i < n_mol; ++i) mv64[i] += sel_h[i];
-      if (nsel == 0 || outer >= opts.max_outer || iters_total >= opts.max_iter) break;
-      PB_TRY(inner(sel, r, dvec));
+      if (nsel == 0 || outer_run >= opts.max_outer || iters_total >= opts.max_iter) return PB_OK;
+      PB_TRY(inner(sel, r, dvec, with_prec));
       k_add_batch<<<B.nseg, kBlock, 0, B.st>>>(B.nseg, B.segs, sel, dvec, x);
       ++outer;
+      ++outer_run;
     }
-  } else {
-    // FP64: plain restarted GMRES with the FP64 operator, one Arnoldi step per host round trip
-    return ctx->fail(PB_EINVAL, "the batched solve runs the mixed path (precision PB_MIXED)");
+  };
+  std::vector<int> fallback(n_mol, 0);
+  PB_TRY(outer_loop(prec));
+  if (prec) {
+    // plain GMRES judges the learned path: molecules still selected missed the tolerance
+    PB_HIP(ctx, hipMemcpyAsync(sel_h.data(), sel, sizeof(int) * n_mol, hipMemcpyDeviceToHost, B.st));
+    PB_HIP(ctx, hipStreamSynchronize(B.st));
+    bool any = false;
+    for (int i = 0; i < n_mol; ++i) {
+      fallback[i] = sel_h[i];
+      any = any || fallback[i];
+    }
+    if (any) {
+      k_reset_nonfinite<<<nbn, kBlock, 0, B.st>>>(B.ntot, B.mol_of, B.mols, relres, g, B.d.lam1, B.d.lam2, x);
+      outer_run = 0;
+      iters_total = 0;
+      PB_TRY(outer_loop(false));
+    }
   }
 
   // results
@@ -981,7 +1122,7 @@ extern "C" pb_status pb_ibim_solve_batched(pb_ctx* ctx, int n_mol, const pb_band
       stats[i].iters = ks[i].iters;
       stats[i].outer = outer;
       stats[i].converged = ok;
-      stats[i].fallback_used = 0;
+      stats[i].fallback_used = fallback[i];
       stats[i].matvecs_fp64 = mv64[i];
       stats[i].matvecs_mixed = mvmx[i];
       stats[i].true_relres = rel_h[i];
@@ -1007,6 +1148,7 @@ extern "C" pb_status pb_ibim_solve_batched(pb_ctx* ctx, int n_mol, const pb_band
     bstats->far_tpl = kCfgTpl[B.cfg];
     bstats->n_items = B.n_items32[B.cfg];
     bstats->outer = outer;
+    bstats->far_symmetric = B.cfg == kSymB;
   }
   if (!all_ok) return ctx->fail(PB_ENOCONV, "some molecules did not reach the tolerance");
   return PB_OK;

@@ -309,6 +309,15 @@ pb_status pb_set_timing(pb_ctx* ctx, int enable) {
   return PB_OK;
 }
 
+pb_status pb_far_kernel(pb_ctx* ctx, int64_t n, int* cfg) {
+  if (!ctx || !cfg) return PB_EINVAL;
+  auto it = ctx->far_cfg.find((int)n);
+  if (n < 1 || n > INT32_MAX || it == ctx->far_cfg.end())
+    return ctx->fail(PB_EINVAL, "no far-field kernel chosen for bands of %lld nodes", (long long)n);
+  *cfg = it->second;
+  return PB_OK;
+}
+
 pb_status pb_kernel_time(pb_ctx* ctx, const char* name, double* total_ms, int64_t* launches) {
   if (!ctx || !name) return PB_EINVAL;
   PB_TRY(pb::sync(ctx, "pb_kernel_time"));

@@ -8,7 +8,7 @@
 // Layout: φ is one FP64 array, k fastest. Each stencil kernel maps one thread to one node;
 // consecutive threads are consecutive k, so the ±k neighbours are coalesced and the ±i/±j
 // neighbours are served from L2. Products and sums are rounded as written (no FMA
-// contraction) so that the grid values are reproducible to the last bit.
+// contraction), so the grid values are reproducible to the last bit from run to run.
 #include <cmath>
 
 #include "pb_internal.hpp"
@@ -27,13 +27,6 @@ struct GridDev {
 
 __device__ __forceinline__ int64_t lin(const GridDev& g, int64_t i, int64_t j, int64_t k) {
   return (i * g.ny + j) * g.nz + k;
-}
-
-// Even reflection about the boundary node: −m ↦ m, n−1+m ↦ n−1−m (zero Neumann).
-__device__ __forceinline__ int64_t refl(int64_t i, int64_t n) {
-  if (i < 0) return -i;
-  if (i > n - 1) return 2 * (n - 1) - i;
-  return i;
 }
 
 __device__ __forceinline__ double sq(double a) { return a * a; }
@@ -62,33 +55,41 @@ __global__ void __launch_bounds__(kBlock) k_vdw(GridDev g, const double* __restr
   if (id < total) phi[id] = best - shift;
 }
 
-__device__ double weno5(double v1, double v2, double v3, double v4, double v5) {
+// Fifth-order WENO one-sided derivative from five consecutive differences. The weights
+// α_k = d_k/(ε + β_k)² are normalized as α_k/Σα = d_k q_l q_m / Σ d_k q_l q_m with
+// q = (ε + β)², the same quotient with one division instead of four; the constant
+// coefficients of the three candidate stencils are multiplications.
+__device__ __forceinline__ double weno5(double v1, double v2, double v3, double v4, double v5) {
   const double e = 1e-6;
   double s1 = 13.0 / 12.0 * sq(v1 - 2.0 * v2 + v3) + 0.25 * sq(v1 - 4.0 * v2 + 3.0 * v3);
   double s2 = 13.0 / 12.0 * sq(v2 - 2.0 * v3 + v4) + 0.25 * sq(v2 - v4);
   double s3 = 13.0 / 12.0 * sq(v3 - 2.0 * v4 + v5) + 0.25 * sq(3.0 * v3 - 4.0 * v4 + v5);
-  double a1 = 0.1 / sq(s1 + e), a2 = 0.6 / sq(s2 + e), a3 = 0.3 / sq(s3 + e);
-  double p1 = v1 / 3.0 - 7.0 * v2 / 6.0 + 11.0 * v3 / 6.0;
-  double p2 = -v2 / 6.0 + 5.0 * v3 / 6.0 + v4 / 3.0;
-  double p3 = v3 / 3.0 + 5.0 * v4 / 6.0 - v5 / 6.0;
-  return (a1 * p1 + a2 * p2 + a3 * p3) / (a1 + a2 + a3);
+  double q1 = sq(s1 + e), q2 = sq(s2 + e), q3 = sq(s3 + e);
+  double w1 = 0.1 * (q2 * q3), w2 = 0.6 * (q1 * q3), w3 = 0.3 * (q1 * q2);
+  double p1 = v1 * (1.0 / 3.0) - v2 * (7.0 / 6.0) + v3 * (11.0 / 6.0);
+  double p2 = -v2 * (1.0 / 6.0) + v3 * (5.0 / 6.0) + v4 * (1.0 / 3.0);
+  double p3 = v3 * (1.0 / 3.0) + v4 * (5.0 / 6.0) - v5 * (1.0 / 6.0);
+  return (w1 * p1 + w2 * p2 + w3 * p3) / (w1 + w2 + w3);
 }
 
-// Godunov |∇φ| for the Hamiltonian s·|∇φ| at one node.
-__device__ double godunov(const GridDev& g, const double* __restrict__ phi, int64_t i, int64_t j, int64_t k,
+// Godunov |∇φ| for the Hamiltonian s·|∇φ| at node id = (i, j, k) (32-bit indexing; grids
+// hold fewer than 2^31 nodes). ih = 1/h.
+__device__ double godunov(const GridDev& g, const double* __restrict__ phi, int id, int i, int j, int k, double ih,
                           double s) {
   double acc = 0.0;
-  int64_t n3[3] = {g.nx, g.ny, g.nz};
-  int64_t c[3] = {i, j, k};
+  const int n3[3] = {g.nx, g.ny, g.nz};
+  const int c[3] = {i, j, k};
+  const int stride[3] = {g.ny * g.nz, g.nz, 1};
   for (int ax = 0; ax < 3; ++ax) {
     double f[7];
     for (int sft = -3; sft <= 3; ++sft) {
-      int64_t q[3] = {c[0], c[1], c[2]};
-      q[ax] = refl(c[ax] + sft, n3[ax]);
-      f[sft + 3] = phi[lin(g, q[0], q[1], q[2])];
+      int q = c[ax] + sft;
+      // zero-Neumann ghosts: even reflection about the boundary node, −m ↦ m, n−1+m ↦ n−1−m
+      q = q < 0 ? -q : (q > n3[ax] - 1 ? 2 * (n3[ax] - 1) - q : q);
+      f[sft + 3] = phi[id + (q - c[ax]) * stride[ax]];
     }
     double D[6];
-    for (int m = 0; m < 6; ++m) D[m] = (f[m + 1] - f[m]) / g.h;
+    for (int m = 0; m < 6; ++m) D[m] = (f[m + 1] - f[m]) * ih;
     double a = weno5(D[0], D[1], D[2], D[3], D[4]);
     double b = weno5(D[5], D[4], D[3], D[2], D[1]);
     if (s >= 0.0) acc += fmax(sq(fmax(a, 0.0)), sq(fmin(b, 0.0)));
@@ -105,21 +106,24 @@ __device__ double godunov(const GridDev& g, const double* __restrict__ phi, int6
 __global__ void __launch_bounds__(kBlock) k_rk_stage(GridDev g, const double* __restrict__ phi_in,
                                                      const double* __restrict__ phi_n, const double* __restrict__ S,
                                                      double* __restrict__ out, int mode, int stage, double dt) {
-  int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  int64_t total = (int64_t)g.nx * g.ny * g.nz;
-  if (id >= total) return;
-  int64_t k = id % g.nz, j = (id / g.nz) % g.ny, i = id / ((int64_t)g.ny * g.nz);
+  const unsigned total = (unsigned)g.nx * (unsigned)g.ny * (unsigned)g.nz;
+  const unsigned uid = blockIdx.x * kBlock + threadIdx.x;
+  if (uid >= total) return;
+  const unsigned t = uid / (unsigned)g.nz;
+  const int k = (int)(uid - t * (unsigned)g.nz), j = (int)(t % (unsigned)g.ny), i = (int)(t / (unsigned)g.ny);
+  const int id = (int)uid;
+  const double ih = 1.0 / g.h;
   double L;
   if (mode == 0) {
-    L = godunov(g, phi_in, i, j, k, -1.0);
+    L = godunov(g, phi_in, id, i, j, k, ih, -1.0);
   } else {
     double s = S[id];
-    L = -s * (godunov(g, phi_in, i, j, k, s) - 1.0);
+    L = -s * (godunov(g, phi_in, id, i, j, k, ih, s) - 1.0);
   }
   double v;
   if (stage == 0) v = phi_in[id] + dt * L;
   else if (stage == 1) v = 0.75 * phi_n[id] + 0.25 * (phi_in[id] + dt * L);
-  else v = phi_n[id] / 3.0 + (2.0 / 3.0) * (phi_in[id] + dt * L);
+  else v = phi_n[id] * (1.0 / 3.0) + (2.0 / 3.0) * (phi_in[id] + dt * L);
   out[id] = v;
 }
 
@@ -236,6 +240,8 @@ extern "C" pb_status pb_build_levelset(pb_ctx* ctx, const double* atoms, int n_a
   if (std::fabs(grid->h - prm->h) > 1e-12 * prm->h)
     return ctx->fail(PB_EINVAL, "pb_build_levelset: grid spacing differs from params.h");
   PB_HIP(ctx, hipSetDevice(ctx->device));
+  if ((int64_t)grid->nx * grid->ny * grid->nz >= ((int64_t)1 << 31))
+    return ctx->fail(PB_EINVAL, "pb_build_levelset: grid of 2^31 nodes or more");
   GridDev g{grid->nx, grid->ny, grid->nz, grid->origin[0], grid->origin[1], grid->origin[2], grid->h};
   int64_t total = (int64_t)g.nx * g.ny * g.nz;
   unsigned nb = blocks_for(total);

@@ -10,13 +10,16 @@
 // Both sides decide "near" with the same FP32 function of the same FP32 records, so each pair
 // is counted exactly once. The near matrix depends only on the geometry and is built once per
 // band; each application is then an SpMV. The far kernel's tile shape (sources per LDS tile,
-// targets per lane) is chosen per band size by timing the candidates once (autotuner).
+// targets per lane) is chosen per band size by timing the candidates once (autotuner); the
+// symmetric kernel (each unordered pair once, both directions) is one of the candidates.
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <vector>
 
 #include "pair_kernels.hpp"
+#include "sym_kernels.hpp"
 
 namespace pb {
 namespace {
@@ -25,7 +28,36 @@ struct FarCfg {
   int tile, tpl;
 };
 constexpr FarCfg kFarCfgs[] = {{256, 1}, {512, 1}, {256, 2}, {512, 2}};
-constexpr int kNumFarCfgs = sizeof(kFarCfgs) / sizeof(kFarCfgs[0]);
+constexpr int kNumTiled = sizeof(kFarCfgs) / sizeof(kFarCfgs[0]);
+constexpr int kSymCfg = kNumTiled;  // the symmetric kernel
+constexpr int kNumFarCfgs = kNumTiled + 1;
+
+// Work items (Ic, Jc), Ic ≤ Jc, of the symmetric kernel for a band of n nodes: off-diagonal
+// chunk pairs first (they cost the most), the diagonal ones last.
+std::vector<int2> sym_items(int n) {
+  const int nc = sym_chunks(n);
+  std::vector<int2> v;
+  v.reserve((size_t)nc * (nc + 1) / 2);
+  for (int i = 0; i < nc; ++i)
+    for (int j = i + 1; j < nc; ++j) v.push_back(make_int2(i, j));
+  for (int i = 0; i < nc; ++i) v.push_back(make_int2(i, i));
+  return v;
+}
+
+// The item list on the device for a band of n nodes (rebuilt when n changes).
+const int2* sym_items_dev(pb_ctx* ctx, int n, int* n_items) {
+  const std::vector<int2> v = sym_items(n);
+  int2* d = (int2*)workspace(ctx, "sym_items", sizeof(int2) * v.size());
+  if (!d) return nullptr;
+  if (ctx->sym_items_n != n) {
+    if (hipMemcpyAsync(d, v.data(), sizeof(int2) * v.size(), hipMemcpyHostToDevice, ctx->stream) != hipSuccess)
+      return nullptr;
+    ctx->sym_items_n = n;
+    ctx->sym_n_items = (int)v.size();
+  }
+  *n_items = ctx->sym_n_items;
+  return d;
+}
 
 // Source chunks for a launch: at least ~8 blocks per CU, chunks a multiple of the tile.
 int far_chunks(pb_ctx* ctx, int n, int targets_per_block, int tile, int* chunk) {
@@ -54,6 +86,18 @@ int launch_far_t(pb_ctx* ctx, bool screened, const float4* A, const float4* M, c
 
 int launch_far(pb_ctx* ctx, int cfg, bool screened, const float4* A, const float4* M, const float4* N,
                const float4* box, int n, const F32Params& fp, double sig1, double sig2, double* partial) {
+  if (cfg == kSymCfg) {
+    int n_items = 0;
+    const int2* items = sym_items_dev(ctx, n, &n_items);
+    if (!items) return -1;
+    if (screened)
+      k_p2p_f32_sym<true><<<(unsigned)n_items, kBlock, 0, ctx->stream>>>(A, M, N, box, n, sym_nsub(n), items,
+                                                                          n_items, fp, sig1, sig2, partial);
+    else
+      k_p2p_f32_sym<false><<<(unsigned)n_items, kBlock, 0, ctx->stream>>>(A, M, N, box, n, sym_nsub(n), items,
+                                                                           n_items, fp, sig1, sig2, partial);
+    return sym_chunks(n);
+  }
   switch (cfg) {
     case 0: return launch_far_t<256, 1>(ctx, screened, A, M, N, box, n, fp, sig1, sig2, partial);
     case 1: return launch_far_t<512, 1>(ctx, screened, A, M, N, box, n, fp, sig1, sig2, partial);
@@ -63,8 +107,8 @@ int launch_far(pb_ctx* ctx, int cfg, bool screened, const float4* A, const float
 }
 
 int far_max_chunks(pb_ctx* ctx, int n) {
-  int m = 1, c = 0;
-  for (int k = 0; k < kNumFarCfgs; ++k)
+  int m = sym_chunks(n), c = 0;
+  for (int k = 0; k < kNumTiled; ++k)
     m = std::max(m, far_chunks(ctx, n, kBlock * kFarCfgs[k].tpl, kFarCfgs[k].tile, &c));
   return m;
 }
@@ -95,7 +139,8 @@ pb_status far_autotune(pb_ctx* ctx, int n, bool screened, const float4* A, const
   int best = 0;
   float best_ms = 1e30f;
   for (int c = 0; c < kNumFarCfgs; ++c) {
-    launch_far(ctx, c, screened, A, M, N, box, n, fp, 1.0, 1.0, partial);
+    if (launch_far(ctx, c, screened, A, M, N, box, n, fp, 1.0, 1.0, partial) < 0)
+      return ctx->fail(PB_ENOMEM, "far-field work list");
     PB_HIP(ctx, hipEventRecord(e0, ctx->stream));
     launch_far(ctx, c, screened, A, M, N, box, n, fp, 1.0, 1.0, partial);
     PB_HIP(ctx, hipEventRecord(e1, ctx->stream));
@@ -262,9 +307,9 @@ pb_status matvec_mixed(pb_ctx* ctx, const pb_band* band, const Derived& d, const
   {
     Scope t(ctx, "p2p_f32");
     S = launch_far(ctx, P.far_cfg, d.kappa > 0.0, P.A, P.M, P.N, P.box, n, f32params(d, P.sigma), P.sigma,
-                   P.sigma * P.sigma,
-                   partial);
+                   P.sigma * P.sigma, partial);
   }
+  if (S < 0) return ctx->fail(PB_ENOMEM, "far-field work list");
   {
     Scope t(ctx, "near_f64");
     k_near_spmv<<<(unsigned)(((int64_t)n * kRowLanes + kBlock - 1) / kBlock), kBlock, 0, ctx->stream>>>(

@@ -722,6 +722,178 @@ pb_status nn_cast(pb_ctx* ctx, pb_nn* net) {
   return launch_ok(ctx, "nn cast");
 }
 
+// ---------------------------------------------------------------- batch of bands
+
+namespace {
+
+// Per molecule: s[2m], s[2m + 1] = RMS of the two halves of its segment of v (1 when zero).
+// One block per molecule, fixed summation order.
+__global__ void __launch_bounds__(kBlock) k_rms_batch(int n_mol, const int* __restrict__ off, const int* __restrict__ cnt,
+                                                      const double* __restrict__ V, int64_t ldv,
+                                                      const int* __restrict__ kptr, int kmax, double* __restrict__ s) {
+  __shared__ double r1[kBlock], r2[kBlock];
+  const int m = blockIdx.x;
+  if (m >= n_mol) return;
+  if (kptr && *kptr >= kmax) return;
+  const double* v = V + (kptr ? (int64_t)(*kptr) * ldv : 0) + 2 * (int64_t)off[m];
+  const int n = cnt[m];
+  double a = 0.0, c = 0.0;
+  for (int i = threadIdx.x; i < n; i += kBlock) {
+    a += v[i] * v[i];
+    c += v[n + i] * v[n + i];
+  }
+  r1[threadIdx.x] = a;
+  r2[threadIdx.x] = c;
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      r1[threadIdx.x] += r1[threadIdx.x + o];
+      r2[threadIdx.x] += r2[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double q1 = sqrt(r1[0] / n), q2 = sqrt(r2[0] / n);
+    s[2 * m] = q1 > 0.0 ? q1 : 1.0;
+    s[2 * m + 1] = q2 > 0.0 ? q2 : 1.0;
+  }
+}
+
+// Layer-1 input rows of every node of the batch (as k_build_g1, per molecule).
+__global__ void __launch_bounds__(kBlock) k_build_g1_batch(int ntot, const int* __restrict__ mol_of,
+                                                           const int* __restrict__ off, const int* __restrict__ cnt,
+                                                           const double* __restrict__ pos, const int* __restrict__ nbr,
+                                                           const float* __restrict__ feat,
+                                                           const double* __restrict__ V, int64_t ldv,
+                                                           const int* __restrict__ kptr, int kmax,
+                                                           const double* __restrict__ s, double eps,
+                                                           uint16_t* __restrict__ G1) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= (int64_t)ntot * kSlots) return;
+  if (kptr && *kptr >= kmax) return;
+  const int i = (int)(t / kSlots), slot = (int)(t % kSlots);
+  const int j = nbr[(int64_t)i * kSlots + slot];
+  const int m = mol_of[i];
+  const int n = cnt[m];
+  const double* v = V + (kptr ? (int64_t)(*kptr) * ldv : 0) + 2 * (int64_t)off[m];
+  const int lj = j - off[m];
+  const float* fj = feat + (int64_t)j * 5;
+  float f[16];
+  f[0] = fj[0];
+  f[1] = fj[1];
+  f[2] = fj[2];
+  f[3] = fj[3];
+  f[4] = fj[4];
+  f[5] = (float)(v[lj] / s[2 * m]);
+  f[6] = (float)(v[n + lj] / s[2 * m + 1]);
+  f[7] = (float)((pos[3 * (int64_t)j] - pos[3 * (int64_t)i]) / eps);
+  f[8] = (float)((pos[3 * (int64_t)j + 1] - pos[3 * (int64_t)i + 1]) / eps);
+  f[9] = (float)((pos[3 * (int64_t)j + 2] - pos[3 * (int64_t)i + 2]) / eps);
+  for (int q = 10; q < 16; ++q) f[q] = 0.f;
+  uint16_t* out = G1 + t * 16;
+  for (int q = 0; q < 16; ++q) out[q] = bf16_bits(f[q]);
+}
+
+// p = Λ⁻¹(v + s_m ⊙ O[:, 0:2]) over every molecule's segment.
+__global__ void __launch_bounds__(kBlock) k_apply_out_batch(int ntot, const int* __restrict__ mol_of,
+                                                            const int* __restrict__ off, const int* __restrict__ cnt,
+                                                            const double* __restrict__ V, double* __restrict__ Z,
+                                                            int64_t ldv, const int* __restrict__ kptr, int kmax,
+                                                            const float* __restrict__ O, const double* __restrict__ s,
+                                                            double lam1, double lam2) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= ntot) return;
+  if (kptr && *kptr >= kmax) return;
+  const int m = mol_of[i];
+  const int n = cnt[m], l = i - off[m];
+  const int64_t base = (kptr ? (int64_t)(*kptr) * ldv : 0) + 2 * (int64_t)off[m];
+  Z[base + l] = (V[base + l] + s[2 * m] * (double)O[(int64_t)i * 16]) / lam1;
+  Z[base + n + l] = (V[base + n + l] + s[2 * m + 1] * (double)O[(int64_t)i * 16 + 1]) / lam2;
+}
+
+// Local neighbour indices of one molecule → global node indices; positions into the batch table.
+__global__ void __launch_bounds__(kBlock) k_batch_geometry(int n, int off, BandDev b, int* __restrict__ nbr,
+                                                           double* __restrict__ pos) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  for (int q = 0; q < kSlots; ++q) nbr[(int64_t)i * kSlots + q] += off;
+  pos[3 * (int64_t)i] = b.px[i];
+  pos[3 * (int64_t)i + 1] = b.py[i];
+  pos[3 * (int64_t)i + 2] = b.pz[i];
+}
+
+}  // namespace
+
+pb_status nn_batch_prepare(pb_ctx* ctx, int n_mol, const pb_band* bands, const int* off_host, const int* mol_of,
+                           const Derived& d, NNBatch& nb) {
+  int64_t ntot64 = 0;
+  std::vector<int> cnt_host(n_mol);
+  for (int m = 0; m < n_mol; ++m) {
+    if (!bands[m].phi) return ctx->fail(PB_EINVAL, "the learned path needs each band's phi array (molecule %d)", m);
+    cnt_host[m] = (int)bands[m].n;
+    ntot64 += bands[m].n;
+  }
+  const int ntot = (int)ntot64;
+  auto ws = [&](const char* name, size_t bytes) { return workspace(ctx, name, bytes); };
+  nb.n_mol = n_mol;
+  nb.ntot = ntot;
+  nb.eps = d.eps;
+  nb.mol_of = mol_of;
+  nb.off = (int*)ws("nnb_off", sizeof(int) * n_mol);
+  nb.cnt = (int*)ws("nnb_cnt", sizeof(int) * n_mol);
+  nb.pos = (double*)ws("nnb_pos", sizeof(double) * 3 * (size_t)ntot);
+  nb.nbr = (int*)ws("nnb_nbr", sizeof(int) * kSlots * (size_t)ntot);
+  nb.feat = (float*)ws("nnb_feat", sizeof(float) * 5 * (size_t)ntot);
+  nb.s = (double*)ws("nnb_s", sizeof(double) * 2 * n_mol);
+  nb.G1 = (uint16_t*)ws("nnb_G1", sizeof(uint16_t) * (size_t)ntot * kdim(0));
+  nb.X[0] = nullptr;
+  nb.X[1] = (float*)ws("nnb_X1", sizeof(float) * 64 * (size_t)ntot);
+  nb.X[2] = (float*)ws("nnb_X2", sizeof(float) * 64 * (size_t)ntot);
+  nb.X[3] = (float*)ws("nnb_X3", sizeof(float) * 64 * (size_t)ntot);
+  nb.O = (float*)ws("nnb_O", sizeof(float) * 16 * (size_t)ntot);
+  if (!nb.off || !nb.cnt || !nb.pos || !nb.nbr || !nb.feat || !nb.s || !nb.G1 || !nb.X[1] || !nb.X[2] || !nb.X[3] ||
+      !nb.O)
+    return PB_ENOMEM;
+  PB_HIP(ctx, hipMemcpyAsync(nb.off, off_host, sizeof(int) * n_mol, hipMemcpyHostToDevice, ctx->stream));
+  PB_HIP(ctx, hipMemcpyAsync(nb.cnt, cnt_host.data(), sizeof(int) * n_mol, hipMemcpyHostToDevice, ctx->stream));
+  for (int m = 0; m < n_mol; ++m) {
+    const pb_band* band = &bands[m];
+    const int n = (int)band->n, o = off_host[m];
+    MixedPlan P;
+    PB_TRY(near_build(ctx, band, d, "nnb_", P, true));
+    const CellsDev cells{(const int64_t*)ctx->bufs["nnb_cell_start"].ptr, (const int*)ctx->bufs["nnb_cell_nodes"].ptr,
+                         (const int*)ctx->bufs["nnb_cell_of"].ptr, P.ncx, P.ncy, P.ncz};
+    const unsigned nbk = (unsigned)((n + kBlock - 1) / kBlock);
+    int* nbr_m = nb.nbr + (int64_t)o * kSlots;
+    k_knn<<<nbk, kBlock, 0, ctx->stream>>>(n, band_dev(band), cells, nbr_m);
+    k_geom<<<nbk, kBlock, 0, ctx->stream>>>(n, band_dev(band), band->phi, d.eps, nbr_m, nb.feat + (int64_t)o * 5);
+    k_batch_geometry<<<nbk, kBlock, 0, ctx->stream>>>(n, o, band_dev(band), nbr_m, nb.pos + 3 * (int64_t)o);
+    PB_TRY(launch_ok(ctx, "nn batch prepare"));
+  }
+  return PB_OK;
+}
+
+void nn_batch_apply(hipStream_t stream, const pb_nn* net, const NNBatch& nb, const double* V, double* Z, int64_t ldv,
+                    const int* kptr, int kmax, double lam1, double lam2) {
+  const int ntot = nb.ntot;
+  k_rms_batch<<<nb.n_mol, kBlock, 0, stream>>>(nb.n_mol, nb.off, nb.cnt, V, ldv, kptr, kmax, nb.s);
+  k_build_g1_batch<<<(unsigned)(((int64_t)ntot * kSlots + kBlock - 1) / kBlock), kBlock, 0, stream>>>(
+      ntot, nb.mol_of, nb.off, nb.cnt, nb.pos, nb.nbr, nb.feat, V, ldv, kptr, kmax, nb.s, nb.eps, nb.G1);
+  const unsigned nbl = (unsigned)((ntot + 63) / 64);
+  const uint16_t* wt = net->wt;
+  const float* prm = net->params;
+  k_layer_fwd<true, 16, 64, true><<<nbl, 256, 0, stream>>>(ntot, nb.G1, nullptr, nb.nbr, wt + wbf_off(0),
+                                                          prm + b_off(0), nb.X[1]);
+  k_layer_fwd<false, 64, 64, true><<<nbl, 256, 0, stream>>>(ntot, nullptr, nb.X[1], nb.nbr, wt + wbf_off(1),
+                                                           prm + b_off(1), nb.X[2]);
+  k_layer_fwd<false, 64, 64, true><<<nbl, 256, 0, stream>>>(ntot, nullptr, nb.X[2], nb.nbr, wt + wbf_off(2),
+                                                           prm + b_off(2), nb.X[3]);
+  k_layer_fwd<false, 64, 16, false><<<nbl, 256, 0, stream>>>(ntot, nullptr, nb.X[3], nb.nbr, wt + wbf_off(3),
+                                                            prm + b_off(3), nb.O);
+  k_apply_out_batch<<<(unsigned)((ntot + kBlock - 1) / kBlock), kBlock, 0, stream>>>(
+      ntot, nb.mol_of, nb.off, nb.cnt, V, Z, ldv, kptr, kmax, nb.O, nb.s, lam1, lam2);
+}
+
 }  // namespace pb
 
 // ---------------------------------------------------------------- C-ABI

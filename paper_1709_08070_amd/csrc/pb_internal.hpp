@@ -84,6 +84,8 @@ struct pb_ctx {
   int n_cu = 256;
   pb::MixedPlan mixed;
   std::map<int, int> far_cfg;          // autotuned far-field tile shape per band size
+  int sym_items_n = -1;                // band size the symmetric kernel's item list was built for
+  int sym_n_items = 0;
   std::map<int64_t, int> batch_cfg;    // the same for batches, per (nodes, molecules)
   hipStream_t batch_stream = nullptr;  // capture stream of the batched solve
   const void* nn_key = nullptr;        // band prepared for the learned preconditioner
@@ -126,6 +128,28 @@ F32Params f32params(const Derived& d, double sigma);
 // learned preconditioner (nn.hip)
 pb_status nn_prepare(pb_ctx* ctx, const pb_band* band, const Derived& d);
 pb_status nn_apply(pb_ctx* ctx, const pb_nn* net, const pb_band* band, const Derived& d, const double* v, double* p);
+// The same network over a batch of bands whose nodes are concatenated: molecule m owns nodes
+// [off[m], off[m] + cnt[m]) and vector entries [2·off[m], 2·off[m] + 2·cnt[m]) as [ψ | ψn].
+struct NNBatch {
+  int n_mol = 0, ntot = 0;
+  double eps = 0.0;
+  const int* mol_of = nullptr;  // node → molecule (caller-owned)
+  int* off = nullptr;           // per molecule, device
+  int* cnt = nullptr;
+  double* pos = nullptr;        // ntot × 3 projections
+  int* nbr = nullptr;           // ntot × 16 neighbour slots, global node indices
+  float* feat = nullptr;        // ntot × 5 node features
+  double* s = nullptr;          // per molecule: RMS of the two halves of the input
+  uint16_t* G1 = nullptr;
+  float* X[4] = {};
+  float* O = nullptr;
+};
+pb_status nn_batch_prepare(pb_ctx* ctx, int n_mol, const pb_band* bands, const int* off_host, const int* mol_of,
+                           const Derived& d, NNBatch& nb);
+// Z[k] = M(V[k]) for every molecule, k = *kptr (or k = 0 with kptr null); launches only, on
+// `stream` (it may be under graph capture). Kernels return early once *kptr ≥ kmax.
+void nn_batch_apply(hipStream_t stream, const pb_nn* net, const NNBatch& nb, const double* V, double* Z, int64_t ldv,
+                    const int* kptr, int kmax, double lam1, double lam2);
 pb_status matvec_mixed(pb_ctx* ctx, const pb_band* band, const Derived& d, const double* p, double* y);
 pb_status rhs(pb_ctx* ctx, const pb_band* band, const double* atoms, int n_atoms, const Derived& d, double* g);
 

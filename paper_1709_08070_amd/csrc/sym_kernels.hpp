@@ -1,0 +1,275 @@
+// Symmetric FP32 far field: every unordered pair {i, j} is evaluated once and contributes to
+// both i and j.
+//
+// The four kernels of the IBIM operator (eq. IBIM-PBE with the regularized kernels of the
+// section "Regularization of the singular kernels") depend on the pair through d = x_i − x_j,
+// the two normals and the two weights. r, e^{−κr}, a = e^{−κr}(1 + κr), the θ factors and
+// e^{−κr}(κr)² − 3(1 − a) are the same for (i, j) and (j, i); only the dot products with the
+// normals and weights differ (d → −d). Evaluating both directions together shares those
+// terms: 56 FP32 operations and 2 transcendentals per unordered pair, i.e. 28 + 1 per
+// ordered pair, against 36 + 2 for one direction at a time.
+//
+// Work decomposition. The band is cut into chunks of C = 512·nsub nodes (nC chunks). One
+// work item is a chunk pair (Ic, Jc) with Ic ≤ Jc; the partial sums keep the chunked layout
+// of the one-directional kernel, partial[c][e] = contributions to vector entry e from the
+// sources of chunk c. Item (Ic, Jc), Ic < Jc, owns the slots (Jc, i ∈ Ic) (forward) and
+// (Ic, j ∈ Jc) (reverse); the diagonal item (Ic, Ic) owns (Ic, i ∈ Ic). Every slot belongs to
+// exactly one item, which zeroes it and then accumulates into it in FP64 in a fixed order, so
+// the result is bitwise reproducible and needs no atomics in global memory.
+//
+// Inside an item the block (256 threads, 4 waves) walks sub-blocks of 512 nodes: targets T
+// (2 per thread), sources S staged in LDS. For T ≠ S, lane l of a wave pairs its targets with
+// source g·64 + ((l + s) mod 64) at step s, so the 64 lanes touch 64 different sources. The
+// reverse sums travel with their source: after each step every lane passes its running sums
+// to lane l − 1 (ds_bpermute), which takes that source at the next step; after 64 steps lane
+// l holds the sums of source g·64 + l, accumulated in a fixed order. For T = S (only in
+// diagonal items; it holds the self pair and the nearest pairs) the one-directional loop with
+// the near-pair predicate runs.
+// Sub-block pairs whose bounding boxes are farther apart than r_c (with the margin of
+// F32Params::far2) skip the predicate.
+#pragma once
+
+#include "pair_kernels.hpp"
+
+namespace pb {
+
+constexpr int kSymSub = 512;  // nodes per sub-block
+constexpr int kSymWaves = kBlock / 64;
+
+struct SymShared {
+  float4 sA[kSymSub], sM[kSymSub], sN[kSymSub];
+  float racc[kSymWaves][2][kSymSub];
+};
+
+// Both directions of one pair. Target side (i): ta = (x_i, w̃n_i), tm = M_i, tn = n_i; source
+// side (j): sa, sm, sn. fa1/fa2 accumulate the contributions to i, ra1/ra2 those to j. With
+// d = x_i − x_j the reverse direction has d' = −d, so (d'·n_j) = −(d·n_j), (d'·M_i) = −(d·M_i)
+// and their product keeps its sign.
+template <bool kScreened, bool kCheck>
+__device__ __forceinline__ void pair_sym(const float4& ta, const float4& tm, const float4& tn, const float4& sa,
+                                         const float4& sm, const float4& sn, const F32Params& fp, float& fa1,
+                                         float& fa2, float& ra1, float& ra2) {
+  const float dx = ta.x - sa.x, dy = ta.y - sa.y, dz = ta.z - sa.z;
+  const float r2 = r2_f32(ta.x, ta.y, ta.z, sa.x, sa.y, sa.z);
+  float rinv = __builtin_amdgcn_rsqf(r2);
+  if (kCheck && r2 < fp.rc2) rinv = 0.f;
+  float E = 1.f, Ez = 0.f, z = 0.f;
+  if (kScreened) {
+    z = r2 * rinv;
+    E = __builtin_amdgcn_exp2f(fp.mlog2e * z);
+    Ez = E * z;
+  }
+  const float a = E + Ez;
+  const float ri2 = rinv * rinv;
+  const float r3 = ri2 * rinv;
+  const float c1 = __fmaf_rn(-fp.th1, a, 1.f);
+  const float c2 = __fmaf_rn(-fp.th2, a, 1.f);
+  // i ← j
+  const float dnx = __fmaf_rn(dz, tn.z, __fmaf_rn(dy, tn.y, dx * tn.x));
+  const float D = __fmaf_rn(dz, sm.z, __fmaf_rn(dy, sm.y, dx * sm.x));
+  // j ← i
+  const float dny = __fmaf_rn(dz, sn.z, __fmaf_rn(dy, sn.y, dx * sn.x));
+  const float Di = __fmaf_rn(dz, tm.z, __fmaf_rn(dy, tm.y, dx * tm.x));
+  fa1 = __fmaf_rn(c1 * D, r3, fa1);
+  ra1 = __fmaf_rn(-(c1 * Di), r3, ra1);
+  if (kScreened) {
+    const float Nw = __fmaf_rn(tn.z, sm.z, __fmaf_rn(tn.y, sm.y, tn.x * sm.x));
+    const float Nw2 = __fmaf_rn(sn.z, tm.z, __fmaf_rn(sn.y, tm.y, sn.x * tm.x));
+    const float g = __fmaf_rn(Ez, z, __fmaf_rn(3.f, a, -3.f));
+    fa1 = __fmaf_rn(-__fmaf_rn(-E, sa.w, sa.w), rinv, fa1);
+    ra1 = __fmaf_rn(-__fmaf_rn(-E, ta.w, ta.w), rinv, ra1);
+    float t = __fmaf_rn(-a, Nw, Nw);
+    t = __fmaf_rn(c2 * dnx, sa.w, t);
+    t = __fmaf_rn(dnx * D * ri2, g, t);
+    float u = __fmaf_rn(-a, Nw2, Nw2);
+    u = __fmaf_rn(-(c2 * dny), ta.w, u);
+    u = __fmaf_rn(dny * Di * ri2, g, u);
+    fa2 = __fmaf_rn(t, r3, fa2);
+    ra2 = __fmaf_rn(u, r3, ra2);
+  } else {  // κ = 0: E = a = 1 and z = 0, so only the θ terms remain
+    fa2 = __fmaf_rn(c2 * dnx * sa.w, r3, fa2);
+    ra2 = __fmaf_rn(-(c2 * dny * ta.w), r3, ra2);
+  }
+}
+
+// Targets [t0, t0 + 512) (full, 2 per thread) against sources [s0, s0 + 512) of the same
+// records, s0 ≠ t0, both directions. Adds σ·S1, σ²·S2 into fwd (index i − t0) and rev (index
+// j − s0). Every thread of the block calls it (it synchronizes).
+template <bool kScreened, bool kCheck>
+__device__ __forceinline__ void sym_block(const float4* __restrict__ A, const float4* __restrict__ M,
+                                          const float4* __restrict__ N, int n, int t0, int s0, const F32Params& fp,
+                                          double sig1, double sig2, SymShared& sh, double* fwd1, double* fwd2,
+                                          double* rev1, double* rev2) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int q = tid; q < kSymSub; q += kBlock) {
+    const int j = s0 + q;
+    if (j < n) {
+      sh.sA[q] = A[j];
+      sh.sM[q] = M[j];
+      sh.sN[q] = N[j];
+    } else {  // padding: zero weights and normals (such tiles run with the predicate)
+      sh.sA[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+      sh.sM[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+      sh.sN[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  }
+  const int ia = t0 + w * 128 + lane, ib = ia + 64;
+  const float4 taa = A[ia], tma = M[ia], tna = N[ia];
+  const float4 tab = A[ib], tmb = M[ib], tnb = N[ib];
+  __syncthreads();
+  double fa1d = 0.0, fa2d = 0.0, fb1d = 0.0, fb2d = 0.0;
+  const int next = ((lane + 1) & 63) << 2;  // byte address of lane l + 1 for ds_bpermute
+  for (int g = 0; g < kSymSub; g += 64) {
+    float fa1 = 0.f, fa2 = 0.f, fb1 = 0.f, fb2 = 0.f;
+    float ra1 = 0.f, ra2 = 0.f;  // at step s: the reverse sums of source g + ((lane + s) mod 64)
+#pragma unroll 2
+    for (int s = 0; s < 64; ++s) {
+      const int q = g + ((lane + s) & 63);
+      const float4 sa = sh.sA[q], sm = sh.sM[q], sn = sh.sN[q];
+      pair_sym<kScreened, kCheck>(taa, tma, tna, sa, sm, sn, fp, fa1, fa2, ra1, ra2);
+      pair_sym<kScreened, kCheck>(tab, tmb, tnb, sa, sm, sn, fp, fb1, fb2, ra1, ra2);
+      ra1 = __int_as_float(__builtin_amdgcn_ds_bpermute(next, __float_as_int(ra1)));
+      ra2 = __int_as_float(__builtin_amdgcn_ds_bpermute(next, __float_as_int(ra2)));
+    }
+    sh.racc[w][0][g + lane] = ra1;  // 64 rotations: lane l holds source g + l
+    sh.racc[w][1][g + lane] = ra2;
+    fa1d += (double)fa1;
+    fa2d += (double)fa2;
+    fb1d += (double)fb1;
+    fb2d += (double)fb2;
+  }
+  __syncthreads();
+  fwd1[ia - t0] += sig1 * fa1d;
+  fwd2[ia - t0] += sig2 * fa2d;
+  fwd1[ib - t0] += sig1 * fb1d;
+  fwd2[ib - t0] += sig2 * fb2d;
+  for (int q = tid; q < kSymSub; q += kBlock) {
+    if (s0 + q < n) {
+      double x1 = 0.0, x2 = 0.0;
+      for (int v = 0; v < kSymWaves; ++v) {
+        x1 += (double)sh.racc[v][0][q];
+        x2 += (double)sh.racc[v][1][q];
+      }
+      rev1[q] += sig1 * x1;
+      rev2[q] += sig2 * x2;
+    }
+  }
+  __syncthreads();
+}
+
+// Targets [t0, t0 + 512) against the sources of the same sub-block, one direction, with the
+// near-pair predicate (the self pair and the nearest pairs are here). Adds into fwd.
+template <bool kScreened>
+__device__ __forceinline__ void diag_block(const float4* __restrict__ A, const float4* __restrict__ M,
+                                           const float4* __restrict__ N, int n, int t0, const F32Params& fp,
+                                           double sig1, double sig2, SymShared& sh, double* fwd1, double* fwd2) {
+  const int tid = threadIdx.x;
+  for (int q = tid; q < kSymSub; q += kBlock) {
+    const int j = t0 + q;
+    if (j < n) {
+      sh.sA[q] = A[j];
+      sh.sM[q] = M[j];
+    } else {
+      sh.sA[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+      sh.sM[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  }
+  const int ia = t0 + tid, ib = ia + kBlock;
+  const float4 taa = ia < n ? A[ia] : make_float4(0.f, 0.f, 0.f, 0.f);
+  const float4 tna = ia < n ? N[ia] : make_float4(0.f, 0.f, 1.f, 0.f);
+  const float4 tab = ib < n ? A[ib] : make_float4(0.f, 0.f, 0.f, 0.f);
+  const float4 tnb = ib < n ? N[ib] : make_float4(0.f, 0.f, 1.f, 0.f);
+  __syncthreads();
+  double fa1d = 0.0, fa2d = 0.0, fb1d = 0.0, fb2d = 0.0;
+  for (int g = 0; g < kSymSub; g += 64) {
+    float fa1 = 0.f, fa2 = 0.f, fb1 = 0.f, fb2 = 0.f;
+#pragma unroll 4
+    for (int q = g; q < g + 64; ++q) {
+      const float4 sa = sh.sA[q], sm = sh.sM[q];
+      pair_f32<kScreened, true>(taa, tna, sa, sm, fp, fa1, fa2);
+      pair_f32<kScreened, true>(tab, tnb, sa, sm, fp, fb1, fb2);
+    }
+    fa1d += (double)fa1;
+    fa2d += (double)fa2;
+    fb1d += (double)fb1;
+    fb2d += (double)fb2;
+  }
+  if (ia < n) {
+    fwd1[ia - t0] += sig1 * fa1d;
+    fwd2[ia - t0] += sig2 * fa2d;
+  }
+  if (ib < n) {
+    fwd1[ib - t0] += sig1 * fb1d;
+    fwd2[ib - t0] += sig2 * fb2d;
+  }
+  __syncthreads();
+}
+
+// One work item (Ic, Jc), Ic ≤ Jc, of a band of n records with chunks of nsub sub-blocks.
+// partial: the band's chunked partial sums (slot (c, e) at partial[c·2n + e]).
+template <bool kScreened>
+__device__ __forceinline__ void sym_item(const float4* __restrict__ A, const float4* __restrict__ M,
+                                         const float4* __restrict__ N, const float4* __restrict__ box, int n,
+                                         int Ic, int Jc, int nsub, const F32Params& fp, double sig1, double sig2,
+                                         double* __restrict__ partial, SymShared& sh) {
+  const int C = nsub * kSymSub;
+  const int i0 = Ic * C, i1 = min(n, i0 + C), j0 = Jc * C, j1 = min(n, j0 + C);
+  double* rowF = partial + (int64_t)Jc * 2 * n;  // slots (Jc, i): contributions of chunk Jc
+  double* rowR = partial + (int64_t)Ic * 2 * n;  // slots (Ic, j): contributions of chunk Ic
+  for (int e = threadIdx.x; e < i1 - i0; e += kBlock) {
+    rowF[i0 + e] = 0.0;
+    rowF[n + i0 + e] = 0.0;
+  }
+  if (Ic != Jc)
+    for (int e = threadIdx.x; e < j1 - j0; e += kBlock) {
+      rowR[j0 + e] = 0.0;
+      rowR[n + j0 + e] = 0.0;
+    }
+  __syncthreads();
+  for (int T = i0; T < i1; T += kSymSub) {
+    float4 tlo, thi;
+    box_union(box, T / kGroup, min(T + kSymSub, n + kGroup - 1) / kGroup, tlo, thi);
+    for (int S = (Ic == Jc ? T : j0); S < j1; S += kSymSub) {
+      if (S == T) {
+        diag_block<kScreened>(A, M, N, n, T, fp, sig1, sig2, sh, rowF + T, rowF + n + T);
+        continue;
+      }
+      int clear = 0;
+      if (S + kSymSub <= n) {
+        float4 slo, shi;
+        box_union(box, S / kGroup, (S + kSymSub) / kGroup, slo, shi);
+        clear = box_gap2(tlo, thi, slo, shi) >= fp.far2;
+      }
+      clear = __builtin_amdgcn_readfirstlane(clear);
+      if (clear)
+        sym_block<kScreened, false>(A, M, N, n, T, S, fp, sig1, sig2, sh, rowF + T, rowF + n + T, rowR + S,
+                                    rowR + n + S);
+      else
+        sym_block<kScreened, true>(A, M, N, n, T, S, fp, sig1, sig2, sh, rowF + T, rowF + n + T, rowR + S,
+                                   rowR + n + S);
+    }
+  }
+}
+
+// Symmetric FP32 far field of one band: one block per work item (items: (Ic, Jc) pairs).
+template <bool kScreened>
+static __global__ void __attribute__((unused)) __launch_bounds__(kBlock)
+    k_p2p_f32_sym(const float4* __restrict__ A, const float4* __restrict__ M, const float4* __restrict__ N,
+                  const float4* __restrict__ box, int n, int nsub, const int2* __restrict__ items, int n_items,
+                  F32Params fp, double sig1, double sig2, double* __restrict__ partial) {
+  __shared__ SymShared sh;
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int2 w = items[it];
+    sym_item<kScreened>(A, M, N, box, n, w.x, w.y, nsub, fp, sig1, sig2, partial, sh);
+  }
+}
+
+// Chunking of a band of n nodes for the symmetric kernel: about 100 chunks (≈5000 items)
+// for large bands, chunks of one sub-block for small ones.
+inline int sym_nsub(int n) { return std::max(1, (n + 100 * kSymSub - 1) / (100 * kSymSub)); }
+inline int sym_chunks(int n) {
+  const int C = sym_nsub(n) * kSymSub;
+  return (n + C - 1) / C;
+}
+
+}  // namespace pb

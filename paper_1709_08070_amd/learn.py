@@ -33,7 +33,8 @@ def smooth_field(band: pb.Band, rng: np.random.Generator, n_bumps: int = 8) -> t
     return torch.cat(out)
 
 
-def make_example(ctx: pb.Context, n_atoms: int, seed: int, h: float, n_random: int, rng: np.random.Generator):
+def make_example(ctx: pb.Context, n_atoms: int, seed: int, h: float, n_random: int, rng: np.random.Generator,
+                 tol: float = 1e-8):
     """One molecule: (prm, band, list of (v, u) pairs)."""
     atoms = synth.globule(n_atoms, seed)
     prm = pb.params(h, ls_mode=pb.PB_LS_SES)
@@ -42,7 +43,7 @@ def make_example(ctx: pb.Context, n_atoms: int, seed: int, h: float, n_random: i
     phi = pb.pb_build_levelset(ctx, at, prm, grid)
     band = pb.pb_narrowband_compact(ctx, grid, phi, prm)
     g = pb.pb_ibim_rhs(ctx, band, at, prm)
-    u, st = pb.pb_ibim_solve(ctx, band, at, prm, pb.solve_opts(tol=1e-8, precision=pb.PB_MIXED))
+    u, st = pb.pb_ibim_solve(ctx, band, at, prm, pb.solve_opts(tol=tol, precision=pb.PB_MIXED))
     pairs = [(g, u)]
     for _ in range(n_random):
         e = smooth_field(band, rng)
@@ -51,19 +52,23 @@ def make_example(ctx: pb.Context, n_atoms: int, seed: int, h: float, n_random: i
 
 
 def train(ctx: pb.Context, net: pb.Net, n_mol: int = 2000, lo: int = 200, hi: int = 1500, h: float = 0.5,
-          seed0: int = 100000, epochs: int = 2, lr: float = 1e-3, n_random: int = 1, log=None) -> dict:
-    """Builds the training set (n_mol molecules, atom counts uniform in [lo, hi]) and trains."""
+          seed0: int = 100000, epochs: int = 2, lr: float = 1e-3, n_random: int = 1, log=None,
+          tol: float = 1e-8) -> dict:
+    """Builds the training set (n_mol molecules, atom counts uniform in [lo, hi], seeds
+    seed0 + i) and trains."""
     rng = np.random.default_rng(seed0)
     t0 = time.perf_counter()
     data = []
     for i in range(n_mol):
         na = int(rng.integers(lo, hi + 1))
-        data.append(make_example(ctx, na, seed0 + i, h, n_random, rng))
+        data.append(make_example(ctx, na, seed0 + i, h, n_random, rng, tol))
         if log and (i + 1) % max(1, n_mol // 10) == 0:
             log(f"training set: {i + 1}/{n_mol} molecules")
     t_data = time.perf_counter() - t0
     t1 = time.perf_counter()
     history = []
+    total = epochs * sum(len(pairs) for _, _, pairs in data)
+    done = 0
     for ep in range(epochs):
         order = rng.permutation(len(data))
         tot, cnt = 0.0, 0
@@ -71,11 +76,53 @@ def train(ctx: pb.Context, net: pb.Net, n_mol: int = 2000, lo: int = 200, hi: in
             prm, band, pairs = data[k]
             pb.pb_nn_prepare(ctx, band, prm)
             for v, u in pairs:
-                step_lr = lr * 0.5 * (1 + math.cos(math.pi * (ep + cnt / max(1, len(data))) / epochs))
+                step_lr = lr * 0.5 * (1 + math.cos(math.pi * done / max(1, total)))  # cosine decay over all steps
+                done += 1
                 tot += pb.pb_nn_train_step(ctx, net, band, prm, v, u, step_lr)
                 cnt += 1
+                if log and cnt % 1000 == 0:
+                    log(f"epoch {ep}: {cnt} steps, mean loss so far {tot / cnt:.4f}")
         history.append(tot / max(cnt, 1))
         if log:
             log(f"epoch {ep}: mean loss {history[-1]:.4f}")
     return {"molecules": n_mol, "epochs": epochs, "t_data_s": t_data, "t_train_s": time.perf_counter() - t1,
             "loss": history}
+
+
+def main(argv=None):
+    """Trains the network on generated molecules and saves its weights (and a JSON record of
+    the run beside them)."""
+    import argparse
+    import json
+    import sys
+
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--molecules", type=int, default=2000)
+    ap.add_argument("--lo", type=int, default=200)
+    ap.add_argument("--hi", type=int, default=1500)
+    ap.add_argument("--h", type=float, default=0.5)
+    ap.add_argument("--seed0", type=int, default=100000)
+    ap.add_argument("--epochs", type=int, default=2)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--tol", type=float, default=1e-7, help="tolerance of the solves that give the targets")
+    ap.add_argument("--net-seed", type=int, default=1)
+    ap.add_argument("--out", required=True)
+    args = ap.parse_args(argv)
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    ctx = pb.Context(0)
+    net = pb.Net(ctx, seed=args.net_seed)
+    info = train(ctx, net, n_mol=args.molecules, lo=args.lo, hi=args.hi, h=args.h, seed0=args.seed0,
+                 epochs=args.epochs, lr=args.lr, log=log, tol=args.tol)
+    net.save(args.out)
+    info.update({k: getattr(args, k) for k in ("lo", "hi", "h", "seed0", "lr", "tol", "net_seed")})
+    with open(args.out.rsplit(".", 1)[0] + ".json", "w") as f:
+        json.dump(info, f, indent=1)
+    log(f"saved {args.out}: loss per epoch {info['loss']}, data {info['t_data_s']:.0f} s, "
+        f"training {info['t_train_s']:.0f} s")
+
+
+if __name__ == "__main__":
+    main()

@@ -29,7 +29,7 @@ EXPORTS = [
     "pb_grid_for_atoms", "pb_build_levelset", "pb_narrowband_compact", "pb_ibim_rhs", "pb_ibim_matvec",
     "pb_ibim_solve", "pb_solvation_energy", "pb_set_timing", "pb_kernel_time", "pb_ibim_solve_batched",
     "pb_nn_create", "pb_nn_destroy", "pb_nn_param_count", "pb_nn_get_params", "pb_nn_set_params", "pb_nn_prepare",
-    "pb_nn_apply", "pb_nn_train_step", "pb_nn_geometry",
+    "pb_nn_apply", "pb_nn_train_step", "pb_nn_geometry", "pb_far_kernel",
 ]
 
 
@@ -63,7 +63,7 @@ class pb_solve_stats(C.Structure):
 class pb_batch_stats(C.Structure):
     _fields_ = [("t_total_s", C.c_double), ("t_p50_s", C.c_double), ("t_p99_s", C.c_double), ("pairs", C.c_double),
                 ("graph_replays", C.c_int), ("far_tile", C.c_int), ("far_tpl", C.c_int), ("n_items", C.c_int),
-                ("outer", C.c_int), ("reserved", C.c_int)]
+                ("outer", C.c_int), ("far_symmetric", C.c_int)]
 
 
 class pb_energy(C.Structure):
@@ -113,6 +113,7 @@ def load(path: str = LIB_PATH):
     L.pb_nn_geometry.argtypes = [vp, P(pb_band), vp, vp]
     L.pb_set_timing.argtypes = [vp, C.c_int]
     L.pb_kernel_time.argtypes = [vp, C.c_char_p, P(C.c_double), P(C.c_int64)]
+    L.pb_far_kernel.argtypes = [vp, C.c_int64, P(C.c_int)]
     for name in EXPORTS:
         if name not in ("pb_destroy", "pb_last_error", "pb_default_params", "pb_default_solve_opts", "pb_nn_destroy",
                         "pb_nn_param_count"):
@@ -179,6 +180,11 @@ class Context:
         ms, cnt = C.c_double(), C.c_int64()
         self.check(lib.pb_kernel_time(self.handle, name.encode(), C.byref(ms), C.byref(cnt)))
         return ms.value, cnt.value
+
+    def far_kernel(self, n: int) -> int:
+        cfg = C.c_int()
+        self.check(lib.pb_far_kernel(self.handle, int(n), C.byref(cfg)))
+        return cfg.value
 
 
 @dataclass

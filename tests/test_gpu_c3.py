@@ -1,0 +1,107 @@
+"""GPU parity at full size: the 5000-atom globule at h = 0.25 (about 0.8M band nodes), the
+largest single-molecule workload, in the launch configuration bench.py times.
+
+The oracle cannot rerun the level set of a 14M-node grid in test time, so parity at this
+size rests on outputs it computes one by one from the GPU's own inputs:
+  * band compaction of the GPU level set by the oracle: node order and indices bit-exact,
+    node values to 1e-12;
+  * 64 sampled operator rows (FP64 path: 1e-10 of max|y|; mixed path: 1e-5 relative, with
+    the autotuner's far-field kernel and with the symmetric and one-directional ones forced);
+  * the mixed solve to 1e-6: its residual on the sampled rows recomputed by the oracle
+    (1e-5 relative), and the energy of its solution recomputed by the oracle (1e-10).
+The level-set kernels are compared node by node with the oracle at the smaller sizes of
+test_gpu_parity.py.
+"""
+import os
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1709_08070_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pbm():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1709_08070_amd import pb
+
+    return pb
+
+
+def test_globule5000_sampled(pbm):
+    import torch
+
+    t0 = time.perf_counter()
+    say("case: globule 5000 atoms seed 5000 h=0.25 SES (sampled rows)")
+    ctx = pbm.Context(0)
+    atoms = synth.globule(5000, 5000)
+    prm = pbm.params(0.25, ls_mode=pbm.PB_LS_SES)
+    grid = pbm.pb_grid_for_atoms(atoms, prm)
+    at = torch.tensor(atoms, dtype=torch.float64, device="cuda")
+    phi = pbm.pb_build_levelset(ctx, at, prm, grid)
+    band = pbm.pb_narrowband_compact(ctx, grid, phi, prm)
+    n = band.n
+    say(f"grid {grid.nx}x{grid.ny}x{grid.nz}, band nodes {n}, {time.perf_counter() - t0:.1f}s")
+    # compaction of the GPU level set by the oracle
+    dims, origin = (grid.nx, grid.ny, grid.nz), tuple(grid.origin)
+    onodes, ogidx = oracle.band(dims, origin, 0.25, phi.cpu().numpy(), 0.5)
+    assert n == len(onodes)
+    np.testing.assert_array_equal(band.gidx[:n].cpu().numpy(), ogidx)
+    nodes = band.table()
+    assert np.max(np.abs(nodes - onodes)) <= 1e-12 * max(1.0, np.max(np.abs(onodes)))
+    say(f"band matches the oracle, {time.perf_counter() - t0:.1f}s")
+    # sampled operator rows
+    oprm = oracle.params(0.25)
+    rows = np.random.default_rng(3).choice(n, 64, replace=False)
+    p = np.random.default_rng(4).normal(size=2 * n)
+    pt = torch.tensor(p, device="cuda")
+    y1, y2 = oracle.matvec_rows(nodes, oprm, p, rows)
+    ref = np.concatenate([y1, y2])
+    y = pbm.pb_ibim_matvec(ctx, band, prm, pt).cpu().numpy()
+    got = np.concatenate([y[rows], y[n + rows]])
+    assert np.max(np.abs(got - ref)) < 1e-10 * np.max(np.abs(ref))
+    ym = pbm.pb_ibim_matvec(ctx, band, prm, pt, pbm.PB_MIXED).cpu().numpy()
+    gm = np.concatenate([ym[rows], ym[n + rows]])
+    rel = np.linalg.norm(gm - ref) / np.linalg.norm(ref)
+    say(f"sampled rows: FP64 ok, mixed rel err {rel:.3e}, {time.perf_counter() - t0:.1f}s")
+    assert rel < 1e-5
+    # both far-field kernels explicitly: symmetric (13 sub-blocks per chunk here) and tiled
+    for cfg in ("4", "2"):
+        os.environ["PB_FAR_CFG"] = cfg
+        try:
+            c2 = pbm.Context(0)
+            yk = pbm.pb_ibim_matvec(c2, band, prm, pt, pbm.PB_MIXED).cpu().numpy()
+            c2.close()
+        finally:
+            del os.environ["PB_FAR_CFG"]
+        gk = np.concatenate([yk[rows], yk[n + rows]])
+        relk = np.linalg.norm(gk - ref) / np.linalg.norm(ref)
+        say(f"far-field kernel {cfg}: sampled rel err {relk:.3e}")
+        assert relk < 1e-5
+    # mixed solve to 1e-6, checked by the oracle on the sampled rows and through the energy
+    sol, st = pbm.pb_ibim_solve(ctx, band, at, prm, pbm.solve_opts(tol=1e-6, precision=pbm.PB_MIXED))
+    say(f"mixed solve: iters={st.iters} outer={st.outer} relres={st.true_relres:.2e} {st.t_total_s:.1f}s")
+    assert st.converged and st.true_relres <= 1e-6
+    s = sol.cpu().numpy()
+    g = oracle.rhs(nodes, atoms, oprm)
+    a1, a2 = oracle.matvec_rows(nodes, oprm, s, rows)
+    res = np.concatenate([a1 - g[rows], a2 - g[n + rows]])
+    assert np.linalg.norm(res) / np.linalg.norm(np.concatenate([g[rows], g[n + rows]])) < 1e-5
+    e_gpu = pbm.pb_solvation_energy(ctx, band, at, prm, sol).g_pol
+    oE, _ = oracle.energy(nodes, atoms, oprm, s)
+    say(f"energy gpu {e_gpu:.12e} oracle {oE:.12e}, {time.perf_counter() - t0:.1f}s")
+    assert e_gpu == pytest.approx(oE, rel=1e-10)
+    ctx.close()

@@ -141,10 +141,9 @@ def _training_set(pbm, ctx, seeds, sizes):
     return data
 
 
-def test_training_and_gain(pbm, ctx):
-    import torch
-
-    say("case: nn training on 12 globules (40-120 atoms), held-out 2 globules (150 atoms)")
+@pytest.fixture(scope="module")
+def trained(pbm, ctx):
+    say("case: nn training on 12 globules (40-120 atoms)")
     rng = np.random.default_rng(11)
     train = _training_set(pbm, ctx, list(range(9100, 9112)), list(rng.integers(40, 121, 12)))
     net = pbm.Net(ctx, seed=3)
@@ -153,6 +152,11 @@ def test_training_and_gain(pbm, ctx):
         for prm, at, band, g, u in train:
             pbm.pb_nn_prepare(ctx, band, prm)
             losses.append(pbm.pb_nn_train_step(ctx, net, band, prm, g, u, 2e-3))
+    return net, losses
+
+
+def test_training_and_gain(pbm, ctx, trained):
+    net, losses = trained
     first, last = np.mean(losses[:12]), np.mean(losses[-12:])
     say(f"loss first epoch {first:.4f} last epoch {last:.4f}")
     assert last < 0.7 * first
@@ -171,6 +175,56 @@ def test_training_and_gain(pbm, ctx):
         assert e1 == pytest.approx(e0, rel=1e-5)
         gains.append(st0.iters - st1.iters)
     assert min(gains) >= 0
+
+
+def test_batched_learned_matches_single(pbm, ctx, trained):
+    """The batched solve with the learned x0 and preconditioner (network over the
+    concatenated batch, applied inside the captured Arnoldi step) against single learned
+    solves and plain solves of the same molecules: same convergence, energies within the
+    tolerance, iteration counts within a few steps of the single learned solves (the
+    per-molecule RMS normalisation sums in another order, and the single solve's first pass
+    runs on g rather than on the FP64 residual), fewer steps than plain."""
+    net, _ = trained
+    say("case: batched learned solve, held-out globules 150/110/70 atoms seeds 9900-9902, h=0.5, tol 1e-6 and 1e-9")
+    mols = [_band(pbm, ctx, synth.globule(na, s)) for na, s in ((150, 9900), (110, 9901), (70, 9902))]
+    bands = [b for _, _, b in mols]
+    ats = [a for _, a, _ in mols]
+    prm = mols[0][0]
+    for tol in (1e-6, 1e-9):
+        lopts = pbm.solve_opts(tol=tol, precision=pbm.PB_MIXED, x0=pbm.PB_X0_LEARNED,
+                               precond=pbm.PB_PRECOND_LEARNED, nn=net.handle)
+        ps, stats, bst = pbm.pb_ibim_solve_batched(ctx, bands, ats, prm, lopts)
+        ps0, stats0, bst0 = pbm.pb_ibim_solve_batched(ctx, bands, ats, prm, pbm.solve_opts(tol=tol, precision=pbm.PB_MIXED))
+        say(f"tol {tol:g}: learned replays {bst.graph_replays} outer {bst.outer}; plain replays {bst0.graph_replays}")
+        for i, (b, at) in enumerate(zip(bands, ats)):
+            st, st0 = stats[i], stats0[i]
+            q, st1 = pbm.pb_ibim_solve(ctx, b, at, prm, lopts)
+            e_b = pbm.pb_solvation_energy(ctx, b, at, prm, ps[i]).g_pol
+            e_1 = pbm.pb_solvation_energy(ctx, b, at, prm, q).g_pol
+            e_0 = pbm.pb_solvation_energy(ctx, b, at, prm, ps0[i]).g_pol
+            say(f"  mol {i}: n={b.n} batch learned iters {st.iters} fallback {st.fallback_used} relres "
+                f"{st.true_relres:.2e}; single learned iters {st1.iters}; batch plain iters {st0.iters}; "
+                f"energies {e_b:.10e} {e_1:.10e} {e_0:.10e}")
+            assert st.converged and st.true_relres <= tol and not st.fallback_used
+            assert e_b == pytest.approx(e_1, rel=max(10 * tol, 1e-8))
+            assert e_b == pytest.approx(e_0, rel=max(10 * tol, 1e-8))
+            assert abs(st.iters - st1.iters) <= max(3, 0.15 * st1.iters)
+        assert bst.graph_replays < bst0.graph_replays
+
+
+def test_batched_learned_fallback(pbm, ctx, small):
+    """A useless network: the batched learned run misses the tolerance and every molecule is
+    finished by plain GMRES from its last iterate, reported as fallback."""
+    net = pbm.Net(ctx, seed=9)
+    net.set_params(_random_params(pbm, 10, scale_last=1.0) * 40.0)
+    say("case: batched learned fallback, globules 12/30 atoms seeds 21/22, useless network, tol 1e-8")
+    m2 = _band(pbm, ctx, synth.globule(30, 22))
+    bands, ats = [small["band"], m2[2]], [small["at"], m2[1]]
+    ps, stats, bst = pbm.pb_ibim_solve_batched(ctx, bands, ats, small["prm"], pbm.solve_opts(
+        tol=1e-8, precision=pbm.PB_MIXED, precond=pbm.PB_PRECOND_LEARNED, nn=net.handle, max_iter=60))
+    for i, st in enumerate(stats):
+        say(f"  mol {i}: fallback {st.fallback_used} iters {st.iters} relres {st.true_relres:.2e}")
+        assert st.converged and st.true_relres <= 1e-8
 
 
 def test_fallback_to_plain_gmres(pbm, ctx, small):

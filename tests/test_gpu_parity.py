@@ -6,8 +6,8 @@ globule through the whole SES pipeline (several 256-node tiles and a ragged tail
 
 Bars: integer work (band selection, node order) bit-exact; FP64 operator 1e-12 relative
 (2-norm) and 1e-10 of max|y| elementwise — the two sides sum in different orders;
-FP64 solves 1e-8 relative energy; the mixed path 1e-6 relative energy (the spec bar
-is 1e-4); level-set values 1e-10 absolute.
+FP64 solves 1e-8 relative energy; the mixed path 1e-6 relative energy (its stated
+tolerance is 1e-4); level-set values 1e-10 absolute.
 """
 import math
 import sys
