@@ -170,7 +170,9 @@ pb_status pb_ibim_rhs(pb_ctx* ctx, const pb_band* band, const double* atoms, int
    fixes it instead: k = 0..3 the one-directional kernel with (sources per LDS tile, targets
    per lane) = (256, 1), (512, 1), (256, 2), (512, 2); k = 4 the symmetric kernel (each
    unordered pair evaluated once for both directions). All give the same operator up to
-   FP32 rounding; each is bitwise reproducible from run to run. */
+   FP32 rounding; each is bitwise reproducible from run to run.
+   PB_FP64: the same choice between the one-directional kernel (PB_F64_CFG=0) and the
+   symmetric one (PB_F64_CFG=1), which evaluates the regularization test per direction. */
 pb_status pb_ibim_matvec(pb_ctx* ctx, const pb_band* band, const pb_params* prm, int precision, const double* p,
                          double* y);
 

@@ -35,6 +35,7 @@
 #include <vector>
 
 #include "pair_kernels.hpp"
+#include "sym64_kernels.hpp"
 #include "sym_kernels.hpp"
 
 namespace pb {
@@ -132,6 +133,22 @@ static __global__ void __launch_bounds__(kBlock) k_far32_sym_batch(const Item* _
   }
 }
 
+// Symmetric FP64 operator of every selected molecule: items (molecule, Ic, Jc), persistent.
+static __global__ void __launch_bounds__(kBlock) k_far64_sym_batch(const Item* __restrict__ items, int n_items,
+                                                                   const MolDev* __restrict__ mols,
+                                                                   const int* __restrict__ active,
+                                                                   const double* __restrict__ wpsi,
+                                                                   const double* __restrict__ wpsn, KParams kp,
+                                                                   double* __restrict__ partial) {
+  __shared__ Sym64Shared sh;
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const Item w = items[it];
+    if (!active[w.mol]) continue;
+    const MolDev& m = mols[w.mol];
+    sym64_item(m.band, wpsi + m.off, wpsn + m.off, m.n, w.tb, w.ch, m.nsub, kp, partial + m.poffsym, sh);
+  }
+}
+
 static __global__ void __launch_bounds__(kBlock) k_weights_batch(int ntot, const int* __restrict__ mol_of,
                                                                  const MolDev* __restrict__ mols,
                                                                  const double* __restrict__ x, double scale,
@@ -166,7 +183,7 @@ static __global__ void __launch_bounds__(kBlock) k_far64_batch(const Item* __res
 }
 
 // Layout of the far-field partial sums read by k_reduce_batch.
-constexpr int kModeTiled = 0, kModeF64 = 1, kModeSym = 2;
+constexpr int kModeTiled = 0, kModeF64 = 1, kModeSym = 2, kModeF64Sym = 3;
 
 // y = Λx + Σ chunks (+ near), per molecule; x and y at step *kptr / *kptr + 1 of a basis
 // when kptr is given.
@@ -187,9 +204,10 @@ static __global__ void __launch_bounds__(kBlock) k_reduce_batch(int ntot, const 
   const double* xv = x + k * ldv;
   double* yv = y + (kptr ? (k + 1) * ldv : 0);
   const int l = g - m.off;
-  const bool use64 = mode == kModeF64;
-  const int S = use64 ? m.S64 : mode == kModeSym ? m.Ssym : m.S32;
-  const double* part = partial + (use64 ? m.poff64 : mode == kModeSym ? m.poffsym : m.poff32);
+  const bool use64 = mode == kModeF64 || mode == kModeF64Sym;  // the FP64 operator has no near field
+  const bool sym = mode == kModeSym || mode == kModeF64Sym;
+  const int S = sym ? m.Ssym : use64 ? m.S64 : m.S32;
+  const double* part = partial + (sym ? m.poffsym : use64 ? m.poff64 : m.poff32);
   double s1 = 0.0, s2 = 0.0;
   for (int c = 0; c < S; ++c) {
     s1 += part[(int64_t)c * 2 * m.n + l];
@@ -549,6 +567,8 @@ struct Batch {
   int n_items32[kNumCfgB] = {}, grid32[kNumCfgB] = {};
   Item* items64 = nullptr;
   int n_items64 = 0, grid64 = 0;
+  int grid64sym = 0;
+  int cfg64 = 0;  // FP64 operator kernel: 0 tiled, 1 symmetric (over items32[kSymB])
   double* partial = nullptr;  // far-field chunk sums of either path
   double* wpsi = nullptr;
   double* wpsn = nullptr;
@@ -662,14 +682,23 @@ std::vector<Item> make_sym_items(const std::vector<MolDev>& mols) {
   return out;
 }
 
+// FP64 far sums of the molecules in sel, with kernel cfg (0 tiled, 1 symmetric).
+void far64(Batch& B, int cfg, const int* sel) {
+  if (cfg == 1)
+    k_far64_sym_batch<<<B.grid64sym, kBlock, 0, B.st>>>(B.items32[kSymB], B.n_items32[kSymB], B.mols, sel, B.wpsi,
+                                                        B.wpsn, kparams(B.d), B.partial);
+  else
+    k_far64_batch<<<B.grid64, kBlock, 0, B.st>>>(B.items64, B.n_items64, B.mols, kChunk64, sel, B.wpsi, B.wpsn,
+                                                 kparams(B.d), B.partial);
+}
+
 // Molecules selected by `sel` get y = A x with the FP64 operator (persistent launch).
 void op64(Batch& B, const double* x, double* y, const int* sel) {
   const unsigned nbn = (unsigned)((B.ntot + kBlock - 1) / kBlock);
   k_weights_batch<<<nbn, kBlock, 0, B.st>>>(B.ntot, B.mol_of, B.mols, x, B.d.h3 / (4.0 * kPi), B.wpsi, B.wpsn);
-  k_far64_batch<<<B.grid64, kBlock, 0, B.st>>>(B.items64, B.n_items64, B.mols, kChunk64, sel, B.wpsi, B.wpsn,
-                                               kparams(B.d), B.partial);
-  k_reduce_batch<<<nbn, kBlock, 0, B.st>>>(B.ntot, B.mol_of, B.mols, sel, kModeF64, B.partial, x, y, nullptr, 0, 0,
-                                           B.d.lam1, B.d.lam2);
+  far64(B, B.cfg64, sel);
+  k_reduce_batch<<<nbn, kBlock, 0, B.st>>>(B.ntot, B.mol_of, B.mols, sel, B.cfg64 ? kModeF64Sym : kModeF64, B.partial,
+                                           x, y, nullptr, 0, 0, B.d.lam1, B.d.lam2);
 }
 
 // Mixed operator: y = A x for molecules in `act`; with kptr, x = V[*kptr] and y = V[*kptr+1].
@@ -895,6 +924,12 @@ extern "C" pb_status pb_ibim_solve_batched(pb_ctx* ctx, int n_mol, const pb_band
         per_cu < 1)
       per_cu = 2;
     B.grid64 = std::min(B.n_items64, per_cu * ctx->n_cu);
+    per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_far64_sym_batch, kBlock, 0) !=
+            hipSuccess ||
+        per_cu < 1)
+      per_cu = 1;
+    B.grid64sym = std::min(B.n_items32[kSymB], per_cu * ctx->n_cu);
   }
   for (int i = 0; i < n_mol; ++i) {
     const MolDev& md = B.mols_h[i];
@@ -964,6 +999,37 @@ extern "C" pb_status pb_ibim_solve_batched(pb_ctx* ctx, int n_mol, const pb_band
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
       ctx->batch_cfg[key] = B.cfg;
+    }
+    // the FP64 operator's kernel, the same way (PB_F64_CFG=<0|1> fixes it)
+    auto it64 = ctx->batch_cfg64.find(key);
+    const char* env64 = std::getenv("PB_F64_CFG");
+    if (it64 != ctx->batch_cfg64.end()) {
+      B.cfg64 = it64->second;
+    } else if (env64 && (std::atoi(env64) == 0 || std::atoi(env64) == 1)) {
+      B.cfg64 = std::atoi(env64);
+      ctx->batch_cfg64[key] = B.cfg64;
+    } else {
+      k_weights_batch<<<nbn, kBlock, 0, B.st>>>(B.ntot, B.mol_of, B.mols, x, B.d.h3 / (4.0 * kPi), B.wpsi, B.wpsn);
+      hipEvent_t e0, e1;
+      PB_HIP(ctx, hipEventCreate(&e0));
+      PB_HIP(ctx, hipEventCreate(&e1));
+      float best = 1e30f;
+      for (int c = 0; c < 2; ++c) {
+        PB_HIP(ctx, hipEventRecord(e0, B.st));
+        far64(B, c, all_on);
+        PB_HIP(ctx, hipEventRecord(e1, B.st));
+        PB_TRY(launch_ok(ctx, "batch autotune"));
+        PB_HIP(ctx, hipEventSynchronize(e1));
+        float ms = 0.f;
+        PB_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+          best = ms;
+          B.cfg64 = c;
+        }
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      ctx->batch_cfg64[key] = B.cfg64;
     }
   }
 

@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "pair_kernels.hpp"
+#include "sym64_kernels.hpp"
 #include "sym_kernels.hpp"
 
 namespace pb {
@@ -160,20 +161,90 @@ pb_status far_autotune(pb_ctx* ctx, int n, bool screened, const float4* A, const
   return PB_OK;
 }
 
+namespace {
+
+// FP64 operator kernel: 0 = one target per lane over source chunks, 1 = symmetric.
+int launch_f64(pb_ctx* ctx, int cfg, const pb_band* band, const double* wpsi, const double* wpsn, const KParams& kp,
+               double* partial) {
+  const int n = (int)band->n;
+  if (cfg == 1) {
+    int n_items = 0;
+    const int2* items = sym_items_dev(ctx, n, &n_items);
+    if (!items) return -1;
+    k_p2p_f64_sym<<<(unsigned)n_items, kBlock, 0, ctx->stream>>>(band_dev(band), wpsi, wpsn, n, sym_nsub(n), items,
+                                                                 n_items, kp, partial);
+    return sym_chunks(n);
+  }
+  int chunk = 0;
+  const int S = far_chunks(ctx, n, kBlock, kBlock, &chunk);
+  const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
+  k_p2p_f64<<<dim3(nb, S), kBlock, 0, ctx->stream>>>(band_dev(band), wpsi, wpsn, n, chunk, partial, kp);
+  return S;
+}
+
+// The FP64 kernel for bands of n nodes: timed once per n (PB_F64_CFG=<0|1> fixes it).
+pb_status f64_autotune(pb_ctx* ctx, const pb_band* band, const double* wpsi, const double* wpsn, const KParams& kp,
+                       double* partial, int* cfg_out) {
+  const int n = (int)band->n;
+  auto it = ctx->f64_cfg.find(n);
+  if (it != ctx->f64_cfg.end()) {
+    *cfg_out = it->second;
+    return PB_OK;
+  }
+  if (const char* env = std::getenv("PB_F64_CFG")) {
+    const int c = std::atoi(env);
+    if (c == 0 || c == 1) {
+      ctx->f64_cfg[n] = c;
+      *cfg_out = c;
+      return PB_OK;
+    }
+  }
+  hipEvent_t e0, e1;
+  PB_HIP(ctx, hipEventCreate(&e0));
+  PB_HIP(ctx, hipEventCreate(&e1));
+  int best = 0;
+  float best_ms = 1e30f;
+  for (int c = 0; c < 2; ++c) {
+    PB_HIP(ctx, hipEventRecord(e0, ctx->stream));
+    if (launch_f64(ctx, c, band, wpsi, wpsn, kp, partial) < 0) return ctx->fail(PB_ENOMEM, "FP64 work list");
+    PB_HIP(ctx, hipEventRecord(e1, ctx->stream));
+    PB_TRY(launch_ok(ctx, "f64 autotune"));
+    PB_HIP(ctx, hipEventSynchronize(e1));
+    float ms = 0.f;
+    PB_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ctx->f64_cfg[n] = best;
+  *cfg_out = best;
+  return PB_OK;
+}
+
+}  // namespace
+
 pb_status matvec_fp64(pb_ctx* ctx, const pb_band* band, const Derived& d, const double* p, double* y) {
   const int n = (int)band->n;
   int chunk = 0;
-  const int S = far_chunks(ctx, n, kBlock, kBlock, &chunk);
+  const int S64 = std::max(far_chunks(ctx, n, kBlock, kBlock, &chunk), sym_chunks(n));
   double* wpsi = (double*)workspace(ctx, "mv_wpsi", sizeof(double) * n);
   double* wpsn = (double*)workspace(ctx, "mv_wpsn", sizeof(double) * n);
-  double* partial = (double*)workspace(ctx, "mv_partial64", sizeof(double) * 2 * (size_t)n * S);
+  double* partial = (double*)workspace(ctx, "mv_partial64", sizeof(double) * 2 * (size_t)n * S64);
   if (!wpsi || !wpsn || !partial) return PB_ENOMEM;
   const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
   k_weights_f64<<<nb, kBlock, 0, ctx->stream>>>(n, band->w, p, d.h3 / (4.0 * kPi), wpsi, wpsn);
+  const KParams kp = kparams(d);
+  int cfg = 0;
+  PB_TRY(f64_autotune(ctx, band, wpsi, wpsn, kp, partial, &cfg));
+  int S = 0;
   {
     Scope t(ctx, "p2p_f64");
-    k_p2p_f64<<<dim3(nb, S), kBlock, 0, ctx->stream>>>(band_dev(band), wpsi, wpsn, n, chunk, partial, kparams(d));
+    S = launch_f64(ctx, cfg, band, wpsi, wpsn, kp, partial);
   }
+  if (S < 0) return ctx->fail(PB_ENOMEM, "FP64 work list");
   {
     Scope t(ctx, "reduce");
     k_reduce<<<(unsigned)((2 * n + kBlock - 1) / kBlock), kBlock, 0, ctx->stream>>>(n, S, partial, nullptr, p, d.lam1,

@@ -84,9 +84,11 @@ struct pb_ctx {
   int n_cu = 256;
   pb::MixedPlan mixed;
   std::map<int, int> far_cfg;          // autotuned far-field tile shape per band size
+  std::map<int, int> f64_cfg;          // FP64 operator kernel per band size (0 tiled, 1 symmetric)
   int sym_items_n = -1;                // band size the symmetric kernel's item list was built for
   int sym_n_items = 0;
   std::map<int64_t, int> batch_cfg;    // the same for batches, per (nodes, molecules)
+  std::map<int64_t, int> batch_cfg64;  // FP64 operator kernel for batches (0 tiled, 1 symmetric)
   hipStream_t batch_stream = nullptr;  // capture stream of the batched solve
   const void* nn_key = nullptr;        // band prepared for the learned preconditioner
   int64_t nn_n = 0;

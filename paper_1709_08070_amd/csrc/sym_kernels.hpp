@@ -14,8 +14,9 @@
 // of the one-directional kernel, partial[c][e] = contributions to vector entry e from the
 // sources of chunk c. Item (Ic, Jc), Ic < Jc, owns the slots (Jc, i ∈ Ic) (forward) and
 // (Ic, j ∈ Jc) (reverse); the diagonal item (Ic, Ic) owns (Ic, i ∈ Ic). Every slot belongs to
-// exactly one item, which zeroes it and then accumulates into it in FP64 in a fixed order, so
-// the result is bitwise reproducible and needs no atomics in global memory.
+// exactly one item, which writes it (one sub-block per chunk) or zeroes it and then
+// accumulates into it in FP64 in a fixed order (several), so the result is bitwise
+// reproducible and needs no atomics in global memory.
 //
 // Inside an item the block (256 threads, 4 waves) walks sub-blocks of 512 nodes: targets T
 // (2 per thread), sources S staged in LDS. For T ≠ S, lane l of a wave pairs its targets with
@@ -99,7 +100,7 @@ template <bool kScreened, bool kCheck>
 __device__ __forceinline__ void sym_block(const float4* __restrict__ A, const float4* __restrict__ M,
                                           const float4* __restrict__ N, int n, int t0, int s0, const F32Params& fp,
                                           double sig1, double sig2, SymShared& sh, double* fwd1, double* fwd2,
-                                          double* rev1, double* rev2) {
+                                          double* rev1, double* rev2, bool acc) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   for (int q = tid; q < kSymSub; q += kBlock) {
     const int j = s0 + q;
@@ -139,10 +140,10 @@ __device__ __forceinline__ void sym_block(const float4* __restrict__ A, const fl
     fb2d += (double)fb2;
   }
   __syncthreads();
-  fwd1[ia - t0] += sig1 * fa1d;
-  fwd2[ia - t0] += sig2 * fa2d;
-  fwd1[ib - t0] += sig1 * fb1d;
-  fwd2[ib - t0] += sig2 * fb2d;
+  fwd1[ia - t0] = sig1 * fa1d + (acc ? fwd1[ia - t0] : 0.0);
+  fwd2[ia - t0] = sig2 * fa2d + (acc ? fwd2[ia - t0] : 0.0);
+  fwd1[ib - t0] = sig1 * fb1d + (acc ? fwd1[ib - t0] : 0.0);
+  fwd2[ib - t0] = sig2 * fb2d + (acc ? fwd2[ib - t0] : 0.0);
   for (int q = tid; q < kSymSub; q += kBlock) {
     if (s0 + q < n) {
       double x1 = 0.0, x2 = 0.0;
@@ -150,8 +151,8 @@ __device__ __forceinline__ void sym_block(const float4* __restrict__ A, const fl
         x1 += (double)sh.racc[v][0][q];
         x2 += (double)sh.racc[v][1][q];
       }
-      rev1[q] += sig1 * x1;
-      rev2[q] += sig2 * x2;
+      rev1[q] = sig1 * x1 + (acc ? rev1[q] : 0.0);
+      rev2[q] = sig2 * x2 + (acc ? rev2[q] : 0.0);
     }
   }
   __syncthreads();
@@ -162,7 +163,8 @@ __device__ __forceinline__ void sym_block(const float4* __restrict__ A, const fl
 template <bool kScreened>
 __device__ __forceinline__ void diag_block(const float4* __restrict__ A, const float4* __restrict__ M,
                                            const float4* __restrict__ N, int n, int t0, const F32Params& fp,
-                                           double sig1, double sig2, SymShared& sh, double* fwd1, double* fwd2) {
+                                           double sig1, double sig2, SymShared& sh, double* fwd1, double* fwd2,
+                                           bool acc) {
   const int tid = threadIdx.x;
   for (int q = tid; q < kSymSub; q += kBlock) {
     const int j = t0 + q;
@@ -195,12 +197,12 @@ __device__ __forceinline__ void diag_block(const float4* __restrict__ A, const f
     fb2d += (double)fb2;
   }
   if (ia < n) {
-    fwd1[ia - t0] += sig1 * fa1d;
-    fwd2[ia - t0] += sig2 * fa2d;
+    fwd1[ia - t0] = sig1 * fa1d + (acc ? fwd1[ia - t0] : 0.0);
+    fwd2[ia - t0] = sig2 * fa2d + (acc ? fwd2[ia - t0] : 0.0);
   }
   if (ib < n) {
-    fwd1[ib - t0] += sig1 * fb1d;
-    fwd2[ib - t0] += sig2 * fb2d;
+    fwd1[ib - t0] = sig1 * fb1d + (acc ? fwd1[ib - t0] : 0.0);
+    fwd2[ib - t0] = sig2 * fb2d + (acc ? fwd2[ib - t0] : 0.0);
   }
   __syncthreads();
 }
@@ -216,22 +218,27 @@ __device__ __forceinline__ void sym_item(const float4* __restrict__ A, const flo
   const int i0 = Ic * C, i1 = min(n, i0 + C), j0 = Jc * C, j1 = min(n, j0 + C);
   double* rowF = partial + (int64_t)Jc * 2 * n;  // slots (Jc, i): contributions of chunk Jc
   double* rowR = partial + (int64_t)Ic * 2 * n;  // slots (Ic, j): contributions of chunk Ic
-  for (int e = threadIdx.x; e < i1 - i0; e += kBlock) {
-    rowF[i0 + e] = 0.0;
-    rowF[n + i0 + e] = 0.0;
-  }
-  if (Ic != Jc)
-    for (int e = threadIdx.x; e < j1 - j0; e += kBlock) {
-      rowR[j0 + e] = 0.0;
-      rowR[n + j0 + e] = 0.0;
+  // With one sub-block per chunk every owned slot is written exactly once (no zeroing, no
+  // read-back); with several, the owned slots are zeroed and then accumulated into.
+  const bool acc = nsub > 1;
+  if (acc) {
+    for (int e = threadIdx.x; e < i1 - i0; e += kBlock) {
+      rowF[i0 + e] = 0.0;
+      rowF[n + i0 + e] = 0.0;
     }
-  __syncthreads();
+    if (Ic != Jc)
+      for (int e = threadIdx.x; e < j1 - j0; e += kBlock) {
+        rowR[j0 + e] = 0.0;
+        rowR[n + j0 + e] = 0.0;
+      }
+    __syncthreads();
+  }
   for (int T = i0; T < i1; T += kSymSub) {
     float4 tlo, thi;
     box_union(box, T / kGroup, min(T + kSymSub, n + kGroup - 1) / kGroup, tlo, thi);
     for (int S = (Ic == Jc ? T : j0); S < j1; S += kSymSub) {
       if (S == T) {
-        diag_block<kScreened>(A, M, N, n, T, fp, sig1, sig2, sh, rowF + T, rowF + n + T);
+        diag_block<kScreened>(A, M, N, n, T, fp, sig1, sig2, sh, rowF + T, rowF + n + T, acc);
         continue;
       }
       int clear = 0;
@@ -243,10 +250,10 @@ __device__ __forceinline__ void sym_item(const float4* __restrict__ A, const flo
       clear = __builtin_amdgcn_readfirstlane(clear);
       if (clear)
         sym_block<kScreened, false>(A, M, N, n, T, S, fp, sig1, sig2, sh, rowF + T, rowF + n + T, rowR + S,
-                                    rowR + n + S);
+                                    rowR + n + S, acc);
       else
         sym_block<kScreened, true>(A, M, N, n, T, S, fp, sig1, sig2, sh, rowF + T, rowF + n + T, rowR + S,
-                                   rowR + n + S);
+                                   rowR + n + S, acc);
     }
   }
 }

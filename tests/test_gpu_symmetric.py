@@ -1,12 +1,15 @@
-"""GPU: the symmetric FP32 far-field kernel (each unordered pair evaluated once for both
-directions), forced with PB_FAR_CFG=4, against the FP64 oracle and the one-directional
-kernel (PB_FAR_CFG=2).
+"""GPU: the symmetric kernels (each unordered pair evaluated once for both directions) —
+the FP32 far field forced with PB_FAR_CFG=4 and the FP64 operator forced with
+PB_F64_CFG=1 — against the FP64 oracle and the one-directional kernels.
 
 Cases: the Born ion (3281 nodes: chunks of one 512-node sub-block, a ragged last chunk,
 near pairs inside diagonal and off-diagonal chunk pairs), the 500-atom globule at h = 0.5
 (36,033 nodes, sampled rows), a batch through the batched solve, and repeated launches
 (bitwise reproducible). Bars as for the mixed operator: 1e-5 relative against the oracle
-(2-norm over the rows compared), 1e-6 relative between the two FP32 kernels.
+(2-norm over the rows compared), 1e-6 relative between the two FP32 kernels; for the FP64
+operator as for the FP64 path: 1e-12 relative (2-norm) and 1e-10 of max|y| elementwise
+against the oracle, under each regularization metric (the tangent-plane test is taken per
+direction).
 """
 import os
 import sys
@@ -90,19 +93,22 @@ def test_symmetric_matches_oracle_and_tiled(pbm, case):
 
 
 def test_symmetric_in_batched_solve(pbm):
-    say("case: batched solve with the symmetric far field, 3 globules (25/60/110 atoms), h=0.5, tol 1e-8")
+    say("case: batched solve with the symmetric FP32 far field and FP64 operator, 3 globules (25/60/110 atoms), "
+        "h=0.5, tol 1e-8")
     ctx = pbm.Context(0)
     mols = [_pipeline(pbm, ctx, synth.globule(na, s), 0.5, True) for na, s in ((25, 7300), (60, 7301), (110, 7302))]
     prm = mols[0][0]
     bands, ats = [b for _, _, b in mols], [a for _, a, _ in mols]
     opts = pbm.solve_opts(tol=1e-8, precision=pbm.PB_MIXED)
     os.environ["PB_FAR_CFG"] = "4"
+    os.environ["PB_F64_CFG"] = "1"
     try:
         bctx = pbm.Context(0)
         ps, stats, bst = pbm.pb_ibim_solve_batched(bctx, bands, ats, prm, opts)
         ps2, _, _ = pbm.pb_ibim_solve_batched(bctx, bands, ats, prm, opts)
     finally:
         del os.environ["PB_FAR_CFG"]
+        del os.environ["PB_F64_CFG"]
     assert bst.far_symmetric == 1
     for i, (b, at) in enumerate(zip(bands, ats)):
         assert stats[i].converged and stats[i].true_relres <= 1e-8
@@ -113,4 +119,60 @@ def test_symmetric_in_batched_solve(pbm):
         say(f"  mol {i}: n={b.n} iters {stats[i].iters} energy batch {e_b:.10e} FP64 {e_1:.10e}")
         assert e_b == pytest.approx(e_1, rel=1e-7)
     bctx.close()
+    ctx.close()
+
+
+def _fp64(pbm, cfg, band, prm, p):
+    os.environ["PB_F64_CFG"] = str(cfg)
+    try:
+        ctx = pbm.Context(0)
+        y = pbm.pb_ibim_matvec(ctx, band, prm, p, pbm.PB_FP64).cpu().numpy()
+        y2 = pbm.pb_ibim_matvec(ctx, band, prm, p, pbm.PB_FP64).cpu().numpy()
+        ctx.close()
+    finally:
+        del os.environ["PB_F64_CFG"]
+    assert np.array_equal(y, y2), "repeated launches differ"
+    return y
+
+
+@pytest.mark.parametrize("tau_k,metric", [(1.0, 0), (0.5, 0), (1.0, 1), (1.0, 2)])
+def test_symmetric_fp64_born(pbm, tau_k, metric):
+    import torch
+
+    say(f"case: symmetric FP64 operator, Born ion R=2 h=0.25, tau_k={tau_k} metric={metric} (all rows)")
+    ctx = pbm.Context(0)
+    atoms = synth.born_ion()
+    prm = pbm.params(0.25, ls_mode=pbm.PB_LS_VDW, tau_k=tau_k, reg_metric=metric)
+    grid = pbm.pb_grid_for_atoms(atoms, prm)
+    at = torch.tensor(atoms, dtype=torch.float64, device="cuda")
+    phi = pbm.pb_build_levelset(ctx, at, prm, grid)
+    band = pbm.pb_narrowband_compact(ctx, grid, phi, prm)
+    n = band.n
+    p = torch.tensor(np.random.default_rng(7).normal(size=2 * n), device="cuda")
+    ys = _fp64(pbm, 1, band, prm, p)
+    yt = _fp64(pbm, 0, band, prm, p)
+    ref = oracle.matvec(band.table(), oracle.params(0.25, tau_k=tau_k, metric=metric), p.cpu().numpy())
+    rel = np.linalg.norm(ys - ref) / np.linalg.norm(ref)
+    say(f"n={n}: symmetric vs oracle {rel:.3e} (max {np.max(np.abs(ys - ref)) / np.max(np.abs(ref)):.3e}), "
+        f"vs tiled {np.linalg.norm(ys - yt) / np.linalg.norm(yt):.3e}")
+    assert rel < 1e-12
+    assert np.max(np.abs(ys - ref)) < 1e-10 * np.max(np.abs(ref))
+    ctx.close()
+
+
+def test_symmetric_fp64_globule500(pbm):
+    import torch
+
+    say("case: symmetric FP64 operator, globule 500 atoms seed 500 h=0.5 (64 sampled rows)")
+    ctx = pbm.Context(0)
+    prm, at, band = _pipeline(pbm, ctx, synth.globule(500, 500), 0.5, True)
+    n = band.n
+    p = torch.tensor(np.random.default_rng(8).normal(size=2 * n), device="cuda")
+    ys = _fp64(pbm, 1, band, prm, p)
+    rows = np.random.default_rng(9).choice(n, 64, replace=False)
+    y1, y2 = oracle.matvec_rows(band.table(), oracle.params(0.5), p.cpu().numpy(), rows)
+    ref = np.concatenate([y1, y2])
+    got = np.concatenate([ys[rows], ys[n + rows]])
+    say(f"n={n}: symmetric FP64 vs oracle rows {np.linalg.norm(got - ref) / np.linalg.norm(ref):.3e}")
+    assert np.max(np.abs(got - ref)) < 1e-10 * np.max(np.abs(ref))
     ctx.close()
