@@ -54,9 +54,9 @@ struct MolDev {
   double cx, cy, cz;
   BandDev band;
   const double* w;
-  float4* A;  // FP32 records (σ(x − c), ψn weight), σ·(ψ weight)·n, n
+  float4* A;  // FP32 records (σ(x − c), ψn weight), σ·(ψ weight)·n, (n, σ·ψ weight)
   float4* M;
-  const float4* N;
+  float4* N;
   const float4* box;  // bounding boxes of groups of 256 records
   const int64_t* row;
   const int* col;
@@ -96,6 +96,7 @@ static __global__ void __launch_bounds__(kBlock) k_pack_batch(int ntot, const in
   m.A[l] = make_float4((float)(sigma * (m.band.px[l] - m.cx)), (float)(sigma * (m.band.py[l] - m.cy)),
                        (float)(sigma * (m.band.pz[l] - m.cz)), (float)w2);
   m.M[l] = make_float4((float)(w1 * m.band.nx[l]), (float)(w1 * m.band.ny[l]), (float)(w1 * m.band.nz[l]), 0.f);
+  m.N[l] = make_float4((float)m.band.nx[l], (float)m.band.ny[l], (float)m.band.nz[l], (float)w1);
 }
 
 template <int TILE, int TPL, bool kScreened>
@@ -129,7 +130,7 @@ static __global__ void __launch_bounds__(kBlock) k_far32_sym_batch(const Item* _
     const Item w = items[it];
     if (!active[w.mol]) continue;
     const MolDev& m = mols[w.mol];
-    sym_item<kScreened>(m.A, m.M, m.N, m.box, m.n, w.tb, w.ch, m.nsub, fp, sig1, sig2, partial + m.poffsym, sh);
+    sym_item<kScreened>(m.A, m.N, m.box, m.n, w.tb, w.ch, m.nsub, fp, sig1, sig2, partial + m.poffsym, sh);
   }
 }
 

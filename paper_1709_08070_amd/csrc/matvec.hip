@@ -92,10 +92,10 @@ int launch_far(pb_ctx* ctx, int cfg, bool screened, const float4* A, const float
     const int2* items = sym_items_dev(ctx, n, &n_items);
     if (!items) return -1;
     if (screened)
-      k_p2p_f32_sym<true><<<(unsigned)n_items, kBlock, 0, ctx->stream>>>(A, M, N, box, n, sym_nsub(n), items,
+      k_p2p_f32_sym<true><<<(unsigned)n_items, kBlock, 0, ctx->stream>>>(A, N, box, n, sym_nsub(n), items,
                                                                           n_items, fp, sig1, sig2, partial);
     else
-      k_p2p_f32_sym<false><<<(unsigned)n_items, kBlock, 0, ctx->stream>>>(A, M, N, box, n, sym_nsub(n), items,
+      k_p2p_f32_sym<false><<<(unsigned)n_items, kBlock, 0, ctx->stream>>>(A, N, box, n, sym_nsub(n), items,
                                                                            n_items, fp, sig1, sig2, partial);
     return sym_chunks(n);
   }

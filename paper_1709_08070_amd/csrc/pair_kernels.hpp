@@ -80,7 +80,7 @@ __device__ __forceinline__ void pair_f64(double xi, double yi, double zi, double
 // ---------------------------------------------------------------- FP32
 
 // FP32 records, coordinates centred on the band and scaled by σ = κ (σ = 1 when κ = 0):
-//   A_j = (σ(x_j − c), w̃n_j),  M_j = σ·w̃_j·n_j,  N_j = n_j,
+//   A_j = (σ(x_j − c), w̃n_j),  M_j = σ·w̃_j·n_j,  N_j = (n_j, σ·w̃_j),
 // with w̃_j = h³ω_jψ_j/(4π) and w̃n_j = h³ω_jψn_j/(4π). In scaled coordinates r' = κr = z, so
 // e^{−κr} = exp2(−log2(e)·r') needs no extra product, and the sums come out as y1 = σ·S1,
 // y2 = σ²·S2 (the scale is applied in FP64 afterwards). Folding the ψ weight into the source
@@ -342,7 +342,7 @@ static __global__ void __attribute__((unused)) __launch_bounds__(kBlock) k_pack_
   A[j] = make_float4((float)(sigma * (b.px[j] - cx)), (float)(sigma * (b.py[j] - cy)), (float)(sigma * (b.pz[j] - cz)),
                      (float)w2);
   M[j] = make_float4((float)(w1 * b.nx[j]), (float)(w1 * b.ny[j]), (float)(w1 * b.nz[j]), 0.f);
-  N[j] = make_float4((float)b.nx[j], (float)b.ny[j], (float)b.nz[j], 0.f);
+  N[j] = make_float4((float)b.nx[j], (float)b.ny[j], (float)b.nz[j], (float)w1);
 }
 
 // Bounding box of each aligned group of kGroup records (one block per group):

@@ -3,11 +3,17 @@
 //
 // The four kernels of the IBIM operator (eq. IBIM-PBE with the regularized kernels of the
 // section "Regularization of the singular kernels") depend on the pair through d = x_i − x_j,
-// the two normals and the two weights. r, e^{−κr}, a = e^{−κr}(1 + κr), the θ factors and
-// e^{−κr}(κr)² − 3(1 − a) are the same for (i, j) and (j, i); only the dot products with the
-// normals and weights differ (d → −d). Evaluating both directions together shares those
-// terms: 56 FP32 operations and 2 transcendentals per unordered pair, i.e. 28 + 1 per
-// ordered pair, against 36 + 2 for one direction at a time.
+// the two normals and the two weights. With the scalar weights W = σ·w̃ (ψ) and V = w̃n (ψn),
+// in κ-scaled coordinates (r' = κr, E = e^{−r'}, a = E(1 + r'), c1,2 = 1 − θ1,2 a,
+// g = E r'² − 3(1 − a)) the contributions of the pair are
+//   to i:  a1 += (c1/r'³)(d·n_j) W_j − ((1 − E)/r') V_j,
+//          a2 += [W_j Q + c2 (d·n_i) V_j]/r'³,
+//   to j:  a1 += −(c1/r'³)(d·n_i) W_i − ((1 − E)/r') V_i,
+//          a2 += [W_i Q − c2 (d·n_j) V_i]/r'³,
+// with Q = (1 − a)(n_i·n_j) + (d·n_i)(d·n_j) g/r'² the weight-free K21 core, symmetric in
+// (i, j). Everything but the last products is shared: 46 FP32 operations and 2
+// transcendentals per unordered pair, 23 + 1 per ordered pair (36 + 2 for one direction at a
+// time). Records: A = (σ(x − c), V) and N = (n, W), two float4 per node.
 //
 // Work decomposition. The band is cut into chunks of C = 512·nsub nodes (nC chunks). One
 // work item is a chunk pair (Ic, Jc) with Ic ≤ Jc; the partial sums keep the chunked layout
@@ -38,18 +44,19 @@ constexpr int kSymSub = 512;  // nodes per sub-block
 constexpr int kSymWaves = kBlock / 64;
 
 struct SymShared {
-  float4 sA[kSymSub], sM[kSymSub], sN[kSymSub];
+  float4 sA[kSymSub], sN[kSymSub];
   float racc[kSymWaves][2][kSymSub];
 };
 
-// Both directions of one pair. Target side (i): ta = (x_i, w̃n_i), tm = M_i, tn = n_i; source
-// side (j): sa, sm, sn. fa1/fa2 accumulate the contributions to i, ra1/ra2 those to j. With
-// d = x_i − x_j the reverse direction has d' = −d, so (d'·n_j) = −(d·n_j), (d'·M_i) = −(d·M_i)
-// and their product keeps its sign.
+// Radial and pair terms shared by both directions (see the header): rinv = 1/r' (0 for a
+// near pair when kCheck), r3, P1 = c1/r'³, c2, f0r = (1 − E)/r', Q; dnx = d·n_i, dny = d·n_j.
+struct PairTerms {
+  float r3, P1, c2, f0r, Q, dnx, dny;
+};
+
 template <bool kScreened, bool kCheck>
-__device__ __forceinline__ void pair_sym(const float4& ta, const float4& tm, const float4& tn, const float4& sa,
-                                         const float4& sm, const float4& sn, const F32Params& fp, float& fa1,
-                                         float& fa2, float& ra1, float& ra2) {
+__device__ __forceinline__ PairTerms pair_terms(const float4& ta, const float4& tn, const float4& sa,
+                                                const float4& sn, const F32Params& fp) {
   const float dx = ta.x - sa.x, dy = ta.y - sa.y, dz = ta.z - sa.z;
   const float r2 = r2_f32(ta.x, ta.y, ta.z, sa.x, sa.y, sa.z);
   float rinv = __builtin_amdgcn_rsqf(r2);
@@ -62,43 +69,55 @@ __device__ __forceinline__ void pair_sym(const float4& ta, const float4& tm, con
   }
   const float a = E + Ez;
   const float ri2 = rinv * rinv;
-  const float r3 = ri2 * rinv;
-  const float c1 = __fmaf_rn(-fp.th1, a, 1.f);
-  const float c2 = __fmaf_rn(-fp.th2, a, 1.f);
-  // i ← j
-  const float dnx = __fmaf_rn(dz, tn.z, __fmaf_rn(dy, tn.y, dx * tn.x));
-  const float D = __fmaf_rn(dz, sm.z, __fmaf_rn(dy, sm.y, dx * sm.x));
-  // j ← i
-  const float dny = __fmaf_rn(dz, sn.z, __fmaf_rn(dy, sn.y, dx * sn.x));
-  const float Di = __fmaf_rn(dz, tm.z, __fmaf_rn(dy, tm.y, dx * tm.x));
-  fa1 = __fmaf_rn(c1 * D, r3, fa1);
-  ra1 = __fmaf_rn(-(c1 * Di), r3, ra1);
+  PairTerms t;
+  t.r3 = ri2 * rinv;
+  t.dnx = __fmaf_rn(dz, tn.z, __fmaf_rn(dy, tn.y, dx * tn.x));
+  t.dny = __fmaf_rn(dz, sn.z, __fmaf_rn(dy, sn.y, dx * sn.x));
+  t.P1 = __fmaf_rn(-fp.th1, a, 1.f) * t.r3;
+  t.c2 = __fmaf_rn(-fp.th2, a, 1.f);
   if (kScreened) {
-    const float Nw = __fmaf_rn(tn.z, sm.z, __fmaf_rn(tn.y, sm.y, tn.x * sm.x));
-    const float Nw2 = __fmaf_rn(sn.z, tm.z, __fmaf_rn(sn.y, tm.y, sn.x * tm.x));
+    const float nn = __fmaf_rn(tn.z, sn.z, __fmaf_rn(tn.y, sn.y, tn.x * sn.x));
     const float g = __fmaf_rn(Ez, z, __fmaf_rn(3.f, a, -3.f));
-    fa1 = __fmaf_rn(-__fmaf_rn(-E, sa.w, sa.w), rinv, fa1);
-    ra1 = __fmaf_rn(-__fmaf_rn(-E, ta.w, ta.w), rinv, ra1);
-    float t = __fmaf_rn(-a, Nw, Nw);
-    t = __fmaf_rn(c2 * dnx, sa.w, t);
-    t = __fmaf_rn(dnx * D * ri2, g, t);
-    float u = __fmaf_rn(-a, Nw2, Nw2);
-    u = __fmaf_rn(-(c2 * dny), ta.w, u);
-    u = __fmaf_rn(dny * Di * ri2, g, u);
-    fa2 = __fmaf_rn(t, r3, fa2);
-    ra2 = __fmaf_rn(u, r3, ra2);
-  } else {  // κ = 0: E = a = 1 and z = 0, so only the θ terms remain
-    fa2 = __fmaf_rn(c2 * dnx * sa.w, r3, fa2);
-    ra2 = __fmaf_rn(-(c2 * dny * ta.w), r3, ra2);
+    t.f0r = __fmaf_rn(-E, rinv, rinv);
+    t.Q = __fmaf_rn((t.dnx * t.dny) * ri2, g, __fmaf_rn(-a, nn, nn));
+  } else {  // κ = 0: E = a = 1 and z = 0, so 1 − E = 0 and Q = 0
+    t.f0r = 0.f;
+    t.Q = 0.f;
   }
+  return t;
+}
+
+// Both directions of one pair. Target side (i): ta = (x_i, V_i), tn = (n_i, W_i); source side
+// (j): sa, sn. fa1/fa2 accumulate the contributions to i, ra1/ra2 those to j.
+template <bool kScreened, bool kCheck>
+__device__ __forceinline__ void pair_sym(const float4& ta, const float4& tn, const float4& sa, const float4& sn,
+                                         const F32Params& fp, float& fa1, float& fa2, float& ra1, float& ra2) {
+  const PairTerms t = pair_terms<kScreened, kCheck>(ta, tn, sa, sn, fp);
+  fa1 = __fmaf_rn(t.P1 * t.dny, sn.w, fa1);
+  ra1 = __fmaf_rn(-(t.P1 * t.dnx), tn.w, ra1);
+  fa2 = __fmaf_rn(__fmaf_rn(t.c2 * t.dnx, sa.w, sn.w * t.Q), t.r3, fa2);
+  ra2 = __fmaf_rn(__fmaf_rn(-(t.c2 * t.dny), ta.w, tn.w * t.Q), t.r3, ra2);
+  if (kScreened) {
+    fa1 = __fmaf_rn(-t.f0r, sa.w, fa1);
+    ra1 = __fmaf_rn(-t.f0r, ta.w, ra1);
+  }
+}
+
+// One direction (i ← j) of the same formula, for the diagonal sub-blocks.
+template <bool kScreened>
+__device__ __forceinline__ void pair_fwd(const float4& ta, const float4& tn, const float4& sa, const float4& sn,
+                                         const F32Params& fp, float& fa1, float& fa2) {
+  const PairTerms t = pair_terms<kScreened, true>(ta, tn, sa, sn, fp);
+  fa1 = __fmaf_rn(t.P1 * t.dny, sn.w, fa1);
+  fa2 = __fmaf_rn(__fmaf_rn(t.c2 * t.dnx, sa.w, sn.w * t.Q), t.r3, fa2);
+  if (kScreened) fa1 = __fmaf_rn(-t.f0r, sa.w, fa1);
 }
 
 // Targets [t0, t0 + 512) (full, 2 per thread) against sources [s0, s0 + 512) of the same
 // records, s0 ≠ t0, both directions. Adds σ·S1, σ²·S2 into fwd (index i − t0) and rev (index
 // j − s0). Every thread of the block calls it (it synchronizes).
 template <bool kScreened, bool kCheck>
-__device__ __forceinline__ void sym_block(const float4* __restrict__ A, const float4* __restrict__ M,
-                                          const float4* __restrict__ N, int n, int t0, int s0, const F32Params& fp,
+__device__ __forceinline__ void sym_block(const float4* __restrict__ A, const float4* __restrict__ N, int n, int t0, int s0, const F32Params& fp,
                                           double sig1, double sig2, SymShared& sh, double* fwd1, double* fwd2,
                                           double* rev1, double* rev2, bool acc) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -106,17 +125,15 @@ __device__ __forceinline__ void sym_block(const float4* __restrict__ A, const fl
     const int j = s0 + q;
     if (j < n) {
       sh.sA[q] = A[j];
-      sh.sM[q] = M[j];
       sh.sN[q] = N[j];
     } else {  // padding: zero weights and normals (such tiles run with the predicate)
       sh.sA[q] = make_float4(0.f, 0.f, 0.f, 0.f);
-      sh.sM[q] = make_float4(0.f, 0.f, 0.f, 0.f);
       sh.sN[q] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
   }
   const int ia = t0 + w * 128 + lane, ib = ia + 64;
-  const float4 taa = A[ia], tma = M[ia], tna = N[ia];
-  const float4 tab = A[ib], tmb = M[ib], tnb = N[ib];
+  const float4 taa = A[ia], tna = N[ia];
+  const float4 tab = A[ib], tnb = N[ib];
   __syncthreads();
   double fa1d = 0.0, fa2d = 0.0, fb1d = 0.0, fb2d = 0.0;
   const int next = ((lane + 1) & 63) << 2;  // byte address of lane l + 1 for ds_bpermute
@@ -126,9 +143,9 @@ __device__ __forceinline__ void sym_block(const float4* __restrict__ A, const fl
 #pragma unroll 2
     for (int s = 0; s < 64; ++s) {
       const int q = g + ((lane + s) & 63);
-      const float4 sa = sh.sA[q], sm = sh.sM[q], sn = sh.sN[q];
-      pair_sym<kScreened, kCheck>(taa, tma, tna, sa, sm, sn, fp, fa1, fa2, ra1, ra2);
-      pair_sym<kScreened, kCheck>(tab, tmb, tnb, sa, sm, sn, fp, fb1, fb2, ra1, ra2);
+      const float4 sa = sh.sA[q], sn = sh.sN[q];
+      pair_sym<kScreened, kCheck>(taa, tna, sa, sn, fp, fa1, fa2, ra1, ra2);
+      pair_sym<kScreened, kCheck>(tab, tnb, sa, sn, fp, fb1, fb2, ra1, ra2);
       ra1 = __int_as_float(__builtin_amdgcn_ds_bpermute(next, __float_as_int(ra1)));
       ra2 = __int_as_float(__builtin_amdgcn_ds_bpermute(next, __float_as_int(ra2)));
     }
@@ -161,8 +178,7 @@ __device__ __forceinline__ void sym_block(const float4* __restrict__ A, const fl
 // Targets [t0, t0 + 512) against the sources of the same sub-block, one direction, with the
 // near-pair predicate (the self pair and the nearest pairs are here). Adds into fwd.
 template <bool kScreened>
-__device__ __forceinline__ void diag_block(const float4* __restrict__ A, const float4* __restrict__ M,
-                                           const float4* __restrict__ N, int n, int t0, const F32Params& fp,
+__device__ __forceinline__ void diag_block(const float4* __restrict__ A, const float4* __restrict__ N, int n, int t0, const F32Params& fp,
                                            double sig1, double sig2, SymShared& sh, double* fwd1, double* fwd2,
                                            bool acc) {
   const int tid = threadIdx.x;
@@ -170,15 +186,15 @@ __device__ __forceinline__ void diag_block(const float4* __restrict__ A, const f
     const int j = t0 + q;
     if (j < n) {
       sh.sA[q] = A[j];
-      sh.sM[q] = M[j];
+      sh.sN[q] = N[j];
     } else {
       sh.sA[q] = make_float4(0.f, 0.f, 0.f, 0.f);
-      sh.sM[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+      sh.sN[q] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
   }
   const int ia = t0 + tid, ib = ia + kBlock;
   const float4 taa = ia < n ? A[ia] : make_float4(0.f, 0.f, 0.f, 0.f);
-  const float4 tna = ia < n ? N[ia] : make_float4(0.f, 0.f, 1.f, 0.f);
+  const float4 tna = ia < n ? N[ia] : make_float4(0.f, 0.f, 1.f, 0.f);  // dead targets: results unused
   const float4 tab = ib < n ? A[ib] : make_float4(0.f, 0.f, 0.f, 0.f);
   const float4 tnb = ib < n ? N[ib] : make_float4(0.f, 0.f, 1.f, 0.f);
   __syncthreads();
@@ -187,9 +203,9 @@ __device__ __forceinline__ void diag_block(const float4* __restrict__ A, const f
     float fa1 = 0.f, fa2 = 0.f, fb1 = 0.f, fb2 = 0.f;
 #pragma unroll 4
     for (int q = g; q < g + 64; ++q) {
-      const float4 sa = sh.sA[q], sm = sh.sM[q];
-      pair_f32<kScreened, true>(taa, tna, sa, sm, fp, fa1, fa2);
-      pair_f32<kScreened, true>(tab, tnb, sa, sm, fp, fb1, fb2);
+      const float4 sa = sh.sA[q], sn = sh.sN[q];
+      pair_fwd<kScreened>(taa, tna, sa, sn, fp, fa1, fa2);
+      pair_fwd<kScreened>(tab, tnb, sa, sn, fp, fb1, fb2);
     }
     fa1d += (double)fa1;
     fa2d += (double)fa2;
@@ -210,8 +226,7 @@ __device__ __forceinline__ void diag_block(const float4* __restrict__ A, const f
 // One work item (Ic, Jc), Ic ≤ Jc, of a band of n records with chunks of nsub sub-blocks.
 // partial: the band's chunked partial sums (slot (c, e) at partial[c·2n + e]).
 template <bool kScreened>
-__device__ __forceinline__ void sym_item(const float4* __restrict__ A, const float4* __restrict__ M,
-                                         const float4* __restrict__ N, const float4* __restrict__ box, int n,
+__device__ __forceinline__ void sym_item(const float4* __restrict__ A, const float4* __restrict__ N, const float4* __restrict__ box, int n,
                                          int Ic, int Jc, int nsub, const F32Params& fp, double sig1, double sig2,
                                          double* __restrict__ partial, SymShared& sh) {
   const int C = nsub * kSymSub;
@@ -238,7 +253,7 @@ __device__ __forceinline__ void sym_item(const float4* __restrict__ A, const flo
     box_union(box, T / kGroup, min(T + kSymSub, n + kGroup - 1) / kGroup, tlo, thi);
     for (int S = (Ic == Jc ? T : j0); S < j1; S += kSymSub) {
       if (S == T) {
-        diag_block<kScreened>(A, M, N, n, T, fp, sig1, sig2, sh, rowF + T, rowF + n + T, acc);
+        diag_block<kScreened>(A, N, n, T, fp, sig1, sig2, sh, rowF + T, rowF + n + T, acc);
         continue;
       }
       int clear = 0;
@@ -249,10 +264,10 @@ __device__ __forceinline__ void sym_item(const float4* __restrict__ A, const flo
       }
       clear = __builtin_amdgcn_readfirstlane(clear);
       if (clear)
-        sym_block<kScreened, false>(A, M, N, n, T, S, fp, sig1, sig2, sh, rowF + T, rowF + n + T, rowR + S,
+        sym_block<kScreened, false>(A, N, n, T, S, fp, sig1, sig2, sh, rowF + T, rowF + n + T, rowR + S,
                                     rowR + n + S, acc);
       else
-        sym_block<kScreened, true>(A, M, N, n, T, S, fp, sig1, sig2, sh, rowF + T, rowF + n + T, rowR + S,
+        sym_block<kScreened, true>(A, N, n, T, S, fp, sig1, sig2, sh, rowF + T, rowF + n + T, rowR + S,
                                    rowR + n + S, acc);
     }
   }
@@ -261,13 +276,13 @@ __device__ __forceinline__ void sym_item(const float4* __restrict__ A, const flo
 // Symmetric FP32 far field of one band: one block per work item (items: (Ic, Jc) pairs).
 template <bool kScreened>
 static __global__ void __attribute__((unused)) __launch_bounds__(kBlock)
-    k_p2p_f32_sym(const float4* __restrict__ A, const float4* __restrict__ M, const float4* __restrict__ N,
+    k_p2p_f32_sym(const float4* __restrict__ A, const float4* __restrict__ N,
                   const float4* __restrict__ box, int n, int nsub, const int2* __restrict__ items, int n_items,
                   F32Params fp, double sig1, double sig2, double* __restrict__ partial) {
   __shared__ SymShared sh;
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     const int2 w = items[it];
-    sym_item<kScreened>(A, M, N, box, n, w.x, w.y, nsub, fp, sig1, sig2, partial, sh);
+    sym_item<kScreened>(A, N, box, n, w.x, w.y, nsub, fp, sig1, sig2, partial, sh);
   }
 }
 
