@@ -27,16 +27,45 @@ struct Sym64Shared {
   double racc[kSymWaves][2][kSymSub];
 };
 
-// Regularization decision for the direction whose target has tangential coordinate dn.
+// Regularization decision for the direction whose target has tangential coordinate dn, for
+// a metric fixed at compile time.
+template <int kMetric>
 __device__ __forceinline__ bool reg_f64(double r2, double dn, const KParams& kp) {
   const double t2 = __dadd_rn(r2, -__dmul_rn(dn, dn));
-  if (kp.metric == PB_REG_EUCLIDEAN) return r2 < kp.tau2;
-  if (kp.metric == PB_REG_TANGENT) return t2 < kp.tau2;
+  if (kMetric == PB_REG_EUCLIDEAN) return r2 < kp.tau2;
+  if (kMetric == PB_REG_TANGENT) return t2 < kp.tau2;
   return t2 < kp.tau2 && r2 < kp.four_tau2;
+}
+
+// e^{−z} for z ≥ 0 in FP64 without branches (Cody–Waite reduction): k = rint(−z·log2 e),
+// t = −z − k·ln2 with ln 2 = L_hi + L_lo (L_hi its nearest double, L_lo the remainder; the
+// products are exact inside the FMAs), |t| ≤ ln2/2, e^t by its Taylor series to degree 13
+// (truncation error below 1e-17 relative), then scaled by 2^k. z is clamped to 745, beyond which
+// e^{−z} is 0 in FP64.
+__device__ __forceinline__ double exp_neg_f64(double z) {
+  z = fmin(z, 745.0);
+  const double k = __builtin_rint(-z * 1.4426950408889634);
+  const double t = fma(-k, 2.3190468138462996e-17, fma(-k, 0.6931471805599453, -z));
+  double p = 1.0 / 6227020800.0;  // 1/13!
+  p = fma(p, t, 1.0 / 479001600.0);
+  p = fma(p, t, 1.0 / 39916800.0);
+  p = fma(p, t, 1.0 / 3628800.0);
+  p = fma(p, t, 1.0 / 362880.0);
+  p = fma(p, t, 1.0 / 40320.0);
+  p = fma(p, t, 1.0 / 5040.0);
+  p = fma(p, t, 1.0 / 720.0);
+  p = fma(p, t, 1.0 / 120.0);
+  p = fma(p, t, 1.0 / 24.0);
+  p = fma(p, t, 1.0 / 6.0);
+  p = fma(p, t, 0.5);
+  p = fma(p, t, 1.0);
+  p = fma(p, t, 1.0);
+  return ldexp(p, (int)k);
 }
 
 // Both directions of one pair. Target i: position xi, normal ni, weights (wψ_i, wψn_i); source j
 // likewise. f1/f2 accumulate into i, g1/g2 into j.
+template <int kMetric>
 __device__ __forceinline__ void pair_sym_f64(double xi, double yi, double zi, double nxi, double nyi, double nzi,
                                              double wpi, double wni, const double2& s0, const double2& s1,
                                              const double2& s2, const double2& s3, const KParams& kp, double& f1,
@@ -46,39 +75,34 @@ __device__ __forceinline__ void pair_sym_f64(double xi, double yi, double zi, do
   const double r2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
   const double dnx = __dadd_rn(__dadd_rn(__dmul_rn(dx, nxi), __dmul_rn(dy, nyi)), __dmul_rn(dz, nzi));
   const double dny = __dadd_rn(__dadd_rn(__dmul_rn(dx, nxj), __dmul_rn(dy, nyj)), __dmul_rn(dz, nzj));
-  const bool rf = reg_f64(r2, dnx, kp), rr = reg_f64(r2, dny, kp);
-  if (rf && rr) {
-    f1 -= kp.k12bar4pi * wnj;
-    g1 -= kp.k12bar4pi * wni;
-    return;
-  }
+  const bool rf = reg_f64<kMetric>(r2, dnx, kp), rr = reg_f64<kMetric>(r2, dny, kp);
+  // Branch-free: the radial terms are formed for every pair and each direction selects its
+  // regularized or regular value. Only a pair regularized both ways can have r = 0; it takes
+  // r² = 1 here, whose (finite) radial terms are discarded.
+  const double r2s = (rf && rr) ? 1.0 : r2;
   const double nn = nxi * nxj + nyi * nyj + nzi * nzj;
-  double rinv = __builtin_amdgcn_rsq(r2);
-  double e = fma(-r2 * rinv, rinv, 1.0);
+  double rinv = __builtin_amdgcn_rsq(r2s);
+  double e = fma(-r2s * rinv, rinv, 1.0);
   rinv = fma(0.5 * rinv, e, rinv);
-  e = fma(-r2 * rinv, rinv, 1.0);
+  e = fma(-r2s * rinv, rinv, 1.0);
   rinv = fma(0.5 * rinv, e, rinv);
-  const double r = r2 * rinv;
+  const double r = r2s * rinv;
   const double r3 = rinv * rinv * rinv;
   const double r5 = r3 * rinv * rinv;
   const double z = kp.kappa * r;
-  const double E = exp(-z);
+  const double E = exp_neg_f64(z);
   const double a = E * (1.0 + z);
   const double b = E * (3.0 + 3.0 * z + z * z);
   const double k12 = (1.0 - E) * rinv;
   const double k21 = nn * (1.0 - a) * r3 - dnx * dny * (3.0 - b) * r5;
-  if (rf) {
-    f1 -= kp.k12bar4pi * wnj;
-  } else {
-    f1 += dny * (1.0 - kp.th1 * a) * r3 * wpj - k12 * wnj;
-    f2 += k21 * wpj + dnx * (1.0 - kp.th2 * a) * r3 * wnj;
-  }
-  if (rr) {
-    g1 -= kp.k12bar4pi * wni;
-  } else {
-    g1 += -dnx * (1.0 - kp.th1 * a) * r3 * wpi - k12 * wni;
-    g2 += k21 * wpi - dny * (1.0 - kp.th2 * a) * r3 * wni;
-  }
+  const double f1r = dny * (1.0 - kp.th1 * a) * r3 * wpj - k12 * wnj;
+  const double f2r = k21 * wpj + dnx * (1.0 - kp.th2 * a) * r3 * wnj;
+  const double g1r = -dnx * (1.0 - kp.th1 * a) * r3 * wpi - k12 * wni;
+  const double g2r = k21 * wpi - dny * (1.0 - kp.th2 * a) * r3 * wni;
+  f1 += rf ? -kp.k12bar4pi * wnj : f1r;
+  f2 += rf ? 0.0 : f2r;
+  g1 += rr ? -kp.k12bar4pi * wni : g1r;
+  g2 += rr ? 0.0 : g2r;
 }
 
 __device__ __forceinline__ double shfl_next(double v, int addr) {
@@ -89,6 +113,7 @@ __device__ __forceinline__ double shfl_next(double v, int addr) {
 
 // Targets [t0, t0 + 512) (full) against sources [s0, s0 + 512), s0 ≠ t0, both directions;
 // adds into fwd (index i − t0) and rev (index j − s0). wpsi/wpsn: h³ωψ/4π, h³ωψn/4π.
+template <int kMetric>
 __device__ __forceinline__ void sym64_block(const BandDev& b, const double* __restrict__ wpsi,
                                             const double* __restrict__ wpsn, int n, int t0, int s0,
                                             const KParams& kp, Sym64Shared& sh, double* fwd1, double* fwd2,
@@ -120,8 +145,8 @@ __device__ __forceinline__ void sym64_block(const BandDev& b, const double* __re
     for (int s = 0; s < 64; ++s) {
       const int q = g + ((lane + s) & 63);
       const double2 c0 = sh.s0[q], c1 = sh.s1[q], c2 = sh.s2[q], c3 = sh.s3[q];
-      pair_sym_f64(xa, ya, za, nxa, nya, nza, wpa, wna, c0, c1, c2, c3, kp, fa1, fa2, ra1, ra2);
-      pair_sym_f64(xb, yb, zb, nxb, nyb, nzb, wpb, wnb, c0, c1, c2, c3, kp, fb1, fb2, ra1, ra2);
+      pair_sym_f64<kMetric>(xa, ya, za, nxa, nya, nza, wpa, wna, c0, c1, c2, c3, kp, fa1, fa2, ra1, ra2);
+      pair_sym_f64<kMetric>(xb, yb, zb, nxb, nyb, nzb, wpb, wnb, c0, c1, c2, c3, kp, fb1, fb2, ra1, ra2);
       ra1 = shfl_next(ra1, next);
       ra2 = shfl_next(ra2, next);
     }
@@ -205,8 +230,15 @@ __device__ __forceinline__ void sym64_item(const BandDev& b, const double* __res
     for (int S = (Ic == Jc ? T : j0); S < j1; S += kSymSub) {
       if (S == T)
         diag64_block(b, wpsi, wpsn, n, T, kp, sh, rowF + T, rowF + n + T, acc);
+      else if (kp.metric == PB_REG_EUCLIDEAN)
+        sym64_block<PB_REG_EUCLIDEAN>(b, wpsi, wpsn, n, T, S, kp, sh, rowF + T, rowF + n + T, rowR + S, rowR + n + S,
+                                      acc);
+      else if (kp.metric == PB_REG_TANGENT)
+        sym64_block<PB_REG_TANGENT>(b, wpsi, wpsn, n, T, S, kp, sh, rowF + T, rowF + n + T, rowR + S, rowR + n + S,
+                                    acc);
       else
-        sym64_block(b, wpsi, wpsn, n, T, S, kp, sh, rowF + T, rowF + n + T, rowR + S, rowR + n + S, acc);
+        sym64_block<PB_REG_TANGENT_GUARDED>(b, wpsi, wpsn, n, T, S, kp, sh, rowF + T, rowF + n + T, rowR + S,
+                                            rowR + n + S, acc);
     }
 }
 

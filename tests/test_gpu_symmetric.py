@@ -176,3 +176,37 @@ def test_symmetric_fp64_globule500(pbm):
     say(f"n={n}: symmetric FP64 vs oracle rows {np.linalg.norm(got - ref) / np.linalg.norm(ref):.3e}")
     assert np.max(np.abs(got - ref)) < 1e-10 * np.max(np.abs(ref))
     ctx.close()
+
+
+@pytest.mark.parametrize("cfg", ["far0", "far1", "far2", "far3", "far4", "f64_0", "f64_1"])
+def test_band_smaller_than_one_tile(pbm, cfg):
+    """A single 0.8 Å sphere at h = 0.5: a band of 195 nodes, below one 256-node group (the
+    tiled kernels run one partial tile and one partial bounding-box group; the symmetric
+    kernels a single, partial diagonal chunk). Every operator variant against the oracle
+    on all rows."""
+    import torch
+
+    ctx = pbm.Context(0)
+    atoms = synth.born_ion(0.8)
+    prm = pbm.params(0.5, ls_mode=pbm.PB_LS_VDW)
+    grid = pbm.pb_grid_for_atoms(atoms, prm)
+    at = torch.tensor(atoms, dtype=torch.float64, device="cuda")
+    phi = pbm.pb_build_levelset(ctx, at, prm, grid)
+    band = pbm.pb_narrowband_compact(ctx, grid, phi, prm)
+    n = band.n
+    say(f"case: small band ({cfg}), sphere R=0.8 h=0.5, n={n}")
+    assert n < 256
+    p = torch.tensor(np.random.default_rng(10).normal(size=2 * n), device="cuda")
+    ref = oracle.matvec(band.table(), oracle.params(0.5), p.cpu().numpy())
+    kind, k = cfg.split("_") if "_" in cfg else ("far", cfg[3:])
+    if kind == "far":
+        y = _mixed(pbm, int(k), band, prm, p)
+        rel = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+        say(f"  mixed vs oracle {rel:.3e}")
+        assert rel < 1e-5
+    else:
+        y = _fp64(pbm, int(k), band, prm, p)
+        rel = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+        say(f"  FP64 vs oracle {rel:.3e}")
+        assert rel < 1e-12
+    ctx.close()
