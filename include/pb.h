@@ -57,6 +57,13 @@ enum { PB_FP64 = 0, PB_MIXED = 1 };
 /* GMRES initial guess: zero, Λ⁻¹g (the paper's diagonal preconditioner), caller's p, learned. */
 enum { PB_X0_ZERO = 0, PB_X0_DIAG = 1, PB_X0_USER = 2, PB_X0_LEARNED = 3 };
 enum { PB_PRECOND_NONE = 0, PB_PRECOND_LEARNED = 1 };
+/* ∇φ at band nodes (section "Projections and weights"): second-order central differences,
+   or the average (p₋ + p₊)/2 of the two fifth-order WENO one-sided derivatives per axis. */
+enum { PB_GRAD_CENTRAL = 0, PB_GRAD_WENO = 1 };
+/* Jacobian in the band weight: J ≡ 1 (every experiment of the paper), or the explicit
+   J = 1 − φΔφ + φ²⟨n, adj(∇²φ) n⟩ of section "Implicit boundary integral methods" (read
+   with the adjugate of the Hessian; second-order central differences). */
+enum { PB_JAC_ONE = 0, PB_JAC_FULL = 1 };
 
 typedef struct pb_ctx pb_ctx;
 
@@ -73,7 +80,8 @@ typedef struct {
   int reg_metric;    /* PB_REG_* */
   int ls_mode;       /* PB_LS_* */
   int reinit_steps;  /* reinitialization steps; 0 = 2·ceil((band_k + 4)/cfl) */
-  int reserved;
+  int grad_scheme;   /* PB_GRAD_* (default central differences) */
+  int jacobian;      /* PB_JAC_* (default J ≡ 1) */
 } pb_params;
 
 typedef struct {
@@ -88,7 +96,7 @@ typedef struct {
   double *px, *py, *pz;   /* device: closest-point projection x* = x − φ n */
   double *nx, *ny, *nz;   /* device: unit normal ∇φ/|∇φ| (central differences) */
   double *phi;            /* device: level-set value at the node */
-  double *w;              /* device: ω = J·δ_ε(φ) with J ≡ 1 (h³ is applied by the operator) */
+  double *w;              /* device: ω = J·δ_ε(φ), J per pb_params.jacobian (h³ is applied by the operator) */
   int64_t *gidx;          /* device: linear grid index of the node */
 } pb_band;
 
@@ -149,8 +157,9 @@ pb_status pb_build_levelset(pb_ctx* ctx, const double* atoms, int n_atoms, const
                             const pb_grid* grid, double* phi);
 
 /* Stage 2 (section "Projections and weights"): band nodes −ε < φ < ε in lexicographic
-   order, n = ∇φ/|∇φ| by central differences, x* = x − φ n, ω = δ_ε(φ) (eq. cosine-kernel),
-   J ≡ 1. phi: device. band: caller fills capacity and the device arrays; on return n holds
+   order, n = ∇φ/|∇φ| with ∇φ by prm->grad_scheme, x* = x − φ n, ω = δ_ε(φ)·J
+   (eq. cosine-kernel; J by prm->jacobian, WENO ghosts by even reflection at the grid
+   boundary as in Stage 1). phi: device. band: caller fills capacity and the device arrays; on return n holds
    the node count. PB_ECAPACITY if capacity < count (n = count, arrays untouched beyond
    capacity); PB_EGEOM if a band node lies on the grid edge or has zero gradient. */
 pb_status pb_narrowband_compact(pb_ctx* ctx, const pb_grid* grid, const double* phi, const pb_params* prm,

@@ -52,7 +52,9 @@ def lib():
         L.pbo_ses.argtypes = [ip, dp, dp, C.c_int, dp, dp]
         L.pbo_ses.restype = C.c_long
         L.pbo_weno_grad.argtypes = [ip, C.c_double, dp, C.c_long, dp, dp]
-        L.pbo_band.argtypes = [ip, dp, C.c_double, dp, C.c_double, C.c_void_p, C.c_void_p]
+        L.pbo_band.argtypes = [ip, dp, C.c_double, dp, C.c_double, C.c_int, C.c_int, C.c_void_p, C.c_void_p]
+        L.pbo_jacobian.argtypes = [ip, C.c_double, dp, C.c_long, dp]
+        L.pbo_jacobian.restype = C.c_double
         L.pbo_band.restype = C.c_long
         L.pbo_delta.argtypes = [C.c_double, C.c_double]
         L.pbo_delta.restype = C.c_double
@@ -137,17 +139,27 @@ def weno_grad(dims, h, phi, node):
     return np.array(m[:]), np.array(p[:])
 
 
-def band(dims, origin, h, phi, eps):
-    """Returns (nodes [n×8], gidx [n]); raises if a band node touches the grid edge."""
+GRAD_CENTRAL, GRAD_WENO = 0, 1
+
+
+def band(dims, origin, h, phi, eps, grad_scheme=GRAD_CENTRAL, jacobian=False):
+    """Returns (nodes [n×8], gidx [n]); raises if a band node touches the grid edge.
+    grad_scheme: central differences or the WENO5 average; jacobian: ω carries the explicit J."""
     phi = _f64(phi)
     d3, o3 = (C.c_int * 3)(*dims), (C.c_double * 3)(*origin)
-    n = lib().pbo_band(d3, o3, h, _d(phi), eps, None, None)
+    n = lib().pbo_band(d3, o3, h, _d(phi), eps, grad_scheme, int(jacobian), None, None)
     if n < 0:
         raise ValueError("band touches the grid boundary")
     nodes = np.empty((n, 8))
     gidx = np.empty(n, dtype=np.int64)
-    lib().pbo_band(d3, o3, h, _d(phi), eps, nodes.ctypes.data_as(C.c_void_p), gidx.ctypes.data_as(C.c_void_p))
+    lib().pbo_band(d3, o3, h, _d(phi), eps, grad_scheme, int(jacobian), nodes.ctypes.data_as(C.c_void_p),
+                   gidx.ctypes.data_as(C.c_void_p))
     return nodes, gidx
+
+
+def jacobian(dims, h, phi, node, n):
+    """Explicit J at one interior grid node with unit normal n."""
+    return lib().pbo_jacobian((C.c_int * 3)(*dims), h, _d(_f64(phi)), int(node), _d(_f64(n)))
 
 
 def delta(eta, eps):
@@ -231,7 +243,7 @@ def grid_margin(atoms, h, band_k=2.0, probe=1.4, ses=True):
     return rmax + (probe if ses else 0.0) + band_k * h + 4 * h + 1.0
 
 
-def pipeline(atoms, h, ses=True, tau_k=1.0, **kw):
+def pipeline(atoms, h, ses=True, tau_k=1.0, grad_scheme=GRAD_CENTRAL, jacobian=False, **kw):
     """Stage 1 + Stage 2 on the CPU: returns dims, origin, phi, nodes, gidx, prm."""
     prm = params(h, tau_k=tau_k, **kw)
     dims, origin = grid(atoms, h, grid_margin(atoms, h, prm[BAND] / h, prm[PROBE], ses))
@@ -239,7 +251,7 @@ def pipeline(atoms, h, ses=True, tau_k=1.0, **kw):
         phi, _ = ses_fn(dims, origin, atoms, prm)
     else:
         phi = vdw(dims, origin, h, atoms)
-    nodes, gidx = band(dims, origin, h, phi, prm[BAND])
+    nodes, gidx = band(dims, origin, h, phi, prm[BAND], grad_scheme, jacobian)
     return dims, origin, phi, nodes, gidx, prm
 
 

@@ -265,10 +265,47 @@ double pbo_delta(double eta, double eps) {
   return (1.0 + cos(PI * eta / eps)) / (2.0 * eps);
 }
 
-/* Nodes with −ε < φ < ε in lexicographic order; ∇φ by central differences;
-   n = ∇φ/|∇φ|; x* = x − φ n; ω = δ_ε(φ) with J ≡ 1 ("Projections and weights"). */
-long pbo_band(const int* dims, const double* origin, double h, const double* phi, double eps,
-              double* nodes, long* gidx) {
+/* Jacobian between Γ and the level set of φ through node (i,j,k) (section "Implicit
+   boundary integral methods", the explicit J):
+     J = 1 − φ Δφ + φ² ⟨n, adj(∇²φ) n⟩,
+   with the Hessian ∇²φ by second-order central differences (the mixed derivatives from the
+   four diagonal neighbours), adj its adjugate (transposed cofactor matrix) and n the unit
+   normal of the node. Reading: the printed last term has the Hessian itself, which vanishes
+   on ∇φ for a distance function; with the adjugate, J = (1 − φκ1)(1 − φκ2) for the principal
+   curvatures κ1, κ2 of the level set through the node, the area ratio of the projection. */
+double pbo_jacobian(const int* dims, double h, const double* phi, long node, const double* n) {
+  long k = node % dims[2], j = (node / dims[2]) % dims[1], i = node / ((long)dims[1] * dims[2]);
+  double c = phi[node], h2 = h * h;
+  double H[3][3];
+  H[0][0] = (phi[lin(dims, i + 1, j, k)] - 2.0 * c + phi[lin(dims, i - 1, j, k)]) / h2;
+  H[1][1] = (phi[lin(dims, i, j + 1, k)] - 2.0 * c + phi[lin(dims, i, j - 1, k)]) / h2;
+  H[2][2] = (phi[lin(dims, i, j, k + 1)] - 2.0 * c + phi[lin(dims, i, j, k - 1)]) / h2;
+  H[0][1] = H[1][0] = (phi[lin(dims, i + 1, j + 1, k)] - phi[lin(dims, i + 1, j - 1, k)] -
+                       phi[lin(dims, i - 1, j + 1, k)] + phi[lin(dims, i - 1, j - 1, k)]) / (4.0 * h2);
+  H[0][2] = H[2][0] = (phi[lin(dims, i + 1, j, k + 1)] - phi[lin(dims, i + 1, j, k - 1)] -
+                       phi[lin(dims, i - 1, j, k + 1)] + phi[lin(dims, i - 1, j, k - 1)]) / (4.0 * h2);
+  H[1][2] = H[2][1] = (phi[lin(dims, i, j + 1, k + 1)] - phi[lin(dims, i, j + 1, k - 1)] -
+                       phi[lin(dims, i, j - 1, k + 1)] + phi[lin(dims, i, j - 1, k - 1)]) / (4.0 * h2);
+  /* adj(H)[a][b] = cofactor of H[b][a]: the signed 2×2 minor left after deleting row b, column a */
+  double A[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      int r0 = (b + 1) % 3, r1 = (b + 2) % 3, c0 = (a + 1) % 3, c1 = (a + 2) % 3;
+      A[a][b] = H[r0][c0] * H[r1][c1] - H[r0][c1] * H[r1][c0];
+    }
+  double q = 0.0;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) q += n[a] * A[a][b] * n[b];
+  return 1.0 - c * (H[0][0] + H[1][1] + H[2][2]) + c * c * q;
+}
+
+/* Nodes with −ε < φ < ε in lexicographic order ("Projections and weights"):
+   ∇φ by central differences (grad_scheme 0) or the average (p₋ + p₊)/2 of the two WENO5
+   one-sided derivatives per axis (grad_scheme 1); n = ∇φ/|∇φ|; x* = x − φ n;
+   ω = δ_ε(φ)·J with J ≡ 1 (jacobian 0, the paper's experiments) or the explicit J of
+   pbo_jacobian (jacobian 1). */
+long pbo_band(const int* dims, const double* origin, double h, const double* phi, double eps, int grad_scheme,
+              int jacobian, double* nodes, long* gidx) {
   long cnt = 0;
   for (long i = 0; i < dims[0]; ++i)
     for (long j = 0; j < dims[1]; ++j)
@@ -278,20 +315,28 @@ long pbo_band(const int* dims, const double* origin, double h, const double* phi
         if (!(f > -eps && f < eps)) continue;
         if (i == 0 || j == 0 || k == 0 || i == dims[0] - 1 || j == dims[1] - 1 || k == dims[2] - 1) return -1;
         if (nodes) {
-          double gx = (phi[lin(dims, i + 1, j, k)] - phi[lin(dims, i - 1, j, k)]) / (2.0 * h);
-          double gy = (phi[lin(dims, i, j + 1, k)] - phi[lin(dims, i, j - 1, k)]) / (2.0 * h);
-          double gz = (phi[lin(dims, i, j, k + 1)] - phi[lin(dims, i, j, k - 1)]) / (2.0 * h);
-          double gn = sqrt((gx * gx + gy * gy) + gz * gz);
-          double nx = gx / gn, ny = gy / gn, nz = gz / gn;
+          double g[3];
+          if (grad_scheme == 1) {
+            double m[3], p[3];
+            pbo_weno_grad(dims, h, phi, id, m, p);
+            for (int a = 0; a < 3; ++a) g[a] = (m[a] + p[a]) / 2.0;
+          } else {
+            g[0] = (phi[lin(dims, i + 1, j, k)] - phi[lin(dims, i - 1, j, k)]) / (2.0 * h);
+            g[1] = (phi[lin(dims, i, j + 1, k)] - phi[lin(dims, i, j - 1, k)]) / (2.0 * h);
+            g[2] = (phi[lin(dims, i, j, k + 1)] - phi[lin(dims, i, j, k - 1)]) / (2.0 * h);
+          }
+          double gn = sqrt((g[0] * g[0] + g[1] * g[1]) + g[2] * g[2]);
+          double nv[3] = {g[0] / gn, g[1] / gn, g[2] / gn};
           double* o = nodes + 8 * cnt;
-          o[0] = origin[0] + h * (double)i - f * nx;
-          o[1] = origin[1] + h * (double)j - f * ny;
-          o[2] = origin[2] + h * (double)k - f * nz;
-          o[3] = nx;
-          o[4] = ny;
-          o[5] = nz;
+          o[0] = origin[0] + h * (double)i - f * nv[0];
+          o[1] = origin[1] + h * (double)j - f * nv[1];
+          o[2] = origin[2] + h * (double)k - f * nv[2];
+          o[3] = nv[0];
+          o[4] = nv[1];
+          o[5] = nv[2];
           o[6] = f;
           o[7] = pbo_delta(f, eps);
+          if (jacobian) o[7] *= pbo_jacobian(dims, h, phi, id, nv);
         }
         if (gidx) gidx[cnt] = id;
         ++cnt;

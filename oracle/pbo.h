@@ -13,7 +13,8 @@
  *           origin + h·(i,j,k) and has linear index (i·ny + j)·nz + k.
  *   nodes : band node table, n × 8 rows (x*, y*, z*, n_x, n_y, n_z, φ, ω), where
  *           x* is the closest-point projection, n the unit normal, φ the level-set
- *           value and ω = δ_ε(φ) (J ≡ 1). h³ is applied inside the sums.
+ *           value and ω = δ_ε(φ)·J (J ≡ 1 unless the explicit J is asked for). h³ is
+ *           applied inside the sums.
  *   prm   : parameter vector, PBO_NPRM doubles, indices below.
  *   p     : 2n vector [ψ̄(nodes in band order); ψ̄_n(same order)].
  */
@@ -49,9 +50,13 @@ long pbo_ses(const int* dims, const double* origin, const double* atoms, int n_a
 void pbo_weno_grad(const int* dims, double h, const double* phi, long node, double* minus3, double* plus3);
 
 /* Stage 2 — band selection, projection, weights. Returns the node count;
-   nodes/gidx may be NULL to count only. Returns -1 if a band node touches the grid edge. */
-long pbo_band(const int* dims, const double* origin, double h, const double* phi, double eps,
-              double* nodes, long* gidx);
+   nodes/gidx may be NULL to count only. Returns -1 if a band node touches the grid edge.
+   grad_scheme: 0 central differences, 1 WENO5 average (p₋ + p₊)/2. jacobian: 0 J ≡ 1,
+   1 the explicit J (pbo_jacobian). */
+long pbo_band(const int* dims, const double* origin, double h, const double* phi, double eps, int grad_scheme,
+              int jacobian, double* nodes, long* gidx);
+/* J = 1 − φΔφ + φ²⟨n, adj(∇²φ) n⟩ at an interior grid node with unit normal n (3 doubles). */
+double pbo_jacobian(const int* dims, double h, const double* phi, long node, const double* n);
 double pbo_delta(double eta, double eps);
 
 /* Stage 3 — kernels, operator, right-hand side, GMRES. */

@@ -1,6 +1,8 @@
 // Stage 2: order-preserving compaction of the narrow band −ε < φ < ε, with the
-// closest-point projection x* = x − φ n, n = ∇φ/|∇φ| (central differences) and the cosine
-// weight ω = δ_ε(φ) (eq. cosine-kernel, J ≡ 1).
+// closest-point projection x* = x − φ n, n = ∇φ/|∇φ| (central differences, or the average
+// of the two WENO5 one-sided derivatives per axis) and the weight ω = δ_ε(φ)·J
+// (eq. cosine-kernel; J ≡ 1 or the explicit J of section "Implicit boundary integral
+// methods", read with the adjugate of the Hessian).
 //
 // Three passes over the grid, each block owning one contiguous tile of kTile linear
 // indices: count the band nodes of each tile, scan the tile counts, then scatter. Inside a
@@ -9,6 +11,7 @@
 #include <cmath>
 
 #include "pb_internal.hpp"
+#include "stencil.hpp"
 
 #pragma clang fp contract(off)
 
@@ -45,7 +48,43 @@ __global__ void __launch_bounds__(kBlock) k_count(const double* __restrict__ phi
   }
 }
 
+// (p₋ + p₊)/2 along one axis: WENO5 one-sided derivatives of φ at node id (coordinate c of
+// n along the axis, stride st), ghosts by even reflection about the boundary node as in the
+// level-set stage. ih = 1/h.
+__device__ double weno_average(const double* __restrict__ phi, int64_t id, int64_t c, int64_t n, int64_t st,
+                               double ih) {
+  double f[7];
+  for (int s = -3; s <= 3; ++s) {
+    int64_t q = c + s;
+    q = q < 0 ? -q : (q > n - 1 ? 2 * (n - 1) - q : q);
+    f[s + 3] = phi[id + (q - c) * st];
+  }
+  double D[6];
+  for (int m = 0; m < 6; ++m) D[m] = (f[m + 1] - f[m]) * ih;
+  const double a = weno5(D[0], D[1], D[2], D[3], D[4]);
+  const double b = weno5(D[5], D[4], D[3], D[2], D[1]);
+  return (a + b) * 0.5;
+}
+
+// J = 1 − φ tr(H) + φ² nᵀ adj(H) n at an interior node, H the central-difference Hessian
+// (mixed terms from the four diagonal neighbours), adj(H) the adjugate of the symmetric H.
+__device__ double jacobian(const double* __restrict__ phi, int64_t id, int64_t si, int64_t sj, double h, double f,
+                           double nx, double ny, double nz) {
+  const double ih2 = 1.0 / (h * h), iq = 0.25 * ih2;
+  const double hxx = (phi[id + si] - 2.0 * f + phi[id - si]) * ih2;
+  const double hyy = (phi[id + sj] - 2.0 * f + phi[id - sj]) * ih2;
+  const double hzz = (phi[id + 1] - 2.0 * f + phi[id - 1]) * ih2;
+  const double hxy = (phi[id + si + sj] - phi[id + si - sj] - phi[id - si + sj] + phi[id - si - sj]) * iq;
+  const double hxz = (phi[id + si + 1] - phi[id + si - 1] - phi[id - si + 1] + phi[id - si - 1]) * iq;
+  const double hyz = (phi[id + sj + 1] - phi[id + sj - 1] - phi[id - sj + 1] + phi[id - sj - 1]) * iq;
+  const double axx = hyy * hzz - hyz * hyz, ayy = hxx * hzz - hxz * hxz, azz = hxx * hyy - hxy * hxy;
+  const double axy = hxz * hyz - hxy * hzz, axz = hxy * hyz - hxz * hyy, ayz = hxy * hxz - hxx * hyz;
+  const double q = axx * nx * nx + ayy * ny * ny + azz * nz * nz + 2.0 * (axy * nx * ny + axz * nx * nz + ayz * ny * nz);
+  return 1.0 - f * (hxx + hyy + hzz) + f * f * q;
+}
+
 __global__ void __launch_bounds__(kBlock) k_scatter(GridDev g, const double* __restrict__ phi, double eps,
+                                                    int grad_scheme, int full_jacobian,
                                                     const int64_t* __restrict__ offsets, int64_t capacity,
                                                     pb_band band, int* __restrict__ bad) {
   __shared__ int wave_cnt[kBlock / 64];
@@ -74,9 +113,17 @@ __global__ void __launch_bounds__(kBlock) k_scatter(GridDev g, const double* __r
       continue;
     }
     const int64_t si = (int64_t)g.ny * g.nz, sj = g.nz;
-    double gx = (phi[id + si] - phi[id - si]) / (2.0 * g.h);
-    double gy = (phi[id + sj] - phi[id - sj]) / (2.0 * g.h);
-    double gz = (phi[id + 1] - phi[id - 1]) / (2.0 * g.h);
+    double gx, gy, gz;
+    if (grad_scheme == PB_GRAD_WENO) {
+      const double ih = 1.0 / g.h;
+      gx = weno_average(phi, id, i, g.nx, si, ih);
+      gy = weno_average(phi, id, j, g.ny, sj, ih);
+      gz = weno_average(phi, id, k, g.nz, 1, ih);
+    } else {
+      gx = (phi[id + si] - phi[id - si]) / (2.0 * g.h);
+      gy = (phi[id + sj] - phi[id - sj]) / (2.0 * g.h);
+      gz = (phi[id + 1] - phi[id - 1]) / (2.0 * g.h);
+    }
     double gn = sqrt((gx * gx + gy * gy) + gz * gz);
     if (!(gn > 0.0)) {
       atomicOr(bad, 2);
@@ -90,7 +137,9 @@ __global__ void __launch_bounds__(kBlock) k_scatter(GridDev g, const double* __r
     band.ny[pos] = ny;
     band.nz[pos] = nz;
     band.phi[pos] = f;
-    band.w[pos] = (1.0 + cos(kPi * f / eps)) / (2.0 * eps);
+    double w = (1.0 + cos(kPi * f / eps)) / (2.0 * eps);
+    if (full_jacobian) w *= jacobian(phi, id, si, sj, g.h, f, nx, ny, nz);
+    band.w[pos] = w;
     if (band.gidx) band.gidx[pos] = id;
   }
 }
@@ -131,7 +180,8 @@ extern "C" pb_status pb_narrowband_compact(pb_ctx* ctx, const pb_grid* grid, con
   PB_HIP(ctx, hipMemsetAsync(bad, 0, sizeof(int), ctx->stream));
   {
     Scope t(ctx, "band");
-    k_scatter<<<(unsigned)nb, kBlock, 0, ctx->stream>>>(g, phi, eps, counts, band->capacity, *band, bad);
+    k_scatter<<<(unsigned)nb, kBlock, 0, ctx->stream>>>(g, phi, eps, prm->grad_scheme, prm->jacobian, counts,
+                                                        band->capacity, *band, bad);
   }
   PB_TRY(launch_ok(ctx, "band scatter"));
   int badh = 0;

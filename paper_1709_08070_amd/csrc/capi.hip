@@ -131,6 +131,8 @@ pb_status check_params(pb_ctx* ctx, const pb_params* p) {
   if (p->reg_metric < 0 || p->reg_metric > 2) return ctx->fail(PB_EINVAL, "unknown reg_metric %d", p->reg_metric);
   if (p->ls_mode < 0 || p->ls_mode > 1) return ctx->fail(PB_EINVAL, "unknown ls_mode %d", p->ls_mode);
   if (p->reinit_steps < 0) return ctx->fail(PB_EINVAL, "reinit_steps must be >= 0");
+  if (p->grad_scheme < 0 || p->grad_scheme > 1) return ctx->fail(PB_EINVAL, "unknown grad_scheme %d", p->grad_scheme);
+  if (p->jacobian < 0 || p->jacobian > 1) return ctx->fail(PB_EINVAL, "unknown jacobian %d", p->jacobian);
   return PB_OK;
 }
 
@@ -253,6 +255,8 @@ void pb_default_params(pb_params* p) {
   p->cfl = 0.3;
   p->near_k = 2.0;
   p->reg_metric = PB_REG_TANGENT_GUARDED;
+  p->grad_scheme = PB_GRAD_CENTRAL;
+  p->jacobian = PB_JAC_ONE;
   p->ls_mode = PB_LS_SES;
   p->reinit_steps = 0;
 }

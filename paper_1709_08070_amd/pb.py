@@ -22,6 +22,8 @@ PB_LS_VDW, PB_LS_SES = 0, 1
 PB_FP64, PB_MIXED = 0, 1
 PB_X0_ZERO, PB_X0_DIAG, PB_X0_USER, PB_X0_LEARNED = 0, 1, 2, 3
 PB_PRECOND_NONE, PB_PRECOND_LEARNED = 0, 1
+PB_GRAD_CENTRAL, PB_GRAD_WENO = 0, 1
+PB_JAC_ONE, PB_JAC_FULL = 0, 1
 KCAL_PER_UNIT = 4.0 * np.pi * 332.0637
 
 EXPORTS = [
@@ -37,7 +39,7 @@ class pb_params(C.Structure):
     _fields_ = [("eps_in", C.c_double), ("eps_out", C.c_double), ("kappa", C.c_double), ("probe", C.c_double),
                 ("h", C.c_double), ("band_k", C.c_double), ("tau_k", C.c_double), ("cfl", C.c_double),
                 ("near_k", C.c_double), ("reg_metric", C.c_int), ("ls_mode", C.c_int), ("reinit_steps", C.c_int),
-                ("reserved", C.c_int)]
+                ("grad_scheme", C.c_int), ("jacobian", C.c_int)]
 
 
 class pb_grid(C.Structure):
