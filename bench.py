@@ -295,6 +295,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 time-to-solution comparison")
+    ap.add_argument("--no-tree", action="store_true", help="skip the treecode time-to-solution legs")
     ap.add_argument("--learned-train", type=int, default=0, metavar="N",
                     help="train the learned preconditioner on N generated molecules (200-1500 atoms, h=0.5) and "
                          "add its time-to-tolerance on the (held-out) workload molecule")
@@ -419,6 +420,32 @@ def main():
             ttsol["speedup_learned_mixed_vs_mixed"] = ttsol["mixed_s"] / t3
             ttsol["network"] = rec
             log(f"time to {args.tol:g}: learned mixed {t3:.3f} s, {st3.iters} iterations")
+        if not args.no_tree:
+            # treecode far field as the inner operator (the exact FP64 residual stays outside)
+            legs = [("tree", {})]
+            if net is not None:
+                legs.append(("learned_tree", dict(x0=pb.PB_X0_LEARNED, precond=pb.PB_PRECOND_LEARNED, nn=net.handle)))
+            for name, kw in legs:
+                o = pb.solve_opts(tol=args.tol, precision=pb.PB_TREE, **kw)
+                q = torch.zeros_like(p)
+                log(f"time to {args.tol:g}: {name} solve")
+                t4, st4 = timed_solve(ctx, band, at, prm, o, q)
+                ttsol[name + "_s"] = t4
+                ttsol[name + "_iters"] = st4.iters
+                ttsol[name + "_outer"] = st4.outer
+                ttsol[name + "_relres"] = st4.true_relres
+                ttsol[name + "_g_pol_kcal"] = pb.pb_solvation_energy(ctx, band, at, prm, q).g_pol_kcal
+                ttsol["speedup_" + name + "_vs_fp64"] = ttsol["fp64_s"] / t4
+                log(f"time to {args.tol:g}: {name} {t4:.3f} s, {st4.iters} iterations, {st4.outer} outer steps")
+            ctx.set_timing(True)
+            ms0, c0 = ctx.kernel_time("tree_f32")
+            for _ in range(3):
+                pb.pb_ibim_matvec(ctx, band, prm, p, pb.PB_TREE)
+            ms1, c1 = ctx.kernel_time("tree_f32")
+            ctx.set_timing(False)
+            ttsol["tree_operator"] = dict(degree=prm.tree_degree, theta=prm.tree_theta,
+                                          far_ms=(ms1 - ms0) / max(c1 - c0, 1), **ctx.tree_info())
+            ttsol["energy_rel_diff_tree_vs_fp64"] = abs(ttsol["tree_g_pol_kcal"] / ttsol["fp64_g_pol_kcal"] - 1)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -51,9 +51,14 @@ enum { PB_REG_TANGENT_GUARDED = 0, PB_REG_TANGENT = 1, PB_REG_EUCLIDEAN = 2 };
 /* Level set: van der Waals union F(x) = min_k(|x − z_k| − r_k) (exact signed distance for a
    single atom), or the solvent excluded surface of Stage 1. */
 enum { PB_LS_VDW = 0, PB_LS_SES = 1 };
-/* Arithmetic of the operator: FP64 everywhere, or FP32 pair kernels with FP64 near field,
-   FP64 accumulation and FP64 iterative refinement. */
-enum { PB_FP64 = 0, PB_MIXED = 1 };
+/* Arithmetic of the operator: FP64 everywhere; FP32 pair kernels with FP64 near field,
+   FP64 accumulation and FP64 iterative refinement; or the same with the far field from a
+   treecode (Chebyshev proxies of degree tree_degree on octree source clusters accepted at
+   ratio tree_theta; the cluster-particle form of the fast multipole acceleration of section
+   "Fast linear solvers"). In a solve, PB_TREE is the inner operator of the refinement and
+   the residual stays the exact FP64 operator, so the solution meets tol for the exact
+   discrete system. */
+enum { PB_FP64 = 0, PB_MIXED = 1, PB_TREE = 2 };
 /* GMRES initial guess: zero, Λ⁻¹g (the paper's diagonal preconditioner), caller's p, learned. */
 enum { PB_X0_ZERO = 0, PB_X0_DIAG = 1, PB_X0_USER = 2, PB_X0_LEARNED = 3 };
 enum { PB_PRECOND_NONE = 0, PB_PRECOND_LEARNED = 1 };
@@ -77,11 +82,14 @@ typedef struct {
   double tau_k;      /* regularization radius τ = tau_k·h (experiments: 1 or 0.5) */
   double cfl;        /* level-set time step Δt = cfl·h (0.3) */
   double near_k;     /* mixed path: pairs closer than max(near_k·h, 2τ) use the FP64 near field (2) */
+  double tree_theta; /* PB_TREE: a source cluster is interpolated when (r_B + r_C) < θ·distance (0.6) */
   int reg_metric;    /* PB_REG_* */
   int ls_mode;       /* PB_LS_* */
   int reinit_steps;  /* reinitialization steps; 0 = 2·ceil((band_k + 4)/cfl) */
   int grad_scheme;   /* PB_GRAD_* (default central differences) */
   int jacobian;      /* PB_JAC_* (default J ≡ 1) */
+  int tree_degree;   /* PB_TREE: degree p of the Chebyshev proxies per axis, 2..8 (4) */
+  int reserved;
 } pb_params;
 
 typedef struct {
@@ -121,7 +129,8 @@ typedef struct {
   double true_relres;   /* ‖g − Ap‖₂/‖g‖₂ with the FP64 operator, at exit */
   double t_total_s;     /* wall time of the call */
   double t_matvec_s;    /* device time inside the operator kernels */
-  double pairs;         /* pair-interactions evaluated (n² per operator application) */
+  double pairs;         /* pair-interactions evaluated: n² per dense operator application; for
+                           PB_TREE applications the direct, proxy and near-field interactions */
 } pb_solve_stats;
 
 typedef struct {
@@ -280,6 +289,12 @@ pb_status pb_kernel_time(pb_ctx* ctx, const char* name, double* total_ms, int64_
    kernel, 4 the symmetric one. PB_EINVAL if no mixed operator was applied to a band of that
    size yet. */
 pb_status pb_far_kernel(pb_ctx* ctx, int64_t n, int* cfg);
+
+/* Sizes of the treecode last prepared on this context (PB_TREE operator or solve), host
+   array of 6: target batches, proxy clusters, proxy work items, target–source pairs of the
+   direct lists (near pairs included, they contribute zero there), target–proxy
+   interactions, and the FP64 near-field pairs. PB_EINVAL if none was prepared. */
+pb_status pb_tree_info(pb_ctx* ctx, int64_t info[6]);
 
 #ifdef __cplusplus
 }

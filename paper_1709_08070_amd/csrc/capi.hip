@@ -133,6 +133,9 @@ pb_status check_params(pb_ctx* ctx, const pb_params* p) {
   if (p->reinit_steps < 0) return ctx->fail(PB_EINVAL, "reinit_steps must be >= 0");
   if (p->grad_scheme < 0 || p->grad_scheme > 1) return ctx->fail(PB_EINVAL, "unknown grad_scheme %d", p->grad_scheme);
   if (p->jacobian < 0 || p->jacobian > 1) return ctx->fail(PB_EINVAL, "unknown jacobian %d", p->jacobian);
+  if (!(p->tree_theta > 0.0 && p->tree_theta < 1.0)) return ctx->fail(PB_EINVAL, "tree_theta must be in (0, 1)");
+  if (p->tree_degree < 2 || p->tree_degree > kTreeMaxDegree)
+    return ctx->fail(PB_EINVAL, "tree_degree must be in [2, %d]", kTreeMaxDegree);
   return PB_OK;
 }
 
@@ -257,6 +260,8 @@ void pb_default_params(pb_params* p) {
   p->reg_metric = PB_REG_TANGENT_GUARDED;
   p->grad_scheme = PB_GRAD_CENTRAL;
   p->jacobian = PB_JAC_ONE;
+  p->tree_theta = 0.6;
+  p->tree_degree = 4;
   p->ls_mode = PB_LS_SES;
   p->reinit_steps = 0;
 }
@@ -319,6 +324,19 @@ pb_status pb_far_kernel(pb_ctx* ctx, int64_t n, int* cfg) {
   if (n < 1 || n > INT32_MAX || it == ctx->far_cfg.end())
     return ctx->fail(PB_EINVAL, "no far-field kernel chosen for bands of %lld nodes", (long long)n);
   *cfg = it->second;
+  return PB_OK;
+}
+
+pb_status pb_tree_info(pb_ctx* ctx, int64_t info[6]) {
+  if (!ctx || !info) return PB_EINVAL;
+  const pb::TreePlan& T = ctx->tree;
+  if (!T.band_key) return ctx->fail(PB_EINVAL, "no treecode operator prepared on this context");
+  info[0] = T.n_batch;
+  info[1] = T.n_cl;
+  info[2] = T.n_items;
+  info[3] = T.n_dir_pairs;
+  info[4] = T.n_app_pairs;
+  info[5] = T.near.nnz;
   return PB_OK;
 }
 

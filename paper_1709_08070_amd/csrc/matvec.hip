@@ -404,12 +404,20 @@ extern "C" pb_status pb_ibim_matvec(pb_ctx* ctx, const pb_band* band, const pb_p
   PB_TRY(check_band(ctx, band));
   if (!p || !y) return ctx->fail(PB_EINVAL, "pb_ibim_matvec: NULL vector");
   if (p == y) return ctx->fail(PB_EINVAL, "pb_ibim_matvec: p and y must not alias");
-  if (precision != PB_FP64 && precision != PB_MIXED) return ctx->fail(PB_EINVAL, "unknown precision %d", precision);
-  if (precision == PB_MIXED && prm->reg_metric == PB_REG_TANGENT)
+  if (precision != PB_FP64 && precision != PB_MIXED && precision != PB_TREE)
+    return ctx->fail(PB_EINVAL, "unknown precision %d", precision);
+  if (precision != PB_FP64 && prm->reg_metric == PB_REG_TANGENT)
     return ctx->fail(PB_EINVAL, "the mixed path needs a bounded regularization radius (guarded or Euclidean metric)");
   PB_HIP(ctx, hipSetDevice(ctx->device));
   Derived d = derive(*prm);
-  if (precision == PB_MIXED) PB_TRY(mixed_prepare(ctx, band, d));
-  PB_TRY(precision == PB_FP64 ? matvec_fp64(ctx, band, d, p, y) : matvec_mixed(ctx, band, d, p, y));
+  if (precision == PB_FP64) {
+    PB_TRY(matvec_fp64(ctx, band, d, p, y));
+  } else if (precision == PB_MIXED) {
+    PB_TRY(mixed_prepare(ctx, band, d));
+    PB_TRY(matvec_mixed(ctx, band, d, p, y));
+  } else {
+    PB_TRY(tree_prepare(ctx, band, d, prm->tree_degree, prm->tree_theta));
+    PB_TRY(matvec_tree(ctx, band, d, p, y));
+  }
   return sync(ctx, "pb_ibim_matvec");
 }

@@ -63,6 +63,35 @@ struct MixedPlan {
   int far_cfg = 0;                // far-field tile shape chosen by the autotuner
 };
 
+// Treecode far field of the mixed operator for one band (tree.hip): octree over the FP32
+// coordinates in Morton order, target batches with their direct source ranges and proxy
+// clusters, and the buffers of one application. Built once per band.
+constexpr int kTreeMaxDegree = 8;
+struct TreePlan {
+  const void* band_key = nullptr;
+  int64_t n = 0;
+  double rc = 0, theta = 0;
+  int degree = 0;
+  float u[kTreeMaxDegree + 1] = {};  // Chebyshev points of the second kind, cos(πa/p)
+  MixedPlan near;                    // FP32 records (band order) and the FP64 near field
+  int n_batch = 0, n_cl = 0, n_items = 0;
+  int64_t n_dir_pairs = 0, n_app_pairs = 0;  // target–source and target–proxy interactions
+  int* perm = nullptr;               // tree position → band index
+  int2* batch = nullptr;             // target batches (tree-order ranges)
+  int* dir_ptr = nullptr;            // per batch: direct source ranges
+  int2* dir_rng = nullptr;
+  int* app_ptr = nullptr;            // per batch: proxy clusters
+  int* app_cl = nullptr;
+  float4* box = nullptr;             // per cluster: centre, half-widths (scaled coordinates)
+  int4* items = nullptr;             // proxy work items (cluster, begin, end, ·)
+  int* item_ptr = nullptr;           // per cluster: its items
+  float4 *At = nullptr, *Mt = nullptr, *Nt = nullptr;  // records in tree order
+  float4* PX = nullptr;              // proxies: position and Q (scaled coordinates)
+  float* PM = nullptr;               // proxies: M
+  double2* part = nullptr;           // per item partial proxy weights
+  double* far = nullptr;             // far field, band order, 2n
+};
+
 // Per-kernel-family event timing.
 struct Timer {
   double ms = 0.0;
@@ -83,6 +112,7 @@ struct pb_ctx {
   std::vector<hipEvent_t> event_pool;
   int n_cu = 256;
   pb::MixedPlan mixed;
+  pb::TreePlan tree;
   std::map<int, int> far_cfg;          // autotuned far-field tile shape per band size
   std::map<int, int> f64_cfg;          // FP64 operator kernel per band size (0 tiled, 1 symmetric)
   int sym_items_n = -1;                // band size the symmetric kernel's item list was built for
@@ -153,6 +183,9 @@ pb_status nn_batch_prepare(pb_ctx* ctx, int n_mol, const pb_band* bands, const i
 void nn_batch_apply(hipStream_t stream, const pb_nn* net, const NNBatch& nb, const double* V, double* Z, int64_t ldv,
                     const int* kptr, int kmax, double lam1, double lam2);
 pb_status matvec_mixed(pb_ctx* ctx, const pb_band* band, const Derived& d, const double* p, double* y);
+// Treecode far field (tree.hip): degree of the Chebyshev proxies and the acceptance ratio θ.
+pb_status tree_prepare(pb_ctx* ctx, const pb_band* band, const Derived& d, int degree, double theta);
+pb_status matvec_tree(pb_ctx* ctx, const pb_band* band, const Derived& d, const double* p, double* y);
 pb_status rhs(pb_ctx* ctx, const pb_band* band, const double* atoms, int n_atoms, const Derived& d, double* g);
 
 }  // namespace pb

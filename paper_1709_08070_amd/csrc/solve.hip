@@ -252,8 +252,9 @@ extern "C" pb_status pb_ibim_solve(pb_ctx* ctx, const pb_band* band, const doubl
   if (!atoms || n_atoms <= 0 || !p) return ctx->fail(PB_EINVAL, "pb_ibim_solve: NULL or empty input");
   if (!(opts.tol > 0.0) || !std::isfinite(opts.tol)) return ctx->fail(PB_EINVAL, "tolerance must be positive");
   if (opts.max_iter < 1 || opts.restart < 1 || opts.restart > 2000) return ctx->fail(PB_EINVAL, "bad iteration limits");
-  if (opts.precision != PB_FP64 && opts.precision != PB_MIXED) return ctx->fail(PB_EINVAL, "unknown precision");
-  if (opts.precision == PB_MIXED && prm->reg_metric == PB_REG_TANGENT)
+  if (opts.precision != PB_FP64 && opts.precision != PB_MIXED && opts.precision != PB_TREE)
+    return ctx->fail(PB_EINVAL, "unknown precision");
+  if (opts.precision != PB_FP64 && prm->reg_metric == PB_REG_TANGENT)
     return ctx->fail(PB_EINVAL, "the mixed path needs a bounded regularization radius");
   if (opts.x0 < PB_X0_ZERO || opts.x0 > PB_X0_LEARNED) return ctx->fail(PB_EINVAL, "unknown x0 mode %d", opts.x0);
   if (opts.precond != PB_PRECOND_NONE && opts.precond != PB_PRECOND_LEARNED)
@@ -266,7 +267,7 @@ extern "C" pb_status pb_ibim_solve(pb_ctx* ctx, const pb_band* band, const doubl
   PB_TRY(sync(ctx, "pb_ibim_solve"));
   auto matvec_ms = [&]() {
     double tm = 0.0;
-    for (const char* nm : {"p2p_f64", "p2p_f32", "near_f64", "reduce"}) {
+    for (const char* nm : {"p2p_f64", "p2p_f32", "tree_f32", "near_f64", "reduce"}) {
       auto itt = ctx->timers.find(nm);
       if (itt != ctx->timers.end()) tm += itt->second.ms;
     }
@@ -296,6 +297,7 @@ extern "C" pb_status pb_ibim_solve(pb_ctx* ctx, const pb_band* band, const doubl
   PB_TRY(launch_ok(ctx, "x0"));
 
   if (opts.precision == PB_MIXED) PB_TRY(mixed_prepare(ctx, band, d));
+  if (opts.precision == PB_TREE) PB_TRY(tree_prepare(ctx, band, d, prm->tree_degree, prm->tree_theta));
   int n64 = 0, nmx = 0, nnn = 0;
   OpFn op64 = [&](const double* in, double* out) {
     ++n64;
@@ -303,7 +305,7 @@ extern "C" pb_status pb_ibim_solve(pb_ctx* ctx, const pb_band* band, const doubl
   };
   OpFn opmx = [&](const double* in, double* out) {
     ++nmx;
-    return matvec_mixed(ctx, band, d, in, out);
+    return opts.precision == PB_TREE ? matvec_tree(ctx, band, d, in, out) : matvec_mixed(ctx, band, d, in, out);
   };
   OpFn opnn = [&](const double* in, double* out) {
     ++nnn;
@@ -370,7 +372,10 @@ extern "C" pb_status pb_ibim_solve(pb_ctx* ctx, const pb_band* band, const doubl
     stats->matvecs_fp64 = n64;
     stats->matvecs_mixed = nmx;
     stats->true_relres = relres;
-    stats->pairs = (double)(n64 + nmx) * (double)n * (double)n;
+    const double per_mx = opts.precision == PB_TREE
+                              ? (double)(ctx->tree.n_dir_pairs + ctx->tree.n_app_pairs + ctx->tree.near.nnz)
+                              : (double)n * (double)n;
+    stats->pairs = (double)n64 * (double)n * (double)n + (double)nmx * per_mx;
     stats->t_matvec_s = (matvec_ms() - tm0) * 1e-3;
     stats->t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libpb.so")
 PB_OK, PB_EINVAL, PB_ENOMEM, PB_EDEVICE, PB_ECAPACITY, PB_ENOCONV, PB_EGEOM = 0, -1, -2, -3, -4, -5, -6
 PB_REG_TANGENT_GUARDED, PB_REG_TANGENT, PB_REG_EUCLIDEAN = 0, 1, 2
 PB_LS_VDW, PB_LS_SES = 0, 1
-PB_FP64, PB_MIXED = 0, 1
+PB_FP64, PB_MIXED, PB_TREE = 0, 1, 2
 PB_X0_ZERO, PB_X0_DIAG, PB_X0_USER, PB_X0_LEARNED = 0, 1, 2, 3
 PB_PRECOND_NONE, PB_PRECOND_LEARNED = 0, 1
 PB_GRAD_CENTRAL, PB_GRAD_WENO = 0, 1
@@ -29,7 +29,7 @@ KCAL_PER_UNIT = 4.0 * np.pi * 332.0637
 EXPORTS = [
     "pb_create", "pb_destroy", "pb_last_error", "pb_default_params", "pb_default_solve_opts",
     "pb_grid_for_atoms", "pb_build_levelset", "pb_narrowband_compact", "pb_ibim_rhs", "pb_ibim_matvec",
-    "pb_ibim_solve", "pb_solvation_energy", "pb_set_timing", "pb_kernel_time", "pb_ibim_solve_batched",
+    "pb_ibim_solve", "pb_solvation_energy", "pb_set_timing", "pb_kernel_time", "pb_tree_info", "pb_ibim_solve_batched",
     "pb_nn_create", "pb_nn_destroy", "pb_nn_param_count", "pb_nn_get_params", "pb_nn_set_params", "pb_nn_prepare",
     "pb_nn_apply", "pb_nn_train_step", "pb_nn_geometry", "pb_far_kernel",
 ]
@@ -38,8 +38,8 @@ EXPORTS = [
 class pb_params(C.Structure):
     _fields_ = [("eps_in", C.c_double), ("eps_out", C.c_double), ("kappa", C.c_double), ("probe", C.c_double),
                 ("h", C.c_double), ("band_k", C.c_double), ("tau_k", C.c_double), ("cfl", C.c_double),
-                ("near_k", C.c_double), ("reg_metric", C.c_int), ("ls_mode", C.c_int), ("reinit_steps", C.c_int),
-                ("grad_scheme", C.c_int), ("jacobian", C.c_int)]
+                ("near_k", C.c_double), ("tree_theta", C.c_double), ("reg_metric", C.c_int), ("ls_mode", C.c_int), ("reinit_steps", C.c_int),
+                ("grad_scheme", C.c_int), ("jacobian", C.c_int), ("tree_degree", C.c_int), ("reserved", C.c_int)]
 
 
 class pb_grid(C.Structure):
@@ -116,6 +116,7 @@ def load(path: str = LIB_PATH):
     L.pb_set_timing.argtypes = [vp, C.c_int]
     L.pb_kernel_time.argtypes = [vp, C.c_char_p, P(C.c_double), P(C.c_int64)]
     L.pb_far_kernel.argtypes = [vp, C.c_int64, P(C.c_int)]
+    L.pb_tree_info.argtypes = [vp, P(C.c_int64)]
     for name in EXPORTS:
         if name not in ("pb_destroy", "pb_last_error", "pb_default_params", "pb_default_solve_opts", "pb_nn_destroy",
                         "pb_nn_param_count"):
@@ -182,6 +183,12 @@ class Context:
         ms, cnt = C.c_double(), C.c_int64()
         self.check(lib.pb_kernel_time(self.handle, name.encode(), C.byref(ms), C.byref(cnt)))
         return ms.value, cnt.value
+
+    def tree_info(self) -> dict:
+        info = (C.c_int64 * 6)()
+        self.check(lib.pb_tree_info(self.handle, info))
+        keys = ("batches", "clusters", "proxy_items", "direct_pairs", "proxy_interactions", "near_pairs")
+        return dict(zip(keys, [int(v) for v in info]))
 
     def far_kernel(self, n: int) -> int:
         cfg = C.c_int()
