@@ -126,7 +126,8 @@ def timed_solve(ctx, band, at, prm, opts, q, warm=True):
 
 def bench_heldout(args):
     """Time to 1e-6 on held-out 5000-atom globules (h = 0.5): plain FP64 GMRES, mixed
-    GMRES-IR, and mixed with the learned x0 and right preconditioner."""
+    GMRES-IR, and mixed with the learned x0 and right preconditioner, the latter also with the
+    treecode far field as the inner operator."""
     import torch
 
     from paper_1709_08070_amd import pb, synth
@@ -151,11 +152,15 @@ def bench_heldout(args):
         for name, o in (("fp64", pb.solve_opts(tol=args.tol, precision=pb.PB_FP64)),
                         ("mixed", pb.solve_opts(tol=args.tol, precision=pb.PB_MIXED)),
                         ("learned_mixed", pb.solve_opts(tol=args.tol, precision=pb.PB_MIXED, x0=pb.PB_X0_LEARNED,
-                                                        precond=pb.PB_PRECOND_LEARNED, nn=net.handle))):
+                                                        precond=pb.PB_PRECOND_LEARNED, nn=net.handle)),
+                        ("learned_tree", pb.solve_opts(tol=args.tol, precision=pb.PB_TREE, x0=pb.PB_X0_LEARNED,
+                                                       precond=pb.PB_PRECOND_LEARNED, nn=net.handle))):
             t, st = timed_solve(ctx, band, at, prm, o, q)
             row[name + "_s"] = t
             row[name + "_iters"] = st.iters
             row[name + "_relres"] = st.true_relres
+            if name == "learned_tree":
+                row["learned_tree_fallback"] = st.fallback_used
             if name == "learned_mixed":
                 row["learned_fallback"] = st.fallback_used
                 pairs += st.pairs
@@ -163,20 +168,24 @@ def bench_heldout(args):
             row[name + "_g_pol_kcal"] = pb.pb_solvation_energy(ctx, band, at, prm, q).g_pol_kcal
         log(f"held-out {i}: n={band.n} fp64 {row['fp64_s']:.2f}s/{row['fp64_iters']} it, mixed "
             f"{row['mixed_s']:.2f}s/{row['mixed_iters']} it, learned {row['learned_mixed_s']:.2f}s/"
-            f"{row['learned_mixed_iters']} it (fallback {row['learned_fallback']})")
+            f"{row['learned_mixed_iters']} it (fallback {row['learned_fallback']}), learned tree "
+            f"{row['learned_tree_s']:.2f}s/{row['learned_tree_iters']} it")
         rows.append(row)
 
     def mean(k):
         return sum(r[k] for r in rows) / len(rows)
 
-    ttsol = {k: mean(k) for k in ("fp64_s", "mixed_s", "learned_mixed_s", "fp64_iters", "mixed_iters",
-                                  "learned_mixed_iters")}
+    ttsol = {k: mean(k) for k in ("fp64_s", "mixed_s", "learned_mixed_s", "learned_tree_s", "fp64_iters",
+                                  "mixed_iters", "learned_mixed_iters", "learned_tree_iters")}
+    ttsol["speedup_learned_tree_vs_fp64"] = ttsol["fp64_s"] / ttsol["learned_tree_s"]
+    ttsol["max_energy_rel_diff_learned_tree_vs_fp64"] = max(
+        abs(r["learned_tree_g_pol_kcal"] / r["fp64_g_pol_kcal"] - 1) for r in rows)
     ttsol["speedup_mixed_vs_fp64"] = ttsol["fp64_s"] / ttsol["mixed_s"]
     ttsol["speedup_learned_mixed_vs_fp64"] = ttsol["fp64_s"] / ttsol["learned_mixed_s"]
     ttsol["speedup_learned_mixed_vs_mixed"] = ttsol["mixed_s"] / ttsol["learned_mixed_s"]
     ttsol["max_energy_rel_diff_learned_vs_fp64"] = max(
         abs(r["learned_mixed_g_pol_kcal"] / r["fp64_g_pol_kcal"] - 1) for r in rows)
-    ttsol["fallbacks"] = sum(r["learned_fallback"] for r in rows)
+    ttsol["fallbacks"] = sum(r["learned_fallback"] for r in rows) + sum(r["learned_tree_fallback"] for r in rows)
     ttsol["per_molecule"] = rows
     ttsol["network"] = rec
     out = {
@@ -185,7 +194,8 @@ def bench_heldout(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "accumulate": "f64", "data": "synthetic",
         "config": {"workload": f"heldout5000: {n_mol} held-out synthetic globules of {n_atoms} atoms (seeds "
                                f"{seed0}+i), h={h} A, SES; time to {args.tol:g} of FP64 GMRES, mixed GMRES-IR and "
-                               "learned-preconditioned mixed GMRES-IR (value: pair rate of the learned solves)",
+                               "learned-preconditioned mixed GMRES-IR, dense and treecode inner operator "
+                               "(value: pair rate of the learned dense solves)",
                    "parallelism": "single GPU"},
         "time_to_tol": ttsol, "roofline": None, "cpu_baseline": None,
     }
@@ -296,6 +306,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 time-to-solution comparison")
     ap.add_argument("--no-tree", action="store_true", help="skip the treecode time-to-solution legs")
+    ap.add_argument("--legs", default="fp64,mixed,learned,tree,learned_tree",
+                    help="time-to-solution legs, comma separated: fp64, mixed, learned, tree, learned_tree")
     ap.add_argument("--learned-train", type=int, default=0, metavar="N",
                     help="train the learned preconditioner on N generated molecules (200-1500 atoms, h=0.5) and "
                          "add its time-to-tolerance on the (held-out) workload molecule")
@@ -384,68 +396,62 @@ def main():
                 "p2p_f64_avg_ms": f64_ms / max(f64_n, 1), "near_f64_avg_ms": near_ms / max(near_n, 1)}
 
     ttsol = None
-    if not args.no_compare:
+    legs = [] if args.no_compare else [x for x in args.legs.split(",") if x]
+    if args.no_tree:
+        legs = [x for x in legs if "tree" not in x]
+    if legs:
         ttsol = {}
-        for name, prec in (("fp64", pb.PB_FP64), ("mixed", pb.PB_MIXED)):
+        net, rec = load_net(ctx, args) if any(x.startswith("learned") for x in legs) else (None, None)
+        learned_kw = dict(x0=pb.PB_X0_LEARNED, precond=pb.PB_PRECOND_LEARNED, nn=net.handle) if net else None
+        # (name in the record, precision, learned?): FP64 GMRES, mixed GMRES-IR, and the treecode
+        # far field as the inner operator of the refinement (the exact FP64 residual stays outside)
+        table = {"fp64": ("fp64", pb.PB_FP64, False), "mixed": ("mixed", pb.PB_MIXED, False),
+                 "learned": ("learned_mixed", pb.PB_MIXED, True), "tree": ("tree", pb.PB_TREE, False),
+                 "learned_tree": ("learned_tree", pb.PB_TREE, True)}
+        for leg in legs:
+            name, prec, learned = table[leg]
+            if learned and net is None:
+                ttsol[name + "_s"] = None
+                continue
+            o = pb.solve_opts(tol=args.tol, precision=prec, **(learned_kw if learned else {}))
             q = torch.zeros_like(p)
-            o = pb.solve_opts(tol=args.tol, precision=prec)
-            log(f"time to {args.tol:g}: {name} solve (warm-up)")
-            pb.pb_ibim_solve(ctx, band, at, prm, o, q)  # warm
-            torch.cuda.synchronize()
-            log(f"time to {args.tol:g}: {name} solve (timed)")
-            t1 = time.perf_counter()
-            _, st2 = pb.pb_ibim_solve(ctx, band, at, prm, o, q)
-            torch.cuda.synchronize()
-            ttsol[name + "_s"] = time.perf_counter() - t1
-            log(f"time to {args.tol:g}: {name} {ttsol[name + '_s']:.3f} s, {st2.iters} iterations")
-            ttsol[name + "_iters"] = st2.iters
-            ttsol[name + "_relres"] = st2.true_relres
+            log(f"time to {args.tol:g}: {name} solve (one warm-up, one timed)")
+            t, st = timed_solve(ctx, band, at, prm, o, q)
+            ttsol[name + "_s"] = t
+            ttsol[name + "_iters"] = st.iters
+            ttsol[name + "_outer"] = st.outer
+            ttsol[name + "_relres"] = st.true_relres
             ttsol[name + "_g_pol_kcal"] = pb.pb_solvation_energy(ctx, band, at, prm, q).g_pol_kcal
-        ttsol["speedup_mixed_vs_fp64"] = ttsol["fp64_s"] / ttsol["mixed_s"]
-        ttsol["energy_rel_diff_mixed_vs_fp64"] = abs(ttsol["mixed_g_pol_kcal"] / ttsol["fp64_g_pol_kcal"] - 1)
-        ttsol["learned_mixed_s"] = None
-        net, rec = load_net(ctx, args)
+            if learned:
+                ttsol[name + "_fallback"] = st.fallback_used
+            log(f"time to {args.tol:g}: {name} {t:.3f} s, {st.iters} iterations, {st.outer} outer steps")
         if net is not None:
-            o = pb.solve_opts(tol=args.tol, precision=pb.PB_MIXED, x0=pb.PB_X0_LEARNED,
-                              precond=pb.PB_PRECOND_LEARNED, nn=net.handle)
-            q = torch.zeros_like(p)
-            log(f"time to {args.tol:g}: learned mixed solve")
-            t3, st3 = timed_solve(ctx, band, at, prm, o, q)
-            ttsol["learned_mixed_s"] = t3
-            ttsol["learned_mixed_iters"] = st3.iters
-            ttsol["learned_mixed_relres"] = st3.true_relres
-            ttsol["learned_fallback"] = st3.fallback_used
-            ttsol["learned_g_pol_kcal"] = pb.pb_solvation_energy(ctx, band, at, prm, q).g_pol_kcal
-            ttsol["speedup_learned_mixed_vs_fp64"] = ttsol["fp64_s"] / t3
-            ttsol["speedup_learned_mixed_vs_mixed"] = ttsol["mixed_s"] / t3
             ttsol["network"] = rec
-            log(f"time to {args.tol:g}: learned mixed {t3:.3f} s, {st3.iters} iterations")
-        if not args.no_tree:
-            # treecode far field as the inner operator (the exact FP64 residual stays outside)
-            legs = [("tree", {})]
-            if net is not None:
-                legs.append(("learned_tree", dict(x0=pb.PB_X0_LEARNED, precond=pb.PB_PRECOND_LEARNED, nn=net.handle)))
-            for name, kw in legs:
-                o = pb.solve_opts(tol=args.tol, precision=pb.PB_TREE, **kw)
-                q = torch.zeros_like(p)
-                log(f"time to {args.tol:g}: {name} solve")
-                t4, st4 = timed_solve(ctx, band, at, prm, o, q)
-                ttsol[name + "_s"] = t4
-                ttsol[name + "_iters"] = st4.iters
-                ttsol[name + "_outer"] = st4.outer
-                ttsol[name + "_relres"] = st4.true_relres
-                ttsol[name + "_g_pol_kcal"] = pb.pb_solvation_energy(ctx, band, at, prm, q).g_pol_kcal
-                ttsol["speedup_" + name + "_vs_fp64"] = ttsol["fp64_s"] / t4
-                log(f"time to {args.tol:g}: {name} {t4:.3f} s, {st4.iters} iterations, {st4.outer} outer steps")
+        if ttsol.get("fp64_s"):
+            for name in ("mixed", "learned_mixed", "tree", "learned_tree"):
+                if ttsol.get(name + "_s"):
+                    ttsol[f"speedup_{name}_vs_fp64"] = ttsol["fp64_s"] / ttsol[name + "_s"]
+                    ttsol[f"energy_rel_diff_{name}_vs_fp64"] = abs(ttsol[name + "_g_pol_kcal"] /
+                                                                  ttsol["fp64_g_pol_kcal"] - 1)
+        if ttsol.get("mixed_s") and ttsol.get("learned_mixed_s"):
+            ttsol["speedup_learned_mixed_vs_mixed"] = ttsol["mixed_s"] / ttsol["learned_mixed_s"]
+        if any("tree" in x for x in legs):
             ctx.set_timing(True)
             ms0, c0 = ctx.kernel_time("tree_f32")
             for _ in range(3):
                 pb.pb_ibim_matvec(ctx, band, prm, p, pb.PB_TREE)
             ms1, c1 = ctx.kernel_time("tree_f32")
             ctx.set_timing(False)
-            ttsol["tree_operator"] = dict(degree=prm.tree_degree, theta=prm.tree_theta,
-                                          far_ms=(ms1 - ms0) / max(c1 - c0, 1), **ctx.tree_info())
-            ttsol["energy_rel_diff_tree_vs_fp64"] = abs(ttsol["tree_g_pol_kcal"] / ttsol["fp64_g_pol_kcal"] - 1)
+            info = ctx.tree_info()
+            far_ms = (ms1 - ms0) / max(c1 - c0, 1)
+            # algorithmic work: 61 FLOP per direct pair (the dense definition), 36 per
+            # target-proxy interaction; the far-field kernels are bound by the FP32 VALUs
+            flops = 61.0 * info["direct_pairs"] + 36.0 * info["proxy_interactions"]
+            ttsol["tree_operator"] = dict(
+                degree=prm.tree_degree, theta=prm.tree_theta, far_ms=far_ms,
+                algorithmic_tflops=flops / (far_ms * 1e-3) / 1e12 if far_ms > 0 else None,
+                dense_equivalent_pairs_per_s=float(n) * n / (far_ms * 1e-3) if far_ms > 0 else None,
+                mean_batch=n / max(info["batches"], 1), **info)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -55,9 +55,10 @@ enum { PB_LS_VDW = 0, PB_LS_SES = 1 };
    FP64 accumulation and FP64 iterative refinement; or the same with the far field from a
    treecode (Chebyshev proxies of degree tree_degree on octree source clusters accepted at
    ratio tree_theta; the cluster-particle form of the fast multipole acceleration of section
-   "Fast linear solvers"). In a solve, PB_TREE is the inner operator of the refinement and
-   the residual stays the exact FP64 operator, so the solution meets tol for the exact
-   discrete system. */
+   "Fast linear solvers"). In a solve, PB_TREE is the inner operator of the refinement; the
+   refinement's residuals come from the dense PB_MIXED operator until they meet tol/2, and
+   the exact FP64 operator then certifies the result, so the solution meets tol for the
+   exact discrete system. */
 enum { PB_FP64 = 0, PB_MIXED = 1, PB_TREE = 2 };
 /* GMRES initial guess: zero, Λ⁻¹g (the paper's diagonal preconditioner), caller's p, learned. */
 enum { PB_X0_ZERO = 0, PB_X0_DIAG = 1, PB_X0_USER = 2, PB_X0_LEARNED = 3 };

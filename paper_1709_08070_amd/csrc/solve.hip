@@ -296,9 +296,9 @@ extern "C" pb_status pb_ibim_solve(pb_ctx* ctx, const pb_band* band, const doubl
   else if (opts.x0 == PB_X0_LEARNED) PB_TRY(nn_apply(ctx, net, band, d, g, p));
   PB_TRY(launch_ok(ctx, "x0"));
 
-  if (opts.precision == PB_MIXED) PB_TRY(mixed_prepare(ctx, band, d));
+  if (opts.precision != PB_FP64) PB_TRY(mixed_prepare(ctx, band, d));
   if (opts.precision == PB_TREE) PB_TRY(tree_prepare(ctx, band, d, prm->tree_degree, prm->tree_theta));
-  int n64 = 0, nmx = 0, nnn = 0;
+  int n64 = 0, nmx = 0, nmid = 0, nnn = 0;
   OpFn op64 = [&](const double* in, double* out) {
     ++n64;
     return matvec_fp64(ctx, band, d, in, out);
@@ -306,6 +306,13 @@ extern "C" pb_status pb_ibim_solve(pb_ctx* ctx, const pb_band* band, const doubl
   OpFn opmx = [&](const double* in, double* out) {
     ++nmx;
     return opts.precision == PB_TREE ? matvec_tree(ctx, band, d, in, out) : matvec_mixed(ctx, band, d, in, out);
+  };
+  // PB_TREE: the refinement's residuals come from the dense mixed operator (its distance to
+  // the FP64 operator, about 1e-7 relative, is far below the treecode's) until they meet half
+  // the tolerance; the FP64 operator then certifies the result once
+  OpFn opmid = [&](const double* in, double* out) {
+    ++nmid;
+    return matvec_mixed(ctx, band, d, in, out);
   };
   OpFn opnn = [&](const double* in, double* out) {
     ++nnn;
@@ -326,21 +333,29 @@ extern "C" pb_status pb_ibim_solve(pb_ctx* ctx, const pb_band* band, const doubl
     }
     int used = 0, steps = 0;
     {
-      // first pass straight on A_mixed p = g from the initial guess; the FP64 residual below
-      // then decides whether a correction step is needed
+      // first pass straight on the inner operator from the initial guess (A_mixed p = g, or
+      // the treecode's); the residual below then decides whether a correction step is needed
       int it = 0;
       double res = 0.0;
       PB_TRY(gmres(ctx, K, opmx, prec, g, p, 0.5 * opts.tol * gnorm, kInnerEta, iter_budget, &it, &res));
       used += it;
       ++steps;
     }
+    // below about 1e-7 the dense mixed operator is too far from the FP64 one to steer the
+    // refinement, so tighter tolerances use the FP64 residual from the start
+    bool certify = opts.precision != PB_TREE || opts.tol < 1e-7;
     for (;;) {
-      PB_TRY(op64(p, r));
+      PB_TRY(certify ? op64(p, r) : opmid(p, r));
       k_residual<<<vb, kBlock, 0, ctx->stream>>>(M, g, r);
       double rn = 0.0;
       PB_TRY(norm2(ctx, K, r, &rn));
-      relres = rn / gnorm;
-      if (!(relres > opts.tol) || steps >= opts.max_outer || used >= iter_budget) break;
+      if (!certify) {
+        if (!(rn / gnorm > 0.5 * opts.tol) || steps >= opts.max_outer || used >= iter_budget) certify = true;
+        if (certify) continue;  // the FP64 residual of the same iterate decides
+      } else {
+        relres = rn / gnorm;
+        if (!(relres > opts.tol) || steps >= opts.max_outer || used >= iter_budget) break;
+      }
       k_zero<<<vb, kBlock, 0, ctx->stream>>>(M, dx);
       int it = 0;
       double res = 0.0;
@@ -370,12 +385,12 @@ extern "C" pb_status pb_ibim_solve(pb_ctx* ctx, const pb_band* band, const doubl
     stats->converged = relres <= opts.tol;
     stats->fallback_used = fallback;
     stats->matvecs_fp64 = n64;
-    stats->matvecs_mixed = nmx;
+    stats->matvecs_mixed = nmx + nmid;
     stats->true_relres = relres;
     const double per_mx = opts.precision == PB_TREE
                               ? (double)(ctx->tree.n_dir_pairs + ctx->tree.n_app_pairs + ctx->tree.near.nnz)
                               : (double)n * (double)n;
-    stats->pairs = (double)n64 * (double)n * (double)n + (double)nmx * per_mx;
+    stats->pairs = (double)(n64 + nmid) * (double)n * (double)n + (double)nmx * per_mx;
     stats->t_matvec_s = (matvec_ms() - tm0) * 1e-3;
     stats->t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }

@@ -143,3 +143,24 @@ def test_tree_parameter_checks(pbm, ctx, born):
         with pytest.raises(Exception) as e:
             pbm.pb_ibim_matvec(ctx, band, bad, p, pbm.PB_TREE)
         assert "tree_" in str(e.value)
+
+
+def test_learned_tree_solve(pbm, ctx):
+    """The learned x0 and right preconditioner on top of the treecode inner operator: plain
+    GMRES from the same x0 (the fallback) judges it; here it converges, and its energy matches
+    the FP64 solve's."""
+    import os
+
+    say("case: learned + treecode solve, globule 120 atoms seed 31 h=0.5, tol 1e-8 (committed network)")
+    prm, at, band = _pipeline(pbm, ctx, synth.globule(120, 31), 0.5, True)
+    net = pbm.Net(ctx, seed=3)
+    net.load(os.path.join(os.path.dirname(pbm.__file__), "weights", "learned_h0.5.npz"))
+    opts = pbm.solve_opts(tol=1e-8, precision=pbm.PB_TREE, x0=pbm.PB_X0_LEARNED, precond=pbm.PB_PRECOND_LEARNED,
+                          nn=net.handle)
+    q, st = pbm.pb_ibim_solve(ctx, band, at, prm, opts)
+    assert st.converged and st.true_relres <= 1e-8
+    q64, _ = pbm.pb_ibim_solve(ctx, band, at, prm, pbm.solve_opts(tol=1e-8, precision=pbm.PB_FP64))
+    e = pbm.pb_solvation_energy(ctx, band, at, prm, q).g_pol
+    e64 = pbm.pb_solvation_energy(ctx, band, at, prm, q64).g_pol
+    say(f"  iters {st.iters} outer {st.outer} fallback {st.fallback_used}; energy rel diff {abs(e / e64 - 1):.2e}")
+    assert e == pytest.approx(e64, rel=1e-7)
