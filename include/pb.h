@@ -70,6 +70,14 @@ enum { PB_GRAD_CENTRAL = 0, PB_GRAD_WENO = 1 };
    J = 1 − φΔφ + φ²⟨n, adj(∇²φ) n⟩ of section "Implicit boundary integral methods" (read
    with the adjugate of the Hessian; second-order central differences). */
 enum { PB_JAC_ONE = 0, PB_JAC_FULL = 1 };
+/* Values of the regularized pairs (eq. reg-kernel-a, reg-kernel-b): the paper's disc
+   averages (0, K̄12, 0, 0), or with the leading curvature term of the double-layer averages
+   and the exact flat-disc average of K21:
+     K̄11 = −(1 − θ1ā)·c/(8πτ),  K̄22 = −(1 − θ2ā)·c/(8πτ),  K̄21 = (e^{−κτ} − 1 + κτ)/(2πτ³),
+   c = κ1 + κ2 of the surface at the target's projection (pb_band.curv), ā = (2 − (2 + κτ)e^{−κτ})/(κτ)
+   the disc mean of e^{−κr}(1 + κr). PB_AVG_CURVED needs band->curv; the batched solve and the
+   symmetric FP64 kernel take the paper's averages only. */
+enum { PB_AVG_FLAT = 0, PB_AVG_CURVED = 1 };
 
 typedef struct pb_ctx pb_ctx;
 
@@ -90,7 +98,7 @@ typedef struct {
   int grad_scheme;   /* PB_GRAD_* (default central differences) */
   int jacobian;      /* PB_JAC_* (default J ≡ 1) */
   int tree_degree;   /* PB_TREE: degree p of the Chebyshev proxies per axis, 2..8 (4) */
-  int reserved;
+  int reg_avg;       /* PB_AVG_* (default the paper's flat disc averages) */
 } pb_params;
 
 typedef struct {
@@ -107,6 +115,8 @@ typedef struct {
   double *phi;            /* device: level-set value at the node */
   double *w;              /* device: ω = J·δ_ε(φ), J per pb_params.jacobian (h³ is applied by the operator) */
   int64_t *gidx;          /* device: linear grid index of the node */
+  double *curv;           /* device, optional: κ1 + κ2 of Γ at x* from the central-difference Hessian
+                             of φ, written when non-NULL; needed by PB_AVG_CURVED */
 } pb_band;
 
 typedef struct {

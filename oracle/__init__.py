@@ -20,8 +20,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "libpbo.so")
 
-EPS_IN, EPS_OUT, KAPPA, H, BAND, TAU, METRIC, PROBE, CFL, REINIT = range(10)
-NPRM = 10
+EPS_IN, EPS_OUT, KAPPA, H, BAND, TAU, METRIC, PROBE, CFL, REINIT, AVG = range(11)
+NPRM = 11
+AVG_FLAT, AVG_CURVED = 0, 1
 METRIC_GUARDED, METRIC_TANGENT, METRIC_EUCLID = 0, 1, 2
 
 
@@ -58,12 +59,14 @@ def lib():
         L.pbo_band.restype = C.c_long
         L.pbo_delta.argtypes = [C.c_double, C.c_double]
         L.pbo_delta.restype = C.c_double
-        L.pbo_pair.argtypes = [dp, dp, dp, dp, dp, dp]
-        L.pbo_matvec.argtypes = [C.c_long, dp, dp, dp, dp]
-        L.pbo_matvec_rows.argtypes = [C.c_long, dp, dp, dp, lp, C.c_long, dp, dp]
-        L.pbo_dense.argtypes = [C.c_long, dp, dp, dp]
+        L.pbo_pair.argtypes = [dp, dp, dp, dp, dp, C.c_double, dp]
+        L.pbo_matvec.argtypes = [C.c_long, dp, dp, C.c_void_p, dp, dp]
+        L.pbo_matvec_rows.argtypes = [C.c_long, dp, dp, C.c_void_p, dp, lp, C.c_long, dp, dp]
+        L.pbo_dense.argtypes = [C.c_long, dp, dp, C.c_void_p, dp]
+        L.pbo_curvature.argtypes = [ip, C.c_double, dp, C.c_long, dp]
+        L.pbo_curvature.restype = C.c_double
         L.pbo_rhs.argtypes = [C.c_long, dp, dp, C.c_int, dp, dp]
-        L.pbo_gmres.argtypes = [C.c_long, dp, dp, dp, dp, C.c_double, C.c_int, C.c_int, ip, dp]
+        L.pbo_gmres.argtypes = [C.c_long, dp, dp, C.c_void_p, dp, dp, C.c_double, C.c_int, C.c_int, ip, dp]
         L.pbo_gmres.restype = C.c_int
         L.pbo_area.argtypes = [C.c_long, dp, C.c_double]
         L.pbo_area.restype = C.c_double
@@ -82,13 +85,22 @@ def _f64(a):
 
 
 def params(h, eps_in=1.0, eps_out=80.0, kappa=0.1257, band_k=2.0, tau_k=1.0, metric=METRIC_GUARDED,
-           probe=1.4, cfl=0.3, reinit_steps=0):
-    """Parameter vector: ε = band_k·h, τ = tau_k·h (the experiments use ε = 2h, τ ∈ {h, h/2})."""
+           probe=1.4, cfl=0.3, reinit_steps=0, avg=AVG_FLAT):
+    """Parameter vector: ε = band_k·h, τ = tau_k·h (the experiments use ε = 2h, τ ∈ {h, h/2});
+    avg: disc averages of the regularized pairs (the paper's, or curvature-corrected)."""
     p = np.zeros(NPRM)
     p[EPS_IN], p[EPS_OUT], p[KAPPA], p[H] = eps_in, eps_out, kappa, h
     p[BAND], p[TAU], p[METRIC] = band_k * h, tau_k * h, metric
-    p[PROBE], p[CFL], p[REINIT] = probe, cfl, reinit_steps
+    p[PROBE], p[CFL], p[REINIT], p[AVG] = probe, cfl, reinit_steps, avg
     return p
+
+
+def _cv(curv, n):
+    if curv is None:
+        return None, None
+    c = _f64(curv)
+    assert c.shape == (n,)
+    return c, c.ctypes.data_as(C.c_void_p)
 
 
 def grid(atoms, h, margin):
@@ -162,36 +174,47 @@ def jacobian(dims, h, phi, node, n):
     return lib().pbo_jacobian((C.c_int * 3)(*dims), h, _d(_f64(phi)), int(node), _d(_f64(n)))
 
 
+def curvature(dims, h, phi, gidx, nodes):
+    """κ1 + κ2 of the surface at each band node's projection (nodes: the band table, gidx: grid indices)."""
+    phi = _f64(phi)
+    d3 = (C.c_int * 3)(*dims)
+    L = lib()
+    return np.array([L.pbo_curvature(d3, h, _d(phi), int(g), _d(_f64(nd[3:6]))) for g, nd in zip(gidx, nodes)])
+
+
 def delta(eta, eps):
     return lib().pbo_delta(float(eta), float(eps))
 
 
-def pair(x, nx, y, ny, prm):
+def pair(x, nx, y, ny, prm, curv_x=0.0):
     K = np.empty(4)
-    lib().pbo_pair(_d(_f64(x)), _d(_f64(nx)), _d(_f64(y)), _d(_f64(ny)), _d(_f64(prm)), _d(K))
+    lib().pbo_pair(_d(_f64(x)), _d(_f64(nx)), _d(_f64(y)), _d(_f64(ny)), _d(_f64(prm)), float(curv_x), _d(K))
     return K
 
 
-def matvec(nodes, prm, p):
+def matvec(nodes, prm, p, curv=None):
     nodes, prm, p = _f64(nodes), _f64(prm), _f64(p)
+    c, cp = _cv(curv, len(nodes))
     y = np.empty(2 * len(nodes))
-    lib().pbo_matvec(len(nodes), _d(nodes), _d(prm), _d(p), _d(y))
+    lib().pbo_matvec(len(nodes), _d(nodes), _d(prm), cp, _d(p), _d(y))
     return y
 
 
-def matvec_rows(nodes, prm, p, rows):
+def matvec_rows(nodes, prm, p, rows, curv=None):
     nodes, prm, p = _f64(nodes), _f64(prm), _f64(p)
+    c, cp = _cv(curv, len(nodes))
     rows = np.ascontiguousarray(rows, dtype=np.int64)
     y1, y2 = np.empty(len(rows)), np.empty(len(rows))
-    lib().pbo_matvec_rows(len(nodes), _d(nodes), _d(prm), _d(p), rows.ctypes.data_as(C.POINTER(C.c_long)),
+    lib().pbo_matvec_rows(len(nodes), _d(nodes), _d(prm), cp, _d(p), rows.ctypes.data_as(C.POINTER(C.c_long)),
                           len(rows), _d(y1), _d(y2))
     return y1, y2
 
 
-def dense(nodes, prm):
+def dense(nodes, prm, curv=None):
     nodes, prm = _f64(nodes), _f64(prm)
+    c, cp = _cv(curv, len(nodes))
     A = np.empty((2 * len(nodes), 2 * len(nodes)))
-    lib().pbo_dense(len(nodes), _d(nodes), _d(prm), _d(A))
+    lib().pbo_dense(len(nodes), _d(nodes), _d(prm), cp, _d(A))
     return A
 
 
@@ -207,17 +230,19 @@ def lam(prm):
     return 0.5 * (1 + prm[EPS_OUT] / prm[EPS_IN]), 0.5 * (1 + prm[EPS_IN] / prm[EPS_OUT])
 
 
-def gmres(nodes, prm, g, x0=None, tol=1e-8, max_iter=500, restart=200):
+def gmres(nodes, prm, g, x0=None, tol=1e-8, max_iter=500, restart=200, curv=None):
     """GMRES from x0 (default Λ⁻¹g, the paper's diagonal initial guess). Returns (x, iters, relres, ok)."""
     nodes, prm, g = _f64(nodes), _f64(prm), _f64(g)
     n = len(nodes)
+    c, cp = _cv(curv, n)
     if x0 is None:
         l1, l2 = lam(prm)
         x = np.concatenate([g[:n] / l1, g[n:] / l2])
     else:
         x = _f64(x0).copy()
     it, rr = C.c_int(), C.c_double()
-    ok = lib().pbo_gmres(n, _d(nodes), _d(prm), _d(g), _d(x), tol, max_iter, restart, C.byref(it), C.byref(rr))
+    ok = lib().pbo_gmres(n, _d(nodes), _d(prm), cp, _d(g), _d(x), tol, max_iter, restart, C.byref(it),
+                         C.byref(rr))
     return x, it.value, rr.value, bool(ok)
 
 

@@ -273,7 +273,8 @@ double pbo_delta(double eta, double eps) {
    normal of the node. Reading: the printed last term has the Hessian itself, which vanishes
    on ∇φ for a distance function; with the adjugate, J = (1 − φκ1)(1 − φκ2) for the principal
    curvatures κ1, κ2 of the level set through the node, the area ratio of the projection. */
-double pbo_jacobian(const int* dims, double h, const double* phi, long node, const double* n) {
+static void hessian_terms(const int* dims, double h, const double* phi, long node, const double* n, double* trace,
+                          double* q_adj) {
   long k = node % dims[2], j = (node / dims[2]) % dims[1], i = node / ((long)dims[1] * dims[2]);
   double c = phi[node], h2 = h * h;
   double H[3][3];
@@ -296,7 +297,24 @@ double pbo_jacobian(const int* dims, double h, const double* phi, long node, con
   double q = 0.0;
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b) q += n[a] * A[a][b] * n[b];
-  return 1.0 - c * (H[0][0] + H[1][1] + H[2][2]) + c * c * q;
+  *trace = H[0][0] + H[1][1] + H[2][2];
+  *q_adj = q;
+}
+
+double pbo_jacobian(const int* dims, double h, const double* phi, long node, const double* n) {
+  double tr, q, c = phi[node];
+  hessian_terms(dims, h, phi, node, n, &tr, &q);
+  return 1.0 - c * tr + c * c * q;
+}
+
+/* Sum of the principal curvatures of Γ at the projection x* of node (κ1 + κ2 > 0 on a convex
+   surface with outward normals). The level set of φ through the node has curvatures k1, k2 with
+   k1 + k2 = Δφ and k1·k2 = ⟨n, adj(∇²φ) n⟩; moving a distance φ back along the normal gives
+   κ = k/(1 − φk) for each, so κ1 + κ2 = (k1 + k2 − 2φ k1k2)/J with the J above. */
+double pbo_curvature(const int* dims, double h, const double* phi, long node, const double* n) {
+  double tr, q, c = phi[node];
+  hessian_terms(dims, h, phi, node, n, &tr, &q);
+  return (tr - 2.0 * c * q) / (1.0 - c * tr + c * c * q);
 }
 
 /* Nodes with −ε < φ < ε in lexicographic order ("Projections and weights"):
@@ -360,6 +378,34 @@ static double k12_bar(double kappa, double tau) {
   return (exp(-kappa * tau) - 1.0 + kappa * tau) / (2.0 * PI * kappa * tau * tau);
 }
 
+/* Disc averages of K11, K21, K22 over the regularization disc of radius τ at x*, whose
+   surface has curvature sum curv = κ1 + κ2 there. avg = 0 is the paper's choice, all three 0.
+   avg = 1 keeps the leading term of each (reading of the paper's remark that the
+   regularization can be improved):
+   - on the surface, in tangent coordinates (u, v) of y about x, (x − y)·n_y = −½(κ1u² + κ2v²)
+     and (x − y)·n_x = +½(κ1u² + κ2v²) to second order, so K11 = −(κ1u² + κ2v²)(1 − θ1a)/(8πr³)
+     and K22 = −(κ1u² + κ2v²)(1 − θ2a)/(8πr³); over the disc the angular mean of κ1u² + κ2v²
+     is ½(κ1 + κ2)r², which gives the integrals −(κ1 + κ2)τ(1 − θ ā)/8, ā = (1/τ)∫₀^τ a dr
+     = (2 − (2 + κτ)e^{−κτ})/(κτ) (1 at κ = 0), and the averages (÷ πτ²)
+       K̄11 = −(1 − θ1ā)·curv/(8πτ),   K̄22 = −(1 − θ2ā)·curv/(8πτ);
+   - K21 on the flat disc (n_x = n_y, d·n = 0) is (1 − e^{−κr}(1 + κr))/(4πr³), the
+     r-derivative of (e^{−κr} − 1)/r over 4πr: its integral is (e^{−κτ} − 1 + κτ)/(2τ) and
+       K̄21 = (e^{−κτ} − 1 + κτ)/(2πτ³). */
+static void disc_averages(const double* prm, double curv, double* K) {
+  double kappa = prm[PBO_KAPPA], tau = prm[PBO_TAU];
+  double th1 = prm[PBO_EPS_OUT] / prm[PBO_EPS_IN], th2 = prm[PBO_EPS_IN] / prm[PBO_EPS_OUT];
+  K[1] = k12_bar(kappa, tau);
+  if ((int)prm[PBO_AVG] == 0) {
+    K[0] = K[2] = K[3] = 0.0;
+    return;
+  }
+  double kt = kappa * tau;
+  double abar = kappa == 0.0 ? 1.0 : (2.0 - (2.0 + kt) * exp(-kt)) / kt;
+  K[0] = -(1.0 - th1 * abar) * curv / (8.0 * PI * tau);
+  K[2] = (exp(-kt) - 1.0 + kt) / (2.0 * PI * tau * tau * tau);
+  K[3] = -(1.0 - th2 * abar) * curv / (8.0 * PI * tau);
+}
+
 /* The four regularized kernels between target x (normal nx) and source y (normal ny)
    (eq. IBIM-PBE and the regularization subsection):
      K11 = ∂G0/∂n(y) − θ1 ∂Gκ/∂n(y),  θ1 = ε_E/ε_I
@@ -371,8 +417,9 @@ static double k12_bar(double kappa, double tau) {
      ∂G0/∂n(x) = −(d·n_x)/(4πr³),     ∂Gκ/∂n(x) = −E(1+κr)(d·n_x)/(4πr³)
      ∂²G0/∂n(x)∂n(y) = (n_x·n_y)/(4πr³) − 3(d·n_x)(d·n_y)/(4πr⁵)
      ∂²Gκ/∂n(x)∂n(y) = E(1+κr)(n_x·n_y)/(4πr³) − E(3+3κr+κ²r²)(d·n_x)(d·n_y)/(4πr⁵)
-   Regularized pairs take the disc averages 0, K̄12, 0, 0. */
-void pbo_pair(const double* x, const double* nx, const double* y, const double* ny, const double* prm, double* K) {
+   Regularized pairs take the disc averages (disc_averages; curv: κ1 + κ2 at x). */
+void pbo_pair(const double* x, const double* nx, const double* y, const double* ny, const double* prm, double curv,
+              double* K) {
   double th1 = prm[PBO_EPS_OUT] / prm[PBO_EPS_IN], th2 = prm[PBO_EPS_IN] / prm[PBO_EPS_OUT];
   double kappa = prm[PBO_KAPPA], tau = prm[PBO_TAU];
   double dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
@@ -380,10 +427,7 @@ void pbo_pair(const double* x, const double* nx, const double* y, const double* 
   double dnx = (dx * nx[0] + dy * nx[1]) + dz * nx[2];
   double t2 = r2 - dnx * dnx;
   if (regularized(r2, t2, tau, (int)prm[PBO_METRIC])) {
-    K[0] = 0.0;
-    K[1] = k12_bar(kappa, tau);
-    K[2] = 0.0;
-    K[3] = 0.0;
+    disc_averages(prm, curv, K);
     return;
   }
   double dny = (dx * ny[0] + dy * ny[1]) + dz * ny[2];
@@ -405,7 +449,8 @@ void pbo_pair(const double* x, const double* nx, const double* y, const double* 
 
 /* One row of Λp + KWp (eq. final-lin-sys): Λ = diag(½(1+ε_E/ε_I), ½(1+ε_I/ε_E)),
    W = diag(ω) and the sums carry h³ (eq. IBIM-PBE). */
-static void row(long n, const double* nodes, const double* prm, const double* p, long i, double* y1, double* y2) {
+static void row(long n, const double* nodes, const double* prm, const double* curv, const double* p, long i, double* y1,
+                double* y2) {
   double h3 = prm[PBO_H] * prm[PBO_H] * prm[PBO_H];
   double lam1 = 0.5 * (1.0 + prm[PBO_EPS_OUT] / prm[PBO_EPS_IN]);
   double lam2 = 0.5 * (1.0 + prm[PBO_EPS_IN] / prm[PBO_EPS_OUT]);
@@ -413,7 +458,7 @@ static void row(long n, const double* nodes, const double* prm, const double* p,
   double s1 = 0.0, s2 = 0.0, K[4];
   for (long j = 0; j < n; ++j) {
     const double* yj = nodes + 8 * j;
-    pbo_pair(xi, xi + 3, yj, yj + 3, prm, K);
+    pbo_pair(xi, xi + 3, yj, yj + 3, prm, curv ? curv[i] : 0.0, K);
     double wpsi = h3 * yj[7] * p[j], wpsn = h3 * yj[7] * p[n + j];
     s1 += K[0] * wpsi - K[1] * wpsn;
     s2 += K[2] * wpsi - K[3] * wpsn;
@@ -422,19 +467,19 @@ static void row(long n, const double* nodes, const double* prm, const double* p,
   *y2 = lam2 * p[n + i] + s2;
 }
 
-void pbo_matvec(long n, const double* nodes, const double* prm, const double* p, double* y) {
+void pbo_matvec(long n, const double* nodes, const double* prm, const double* curv, const double* p, double* y) {
 #pragma omp parallel for schedule(dynamic, 16)
-  for (long i = 0; i < n; ++i) row(n, nodes, prm, p, i, y + i, y + n + i);
+  for (long i = 0; i < n; ++i) row(n, nodes, prm, curv, p, i, y + i, y + n + i);
 }
 
-void pbo_matvec_rows(long n, const double* nodes, const double* prm, const double* p,
+void pbo_matvec_rows(long n, const double* nodes, const double* prm, const double* curv, const double* p,
                      const long* rows, long n_rows, double* y1, double* y2) {
 #pragma omp parallel for schedule(dynamic, 4)
-  for (long q = 0; q < n_rows; ++q) row(n, nodes, prm, p, rows[q], y1 + q, y2 + q);
+  for (long q = 0; q < n_rows; ++q) row(n, nodes, prm, curv, p, rows[q], y1 + q, y2 + q);
 }
 
 /* Dense 2n × 2n matrix Λ + KW, row-major. */
-void pbo_dense(long n, const double* nodes, const double* prm, double* A) {
+void pbo_dense(long n, const double* nodes, const double* prm, const double* curv, double* A) {
   double h3 = prm[PBO_H] * prm[PBO_H] * prm[PBO_H];
   double lam1 = 0.5 * (1.0 + prm[PBO_EPS_OUT] / prm[PBO_EPS_IN]);
   double lam2 = 0.5 * (1.0 + prm[PBO_EPS_IN] / prm[PBO_EPS_OUT]);
@@ -445,7 +490,7 @@ void pbo_dense(long n, const double* nodes, const double* prm, double* A) {
     double K[4];
     for (long j = 0; j < n; ++j) {
       const double* yj = nodes + 8 * j;
-      pbo_pair(xi, xi + 3, yj, yj + 3, prm, K);
+      pbo_pair(xi, xi + 3, yj, yj + 3, prm, curv ? curv[i] : 0.0, K);
       double w = h3 * yj[7];
       A[i * m + j] = K[0] * w;
       A[i * m + n + j] = -K[1] * w;
@@ -488,7 +533,7 @@ static double dot(long m, const double* a, const double* b) {
    stopping when ‖g − Ax‖₂/‖g‖₂ ≤ tol (section "Fast linear solvers"). x holds the
    initial guess on entry. iters counts operator applications inside Arnoldi; relres
    is the true relative residual at exit. Returns 1 if converged. */
-int pbo_gmres(long n, const double* nodes, const double* prm, const double* g, double* x,
+int pbo_gmres(long n, const double* nodes, const double* prm, const double* curv, const double* g, double* x,
               double tol, int max_iter, int restart, int* iters, double* relres) {
   long m2 = 2 * n;
   int mr = restart;
@@ -503,7 +548,7 @@ int pbo_gmres(long n, const double* nodes, const double* prm, const double* g, d
   int it = 0, converged = 0;
   if (gnorm == 0.0) gnorm = 1.0;
   while (!converged) {
-    pbo_matvec(n, nodes, prm, x, r);
+    pbo_matvec(n, nodes, prm, curv, x, r);
     for (long q = 0; q < m2; ++q) r[q] = g[q] - r[q];
     double beta = sqrt(dot(m2, r, r));
     if (beta / gnorm <= tol) { converged = 1; break; }
@@ -514,7 +559,7 @@ int pbo_gmres(long n, const double* nodes, const double* prm, const double* g, d
     int k = 0;
     for (; k < mr && it < max_iter; ++k) {
       double* w = V + (size_t)(k + 1) * m2;
-      pbo_matvec(n, nodes, prm, V + (size_t)k * m2, w);
+      pbo_matvec(n, nodes, prm, curv, V + (size_t)k * m2, w);
       ++it;
       for (int i = 0; i <= k; ++i) {
         double hik = dot(m2, w, V + (size_t)i * m2);
@@ -548,7 +593,7 @@ int pbo_gmres(long n, const double* nodes, const double* prm, const double* g, d
     for (int i = 0; i < k; ++i)
       for (long q = 0; q < m2; ++q) x[q] += yv[i] * V[(size_t)i * m2 + q];
   }
-  pbo_matvec(n, nodes, prm, x, r);
+  pbo_matvec(n, nodes, prm, curv, x, r);
   for (long q = 0; q < m2; ++q) r[q] = g[q] - r[q];
   double rr = sqrt(dot(m2, r, r)) / gnorm;
   *relres = rr;

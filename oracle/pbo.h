@@ -35,7 +35,8 @@ enum {
   PBO_PROBE = 7,    /* probe radius ρ0 */
   PBO_CFL = 8,      /* Δt / h for level-set time stepping */
   PBO_REINIT = 9,   /* reinitialization steps (0 → 2·ceil((ε/h + 4)/cfl)) */
-  PBO_NPRM = 10
+  PBO_AVG = 10,     /* disc averages of regularized pairs: 0 the paper's (0, K̄12, 0, 0), 1 curvature-corrected */
+  PBO_NPRM = 11
 };
 
 /* Grid that covers the atoms with the given margin, nodes on hℤ³. */
@@ -57,16 +58,20 @@ long pbo_band(const int* dims, const double* origin, double h, const double* phi
               int jacobian, double* nodes, long* gidx);
 /* J = 1 − φΔφ + φ²⟨n, adj(∇²φ) n⟩ at an interior grid node with unit normal n (3 doubles). */
 double pbo_jacobian(const int* dims, double h, const double* phi, long node, const double* n);
+/* κ1 + κ2 of Γ at the node's projection (from the same Hessian). */
+double pbo_curvature(const int* dims, double h, const double* phi, long node, const double* n);
 double pbo_delta(double eta, double eps);
 
-/* Stage 3 — kernels, operator, right-hand side, GMRES. */
-void pbo_pair(const double* x, const double* nx, const double* y, const double* ny, const double* prm, double* K);
-void pbo_matvec(long n, const double* nodes, const double* prm, const double* p, double* y);
-void pbo_matvec_rows(long n, const double* nodes, const double* prm, const double* p,
+/* Stage 3 — kernels, operator, right-hand side, GMRES. curv: per node κ1 + κ2 at the
+   projection (pbo_curvature), used by the curvature-corrected disc averages; NULL = 0. */
+void pbo_pair(const double* x, const double* nx, const double* y, const double* ny, const double* prm, double curv,
+              double* K);
+void pbo_matvec(long n, const double* nodes, const double* prm, const double* curv, const double* p, double* y);
+void pbo_matvec_rows(long n, const double* nodes, const double* prm, const double* curv, const double* p,
                      const long* rows, long n_rows, double* y1, double* y2);
-void pbo_dense(long n, const double* nodes, const double* prm, double* A);
+void pbo_dense(long n, const double* nodes, const double* prm, const double* curv, double* A);
 void pbo_rhs(long n, const double* nodes, const double* atoms, int n_atoms, const double* prm, double* g);
-int pbo_gmres(long n, const double* nodes, const double* prm, const double* g, double* x,
+int pbo_gmres(long n, const double* nodes, const double* prm, const double* curv, const double* g, double* x,
               double tol, int max_iter, int restart, int* iters, double* relres);
 
 /* Stage 4 — area and polarization energy (paper units, G0 = 1/(4πr)). */

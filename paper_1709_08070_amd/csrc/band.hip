@@ -2,7 +2,8 @@
 // closest-point projection x* = x − φ n, n = ∇φ/|∇φ| (central differences, or the average
 // of the two WENO5 one-sided derivatives per axis) and the weight ω = δ_ε(φ)·J
 // (eq. cosine-kernel; J ≡ 1 or the explicit J of section "Implicit boundary integral
-// methods", read with the adjugate of the Hessian).
+// methods", read with the adjugate of the Hessian), and, when asked for, the curvature sum
+// κ1 + κ2 of the surface at x*.
 //
 // Three passes over the grid, each block owning one contiguous tile of kTile linear
 // indices: count the band nodes of each tile, scan the tile counts, then scatter. Inside a
@@ -66,10 +67,10 @@ __device__ double weno_average(const double* __restrict__ phi, int64_t id, int64
   return (a + b) * 0.5;
 }
 
-// J = 1 − φ tr(H) + φ² nᵀ adj(H) n at an interior node, H the central-difference Hessian
-// (mixed terms from the four diagonal neighbours), adj(H) the adjugate of the symmetric H.
-__device__ double jacobian(const double* __restrict__ phi, int64_t id, int64_t si, int64_t sj, double h, double f,
-                           double nx, double ny, double nz) {
+// tr(H) and nᵀ adj(H) n at an interior node, H the central-difference Hessian of φ (mixed
+// terms from the four diagonal neighbours), adj(H) the adjugate of the symmetric H.
+__device__ void hessian_terms(const double* __restrict__ phi, int64_t id, int64_t si, int64_t sj, double h, double f,
+                              double nx, double ny, double nz, double* tr, double* q) {
   const double ih2 = 1.0 / (h * h), iq = 0.25 * ih2;
   const double hxx = (phi[id + si] - 2.0 * f + phi[id - si]) * ih2;
   const double hyy = (phi[id + sj] - 2.0 * f + phi[id - sj]) * ih2;
@@ -79,8 +80,8 @@ __device__ double jacobian(const double* __restrict__ phi, int64_t id, int64_t s
   const double hyz = (phi[id + sj + 1] - phi[id + sj - 1] - phi[id - sj + 1] + phi[id - sj - 1]) * iq;
   const double axx = hyy * hzz - hyz * hyz, ayy = hxx * hzz - hxz * hxz, azz = hxx * hyy - hxy * hxy;
   const double axy = hxz * hyz - hxy * hzz, axz = hxy * hyz - hxz * hyy, ayz = hxy * hxz - hxx * hyz;
-  const double q = axx * nx * nx + ayy * ny * ny + azz * nz * nz + 2.0 * (axy * nx * ny + axz * nx * nz + ayz * ny * nz);
-  return 1.0 - f * (hxx + hyy + hzz) + f * f * q;
+  *q = axx * nx * nx + ayy * ny * ny + azz * nz * nz + 2.0 * (axy * nx * ny + axz * nx * nz + ayz * ny * nz);
+  *tr = hxx + hyy + hzz;
 }
 
 __global__ void __launch_bounds__(kBlock) k_scatter(GridDev g, const double* __restrict__ phi, double eps,
@@ -138,7 +139,15 @@ __global__ void __launch_bounds__(kBlock) k_scatter(GridDev g, const double* __r
     band.nz[pos] = nz;
     band.phi[pos] = f;
     double w = (1.0 + cos(kPi * f / eps)) / (2.0 * eps);
-    if (full_jacobian) w *= jacobian(phi, id, si, sj, g.h, f, nx, ny, nz);
+    if (full_jacobian || band.curv) {
+      // J = 1 − φ tr(H) + φ² nᵀadj(H)n; the level set through the node has curvature sum tr(H)
+      // and product nᵀadj(H)n, and moving back by φ gives κ1 + κ2 = (tr(H) − 2φ nᵀadj(H)n)/J at x*
+      double tr, q;
+      hessian_terms(phi, id, si, sj, g.h, f, nx, ny, nz, &tr, &q);
+      const double J = 1.0 - f * tr + f * f * q;
+      if (full_jacobian) w *= J;
+      if (band.curv) band.curv[pos] = (tr - 2.0 * f * q) / J;
+    }
     band.w[pos] = w;
     if (band.gidx) band.gidx[pos] = id;
   }

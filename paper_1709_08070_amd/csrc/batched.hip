@@ -1122,6 +1122,8 @@ extern "C" pb_status pb_ibim_solve_batched(pb_ctx* ctx, int n_mol, const pb_band
 
   if (opts.precision != PB_MIXED)
     return ctx->fail(PB_EINVAL, "the batched solve runs the mixed path (precision PB_MIXED)");
+  if (prm->reg_avg != PB_AVG_FLAT)
+    return ctx->fail(PB_EINVAL, "the batched solve takes the paper's disc averages (reg_avg PB_AVG_FLAT)");
   // refinement over the molecules in sel: FP64 residual, inner solve, update
   auto outer_loop = [&](bool with_prec) -> pb_status {
     for (;;) {

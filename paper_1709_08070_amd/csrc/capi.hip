@@ -37,6 +37,16 @@ Derived derive(const pb_params& p) {
   // near-field radius; the margin keeps every pair with r < 2τ inside it after FP32 rounding
   d.rc = std::fmax(p.near_k * p.h, 2.0 * d.tau) * (1.0 + 1e-4);
   d.metric = p.reg_metric;
+  // curvature-corrected disc averages (PB_AVG_CURVED), times 4π as the kernels use them:
+  // 4πK̄11 = k11c·c, 4πK̄22 = k22c·c (c = κ1 + κ2 at the target), 4πK̄21 = k21bar4pi
+  d.curved = p.reg_avg == PB_AVG_CURVED;
+  if (d.curved) {
+    const double kt = p.kappa * d.tau;
+    const double abar = p.kappa == 0.0 ? 1.0 : (2.0 - (2.0 + kt) * std::exp(-kt)) / kt;
+    d.k11c = -(1.0 - d.th1 * abar) / (2.0 * d.tau);
+    d.k22c = -(1.0 - d.th2 * abar) / (2.0 * d.tau);
+    d.k21bar4pi = 2.0 * (std::exp(-kt) - 1.0 + kt) / (d.tau * d.tau * d.tau);
+  }
   return d;
 }
 
@@ -136,6 +146,13 @@ pb_status check_params(pb_ctx* ctx, const pb_params* p) {
   if (!(p->tree_theta > 0.0 && p->tree_theta < 1.0)) return ctx->fail(PB_EINVAL, "tree_theta must be in (0, 1)");
   if (p->tree_degree < 2 || p->tree_degree > kTreeMaxDegree)
     return ctx->fail(PB_EINVAL, "tree_degree must be in [2, %d]", kTreeMaxDegree);
+  if (p->reg_avg < 0 || p->reg_avg > 1) return ctx->fail(PB_EINVAL, "unknown reg_avg %d", p->reg_avg);
+  return PB_OK;
+}
+
+pb_status check_curv(pb_ctx* ctx, const pb_band* b, const pb_params* p) {
+  if (p->reg_avg == PB_AVG_CURVED && !b->curv)
+    return ctx->fail(PB_EINVAL, "reg_avg PB_AVG_CURVED needs band->curv (written by pb_narrowband_compact)");
   return PB_OK;
 }
 
@@ -262,6 +279,7 @@ void pb_default_params(pb_params* p) {
   p->jacobian = PB_JAC_ONE;
   p->tree_theta = 0.6;
   p->tree_degree = 4;
+  p->reg_avg = PB_AVG_FLAT;
   p->ls_mode = PB_LS_SES;
   p->reinit_steps = 0;
 }

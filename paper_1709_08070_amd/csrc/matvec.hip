@@ -178,7 +178,7 @@ int launch_f64(pb_ctx* ctx, int cfg, const pb_band* band, const double* wpsi, co
   int chunk = 0;
   const int S = far_chunks(ctx, n, kBlock, kBlock, &chunk);
   const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
-  k_p2p_f64<<<dim3(nb, S), kBlock, 0, ctx->stream>>>(band_dev(band), wpsi, wpsn, n, chunk, partial, kp);
+  k_p2p_f64<<<dim3(nb, S), kBlock, 0, ctx->stream>>>(band_dev(band, kp.curved), wpsi, wpsn, n, chunk, partial, kp);
   return S;
 }
 
@@ -237,8 +237,8 @@ pb_status matvec_fp64(pb_ctx* ctx, const pb_band* band, const Derived& d, const 
   const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
   k_weights_f64<<<nb, kBlock, 0, ctx->stream>>>(n, band->w, p, d.h3 / (4.0 * kPi), wpsi, wpsn);
   const KParams kp = kparams(d);
-  int cfg = 0;
-  PB_TRY(f64_autotune(ctx, band, wpsi, wpsn, kp, partial, &cfg));
+  int cfg = 0;  // the symmetric kernel takes the paper's disc averages only
+  if (!d.curved) PB_TRY(f64_autotune(ctx, band, wpsi, wpsn, kp, partial, &cfg));
   int S = 0;
   {
     Scope t(ctx, "p2p_f64");
@@ -341,7 +341,7 @@ pb_status near_build(pb_ctx* ctx, const pb_band* band, const Derived& d, const c
   int* col = (int*)workspace(ctx, name("near_col"), sizeof(int) * (size_t)std::max<int64_t>(nnz, 1));
   double4* coef = (double4*)workspace(ctx, name("near_coef"), sizeof(double4) * (size_t)std::max<int64_t>(nnz, 1));
   if (!col || !coef) return PB_ENOMEM;
-  k_near_fill<<<nb, kBlock, 0, ctx->stream>>>(n, band_dev(band), band->w, d.h3 / (4.0 * kPi), A, cells, P.rc2f,
+  k_near_fill<<<nb, kBlock, 0, ctx->stream>>>(n, band_dev(band, d.curved), band->w, d.h3 / (4.0 * kPi), A, cells, P.rc2f,
                                               kparams(d), row, col, coef);
   PB_TRY(launch_ok(ctx, "near fill"));
   P.A = A;
@@ -408,6 +408,7 @@ extern "C" pb_status pb_ibim_matvec(pb_ctx* ctx, const pb_band* band, const pb_p
     return ctx->fail(PB_EINVAL, "unknown precision %d", precision);
   if (precision != PB_FP64 && prm->reg_metric == PB_REG_TANGENT)
     return ctx->fail(PB_EINVAL, "the mixed path needs a bounded regularization radius (guarded or Euclidean metric)");
+  PB_TRY(check_curv(ctx, band, prm));
   PB_HIP(ctx, hipSetDevice(ctx->device));
   Derived d = derive(*prm);
   if (precision == PB_FP64) {

@@ -17,11 +17,15 @@ namespace pb {
 
 struct KParams {
   double th1, th2, kappa, tau2, four_tau2, k12bar4pi;
+  double k11c, k22c, k21bar4pi;  // regularized pairs: 4πK11 = k11c·c_i, 4πK22 = k22c·c_i, 4πK21 = k21bar4pi
   int metric;
+  int curved;                     // curvature-corrected disc averages (the kernels then read b.curv)
 };
 
 inline KParams kparams(const Derived& d) {
-  return KParams{d.th1, d.th2, d.kappa, d.tau2, d.four_tau2, 4.0 * kPi * d.k12bar, d.metric};
+  return KParams{d.th1, d.th2, d.kappa, d.tau2, d.four_tau2, 4.0 * kPi * d.k12bar,
+                 d.curved ? d.k11c : 0.0, d.curved ? d.k22c : 0.0, d.curved ? d.k21bar4pi : 0.0, d.metric,
+                 d.curved ? 1 : 0};
 }
 
 // ---------------------------------------------------------------- FP64
@@ -30,7 +34,7 @@ inline KParams kparams(const Derived& d) {
 // products and sums exactly as written (no contraction).
 __device__ __forceinline__ void kern4_f64(double xi, double yi, double zi, double nxi, double nyi, double nzi,
                                           double xj, double yj, double zj, double nxj, double nyj, double nzj,
-                                          const KParams& kp, double k[4]) {
+                                          const KParams& kp, double ci, double k[4]) {
   double dx = xi - xj, dy = yi - yj, dz = zi - zj;
   double r2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
   double dnx = __dadd_rn(__dadd_rn(__dmul_rn(dx, nxi), __dmul_rn(dy, nyi)), __dmul_rn(dz, nzi));
@@ -39,11 +43,11 @@ __device__ __forceinline__ void kern4_f64(double xi, double yi, double zi, doubl
   if (kp.metric == PB_REG_EUCLIDEAN) reg = r2 < kp.tau2;
   else if (kp.metric == PB_REG_TANGENT) reg = t2 < kp.tau2;
   else reg = t2 < kp.tau2 && r2 < kp.four_tau2;
-  if (reg) {
-    k[0] = 0.0;
+  if (reg) {  // disc averages; ci = κ1 + κ2 at the target (0 with the paper's averages)
+    k[0] = kp.k11c * ci;
     k[1] = kp.k12bar4pi;
-    k[2] = 0.0;
-    k[3] = 0.0;
+    k[2] = kp.k21bar4pi;
+    k[3] = kp.k22c * ci;
     return;
   }
   double dny = dx * nxj + dy * nyj + dz * nzj;
@@ -70,9 +74,10 @@ __device__ __forceinline__ void kern4_f64(double xi, double yi, double zi, doubl
 // s1 += 4πK11·wψ − 4πK12·wψn, s2 += 4πK21·wψ − 4πK22·wψn.
 __device__ __forceinline__ void pair_f64(double xi, double yi, double zi, double nxi, double nyi, double nzi,
                                          double xj, double yj, double zj, double nxj, double nyj, double nzj,
-                                         double wpsi, double wpsn, const KParams& kp, double& s1, double& s2) {
+                                         double wpsi, double wpsn, const KParams& kp, double ci, double& s1,
+                                         double& s2) {
   double k[4];
-  kern4_f64(xi, yi, zi, nxi, nyi, nzi, xj, yj, zj, nxj, nyj, nzj, kp, k);
+  kern4_f64(xi, yi, zi, nxi, nyi, nzi, xj, yj, zj, nxj, nyj, nzj, kp, ci, k);
   s1 += k[0] * wpsi - k[1] * wpsn;
   s2 += k[2] * wpsi - k[3] * wpsn;
 }
@@ -250,9 +255,13 @@ constexpr int kBlock = 256;
 
 struct BandDev {
   const double *px, *py, *pz, *nx, *ny, *nz;
+  const double* curv;  // κ1 + κ2 at the projections, or null (flat disc averages)
 };
 
-inline BandDev band_dev(const pb_band* b) { return BandDev{b->px, b->py, b->pz, b->nx, b->ny, b->nz}; }
+// The band's geometry; the curvature only where the curvature-corrected averages use it.
+inline BandDev band_dev(const pb_band* b, bool with_curv = false) {
+  return BandDev{b->px, b->py, b->pz, b->nx, b->ny, b->nz, with_curv ? b->curv : nullptr};
+}
 
 // Source weights h³ω_j ψ_j/(4π), h³ω_j ψn_j/(4π) in FP64.
 static __global__ void __attribute__((unused)) __launch_bounds__(kBlock) k_weights_f64(int n, const double* __restrict__ w,
@@ -277,10 +286,11 @@ __device__ __forceinline__ void far64_tile_loop(const BandDev& b, const double* 
          *sw1 = snz + kBlk, *sw2 = sw1 + kBlk;
   const int i = t0 + (int)threadIdx.x;
   const bool live = i < t_end;
-  double xi = 0, yi = 0, zi = 0, nxi = 0, nyi = 0, nzi = 1;
+  double xi = 0, yi = 0, zi = 0, nxi = 0, nyi = 0, nzi = 1, ci = 0;
   if (live) {
     xi = b.px[i]; yi = b.py[i]; zi = b.pz[i];
     nxi = b.nx[i]; nyi = b.ny[i]; nzi = b.nz[i];
+    ci = b.curv ? b.curv[i] : 0.0;
   }
   double s1 = 0.0, s2 = 0.0;
   for (int base = j0; base < j1; base += kBlk) {
@@ -294,7 +304,8 @@ __device__ __forceinline__ void far64_tile_loop(const BandDev& b, const double* 
     const int m = min(kBlk, j1 - base);
     if (live)
       for (int q = 0; q < m; ++q)
-        pair_f64(xi, yi, zi, nxi, nyi, nzi, sx[q], sy[q], sz[q], snx[q], sny[q], snz[q], sw1[q], sw2[q], kp, s1, s2);
+        pair_f64(xi, yi, zi, nxi, nyi, nzi, sx[q], sy[q], sz[q], snx[q], sny[q], snz[q], sw1[q], sw2[q], kp, ci, s1,
+                 s2);
     __syncthreads();
   }
   if (live) {
@@ -497,10 +508,11 @@ static __global__ void __attribute__((unused)) __launch_bounds__(kBlock) k_near_
   int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const double xi = b.px[i], yi = b.py[i], zi = b.pz[i], nxi = b.nx[i], nyi = b.ny[i], nzi = b.nz[i];
+  const double ci = b.curv ? b.curv[i] : 0.0;
   int64_t q = row[i];
   for_near(i, A, cells, rc2, [&](int j) {
     double k[4];
-    kern4_f64(xi, yi, zi, nxi, nyi, nzi, b.px[j], b.py[j], b.pz[j], b.nx[j], b.ny[j], b.nz[j], kp, k);
+    kern4_f64(xi, yi, zi, nxi, nyi, nzi, b.px[j], b.py[j], b.pz[j], b.nx[j], b.ny[j], b.nz[j], kp, ci, k);
     const double sj = scale * w[j];
     col[q] = j;
     coef[q] = make_double4(k[0] * sj, -k[1] * sj, k[2] * sj, -k[3] * sj);

@@ -31,6 +31,8 @@ struct Derived {
   double k12bar;          // disc average of G0 − Gκ over radius τ
   double rc;              // mixed path: near-field radius
   int metric;
+  bool curved;            // curvature-corrected disc averages
+  double k11c, k22c, k21bar4pi;
 };
 
 Derived derive(const pb_params& p);
@@ -143,6 +145,8 @@ void flush_timers(pb_ctx* ctx);  // after a stream synchronize
 
 pb_status check_params(pb_ctx* ctx, const pb_params* p);
 pb_status check_band(pb_ctx* ctx, const pb_band* b);
+// PB_AVG_CURVED needs the band's curvature array.
+pb_status check_curv(pb_ctx* ctx, const pb_band* b, const pb_params* p);
 pb_status sync(pb_ctx* ctx, const char* where);
 pb_status launch_ok(pb_ctx* ctx, const char* where);
 

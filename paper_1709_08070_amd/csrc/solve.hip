@@ -246,6 +246,7 @@ extern "C" pb_status pb_ibim_solve(pb_ctx* ctx, const pb_band* band, const doubl
   if (!ctx) return PB_EINVAL;
   PB_TRY(check_params(ctx, prm));
   PB_TRY(check_band(ctx, band));
+  PB_TRY(check_curv(ctx, band, prm));
   pb_solve_opts opts;
   if (opts_in) opts = *opts_in;
   else pb_default_solve_opts(&opts);

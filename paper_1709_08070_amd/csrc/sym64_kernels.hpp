@@ -196,7 +196,7 @@ __device__ __forceinline__ void diag64_block(const BandDev& b, const double* __r
       double s1 = 0.0, s2 = 0.0;
       for (int q = 0; q < m; ++q) {
         const double2 c0 = sh.s0[q], c1 = sh.s1[q], c2 = sh.s2[q], c3 = sh.s3[q];
-        pair_f64(xi, yi, zi, nxi, nyi, nzi, c0.x, c0.y, c1.x, c1.y, c2.x, c2.y, c3.x, c3.y, kp, s1, s2);
+        pair_f64(xi, yi, zi, nxi, nyi, nzi, c0.x, c0.y, c1.x, c1.y, c2.x, c2.y, c3.x, c3.y, kp, 0.0, s1, s2);
       }
       fwd1[i - t0] = s1 + (acc ? fwd1[i - t0] : 0.0);
       fwd2[i - t0] = s2 + (acc ? fwd2[i - t0] : 0.0);

@@ -24,6 +24,7 @@ PB_X0_ZERO, PB_X0_DIAG, PB_X0_USER, PB_X0_LEARNED = 0, 1, 2, 3
 PB_PRECOND_NONE, PB_PRECOND_LEARNED = 0, 1
 PB_GRAD_CENTRAL, PB_GRAD_WENO = 0, 1
 PB_JAC_ONE, PB_JAC_FULL = 0, 1
+PB_AVG_FLAT, PB_AVG_CURVED = 0, 1
 KCAL_PER_UNIT = 4.0 * np.pi * 332.0637
 
 EXPORTS = [
@@ -39,7 +40,7 @@ class pb_params(C.Structure):
     _fields_ = [("eps_in", C.c_double), ("eps_out", C.c_double), ("kappa", C.c_double), ("probe", C.c_double),
                 ("h", C.c_double), ("band_k", C.c_double), ("tau_k", C.c_double), ("cfl", C.c_double),
                 ("near_k", C.c_double), ("tree_theta", C.c_double), ("reg_metric", C.c_int), ("ls_mode", C.c_int), ("reinit_steps", C.c_int),
-                ("grad_scheme", C.c_int), ("jacobian", C.c_int), ("tree_degree", C.c_int), ("reserved", C.c_int)]
+                ("grad_scheme", C.c_int), ("jacobian", C.c_int), ("tree_degree", C.c_int), ("reg_avg", C.c_int)]
 
 
 class pb_grid(C.Structure):
@@ -48,7 +49,7 @@ class pb_grid(C.Structure):
 
 class pb_band(C.Structure):
     _fields_ = [("n", C.c_int64), ("capacity", C.c_int64)] + \
-               [(f, C.c_void_p) for f in ("px", "py", "pz", "nx", "ny", "nz", "phi", "w", "gidx")]
+               [(f, C.c_void_p) for f in ("px", "py", "pz", "nx", "ny", "nz", "phi", "w", "gidx", "curv")]
 
 
 class pb_solve_opts(C.Structure):
@@ -209,6 +210,7 @@ class Band:
     phi: torch.Tensor
     w: torch.Tensor
     gidx: torch.Tensor
+    curv: torch.Tensor | None = None  # κ1 + κ2 at x* (written by the compaction)
 
     def struct(self) -> pb_band:
         b = pb_band()
@@ -216,6 +218,7 @@ class Band:
         b.capacity = self.px.numel()
         for f in ("px", "py", "pz", "nx", "ny", "nz", "phi", "w", "gidx"):
             setattr(b, f, getattr(self, f).data_ptr())
+        b.curv = self.curv.data_ptr() if self.curv is not None else None
         return b
 
     def table(self) -> np.ndarray:
@@ -226,7 +229,7 @@ class Band:
     @staticmethod
     def alloc(capacity: int, device) -> "Band":
         z = lambda dt=torch.float64: torch.zeros(max(capacity, 1), dtype=dt, device=device)
-        return Band(0, z(), z(), z(), z(), z(), z(), z(), z(), z(torch.int64))
+        return Band(0, z(), z(), z(), z(), z(), z(), z(), z(), z(torch.int64), z())
 
 
 def pb_grid_for_atoms(atoms: np.ndarray, prm: pb_params) -> pb_grid:

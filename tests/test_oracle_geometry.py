@@ -168,3 +168,26 @@ def test_weno_average_gradient_normals():
     node = np.ravel_multi_index((6, 5, 7), dims)
     m, p = oracle.weno_grad(dims, h, phi, node)
     np.testing.assert_allclose((m + p) / 2, a + B @ X[node], rtol=0, atol=1e-12)
+
+
+def test_surface_curvature_sphere_and_cylinder():
+    """κ1 + κ2 at the projection: 2/R on a sphere (at every band node, both sides of the
+    surface), 1/R on a cylinder; second order in h."""
+    R, c = 2.0, np.array([0.0123, 0.0456, 0.0789])
+    errs = []
+    for h in (0.25, 0.125):
+        dims, origin, phi, nodes, gidx, prm = oracle.pipeline(synth.born_ion(R, 1.0, tuple(c)), h, ses=False)
+        curv = oracle.curvature(dims, h, phi, gidx, nodes)
+        errs.append(np.max(np.abs(curv - 2.0 / R)))
+    assert errs[1] < 2e-3 and errs[0] / errs[1] > 3.5
+    h, dims = 0.125, (48, 48, 12)
+    i, j, k = np.meshgrid(*[np.arange(d) for d in dims], indexing="ij")
+    x, y = i * h - 3.0 + c[0], j * h - 3.0 + c[1]
+    rho = np.sqrt(x * x + y * y)
+    phi = (rho - R).reshape(-1)
+    sel = np.nonzero((np.abs(phi) < 2 * h) & (k.reshape(-1) == 6))[0]
+    nrm = [np.array([x.reshape(-1)[q], y.reshape(-1)[q], 0.0]) / rho.reshape(-1)[q] for q in sel]
+    nodes = np.zeros((len(sel), 8))
+    nodes[:, 3:6] = nrm
+    curv = oracle.curvature(dims, h, phi, sel, nodes)
+    assert np.max(np.abs(curv - 1.0 / R)) < 1e-3

@@ -121,3 +121,48 @@ def test_regularization_predicate_metrics():
     assert oracle.pair(x, n, [0.3, 0, 0.3], n, euc)[1] == kbar      # r = 0.42 < τ
     assert oracle.pair(x, n, [0.45, 0, 0.25], n, euc)[1] != kbar    # r = 0.515 > τ
     assert oracle.pair(x, n, [0.45, 0, 0.25], n, prm)[1] == kbar    # tangent 0.45 < τ, r < 2τ
+
+
+# ---------------------------------------------- curvature-corrected disc averages
+# A regularized pair stands for the disc of radius τ around x*; its value times the disc's
+# area should be the integral of the kernel over that part of the surface. Fixed here by
+# quadrature of the oracle's own (pinned) kernels: over the spherical cap whose tangent-plane
+# projection at the pole lies within τ (K11, K22: error O(τ²/R²), falling 4× per halving), and
+# over the flat disc (K21: exact).
+
+def _cap_integral(k, R, tau, prm):
+    x, nx = np.array([0.0, 0.0, R]), np.array([0.0, 0.0, 1.0])
+    th_max = math.asin(tau / R)
+
+    def f(th):
+        u = np.array([math.sin(th), 0.0, math.cos(th)])
+        return oracle.pair(x, nx, R * u, u, prm)[k] * 2 * math.pi * R * R * math.sin(th)
+
+    val, _ = integrate.quad(f, 0.0, th_max, limit=200, epsabs=0.0, epsrel=1e-9)
+    return val, 2 * math.pi * R * R * (1 - math.cos(th_max))
+
+
+@pytest.mark.parametrize("k", [0, 3], ids=["K11", "K22"])
+def test_curved_disc_averages_of_the_double_layers(k):
+    R = 2.0
+    unreg = oracle.params(1.0, tau_k=1e-9)
+    errs = []
+    for tau in (0.5, 0.25, 0.125):
+        integral, area = _cap_integral(k, R, tau, unreg)
+        curved = oracle.params(1.0, tau_k=tau, avg=oracle.AVG_CURVED)
+        kbar = oracle.pair([0, 0, R], [0, 0, 1], [0, 0, R], [0, 0, 1], curved, curv_x=2.0 / R)[k]
+        errs.append(abs(kbar * area - integral) / abs(integral))
+        # the paper's average is zero: it drops the whole integral
+        assert oracle.pair([0, 0, R], [0, 0, 1], [0, 0, R], [0, 0, 1], oracle.params(1.0, tau_k=tau), 2.0 / R)[k] == 0
+    assert errs[0] < 0.02 and errs[1] < errs[0] / 3.5 and errs[2] < errs[1] / 3.5
+
+
+@pytest.mark.parametrize("kappa", [KAPPA, 0.7, 0.0])
+def test_flat_disc_average_of_k21(kappa):
+    z, ez = [0.0, 0.0, 0.0], [0.0, 0.0, 1.0]
+    unreg = oracle.params(1.0, kappa=kappa, tau_k=1e-9)
+    for tau in (0.5, 0.25):
+        integral, _ = integrate.quad(lambda r: oracle.pair(z, ez, [r, 0, 0], ez, unreg)[2] * 2 * math.pi * r,
+                                     0.0, tau, epsabs=1e-15, epsrel=1e-12, limit=200)
+        kbar = oracle.pair(z, ez, z, ez, oracle.params(1.0, kappa=kappa, tau_k=tau, avg=oracle.AVG_CURVED))[2]
+        assert kbar * math.pi * tau * tau == pytest.approx(integral, rel=1e-8, abs=1e-15)
