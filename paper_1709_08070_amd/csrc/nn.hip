@@ -217,13 +217,22 @@ __global__ void __launch_bounds__(kBlock) k_build_g1(int n, BandDev b, const int
 
 // Z = A·W + b for 16-node wave tiles; A rows are G1 (dense, BF16, K = 256) or the gathered
 // FP32 activations of the 16 neighbour slots (converted to BF16 per load). kAct applies the
-// leaky ReLU. Block = 4 waves = 64 nodes.
+// leaky ReLU. Block = 4 waves = 64 nodes. The BF16 weights are staged in LDS in chunks of
+// kWChunk columns and shared by the block's four waves (each wave would otherwise stream the
+// whole matrix from the caches); rows are padded by 8 elements so that the 16 rows a wave
+// reads at one column offset fall on different banks.
+constexpr int kWChunk = 256;
+constexpr int kWPad = 8;
+
 template <bool kDense, int CIN, int COUT, bool kAct>
 __global__ void __launch_bounds__(256) k_layer_fwd(int n, const uint16_t* __restrict__ G1, const float* __restrict__ X,
                                                    const int* __restrict__ nbr, const uint16_t* __restrict__ Wt,
                                                    const float* __restrict__ bias, float* __restrict__ Y) {
   constexpr int K = kSlots * CIN;
   constexpr int NT = COUT / 16;
+  constexpr int KC = K < kWChunk ? K : kWChunk;
+  static_assert(K % KC == 0 && KC % 32 == 0, "whole chunks of 32-column steps");
+  __shared__ uint16_t sW[COUT][KC + kWPad];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int node0 = (blockIdx.x * 4 + wave) * 16;
   const int node = node0 + (lane & 15);
@@ -232,29 +241,39 @@ __global__ void __launch_bounds__(256) k_layer_fwd(int n, const uint16_t* __rest
   f32x4_t acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-  for (int kb = 0; kb < K; kb += 32) {
-    const int kk = kb + kq;
-    bf16x8_t a;
-    if (kDense) {
-      if (live) a = load8_bf16(G1 + (int64_t)node * K + kk);
-      else {
-        const float zero[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        a = pack8(zero);
-      }
-    } else {
-      float vals[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      if (live) {
-        const int slot = kk / CIN, c = kk % CIN;
-        const float* src = X + (int64_t)nbr[(int64_t)node * kSlots + slot] * CIN + c;
-#pragma unroll
-        for (int r = 0; r < 8; ++r) vals[r] = src[r];
-      }
-      a = pack8(vals);
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    __syncthreads();  // the previous chunk is no longer read
+    for (int e = threadIdx.x; e < COUT * KC / 8; e += 256) {
+      const int row = e / (KC / 8), col = (e % (KC / 8)) * 8;
+      *reinterpret_cast<short8_t*>(&sW[row][col]) =
+          *reinterpret_cast<const short8_t*>(Wt + (int64_t)row * K + k0 + col);
     }
+    __syncthreads();
+    for (int kb = 0; kb < KC; kb += 32) {
+      const int kk = k0 + kb + kq;
+      bf16x8_t a;
+      if (kDense) {
+        if (live) a = load8_bf16(G1 + (int64_t)node * K + kk);
+        else {
+          const float zero[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+          a = pack8(zero);
+        }
+      } else {
+        float vals[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (live) {
+          const int slot = kk / CIN, c = kk % CIN;
+          const float* src = X + (int64_t)nbr[(int64_t)node * kSlots + slot] * CIN + c;
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const bf16x8_t bw = load8_bf16(Wt + (int64_t)(t * 16 + (lane & 15)) * K + kk);
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw, acc[t], 0, 0, 0);
+          for (int r = 0; r < 8; ++r) vals[r] = src[r];
+        }
+        a = pack8(vals);
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const bf16x8_t bw = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const short8_t*>(
+                                                             &sW[t * 16 + (lane & 15)][kb + kq]));
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw, acc[t], 0, 0, 0);
+      }
     }
   }
 #pragma unroll
