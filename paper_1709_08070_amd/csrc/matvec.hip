@@ -417,8 +417,8 @@ extern "C" pb_status pb_ibim_matvec(pb_ctx* ctx, const pb_band* band, const pb_p
     PB_TRY(mixed_prepare(ctx, band, d));
     PB_TRY(matvec_mixed(ctx, band, d, p, y));
   } else {
-    PB_TRY(tree_prepare(ctx, band, d, prm->tree_degree, prm->tree_theta));
-    PB_TRY(matvec_tree(ctx, band, d, p, y));
+    PB_TRY(tree_prepare(ctx, band, d, prm->tree_degree, prm->tree_theta, ctx->tree, "tc_"));
+    PB_TRY(matvec_tree(ctx, band, d, p, y, ctx->tree));
   }
   return sync(ctx, "pb_ibim_matvec");
 }

@@ -174,17 +174,31 @@ __global__ void __launch_bounds__(kBlock) k_rms_partial(int n, const double* __r
   }
 }
 
-__global__ void k_rms_finish(int n, int nb, const double* __restrict__ part, double* __restrict__ s) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// One block: strided partial sums per thread, then a fixed tree over the block.
+__global__ void __launch_bounds__(kBlock) k_rms_finish(int n, int nb, const double* __restrict__ part,
+                                                       double* __restrict__ s) {
+  __shared__ double r1[kBlock], r2[kBlock];
   double a = 0.0, c = 0.0;
-  for (int q = 0; q < nb; ++q) {
+  for (int q = threadIdx.x; q < nb; q += kBlock) {
     a += part[2 * q];
     c += part[2 * q + 1];
   }
-  a = sqrt(a / n);
-  c = sqrt(c / n);
-  s[0] = a > 0.0 ? a : 1.0;
-  s[1] = c > 0.0 ? c : 1.0;
+  r1[threadIdx.x] = a;
+  r2[threadIdx.x] = c;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      r1[threadIdx.x] += r1[threadIdx.x + off];
+      r2[threadIdx.x] += r2[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    a = sqrt(r1[0] / n);
+    c = sqrt(r2[0] / n);
+    s[0] = a > 0.0 ? a : 1.0;
+    s[1] = c > 0.0 ? c : 1.0;
+  }
 }
 
 // Layer-1 input rows G1[i] = 16 slots × 16 features (BF16).
@@ -657,7 +671,7 @@ pb_status nn_apply(pb_ctx* ctx, const pb_nn* net, const pb_band* band, const Der
   const unsigned nbl = (unsigned)((n + 63) / 64);
   Scope t(ctx, "nn");
   k_rms_partial<<<kRedBlocks, kBlock, 0, ctx->stream>>>(n, v, B.spart);
-  k_rms_finish<<<1, 1, 0, ctx->stream>>>(n, kRedBlocks, B.spart, B.s);
+  k_rms_finish<<<1, kBlock, 0, ctx->stream>>>(n, kRedBlocks, B.spart, B.s);
   k_build_g1<<<(unsigned)(((int64_t)n * kSlots + kBlock - 1) / kBlock), kBlock, 0, ctx->stream>>>(
       n, band_dev(band), B.nbr, B.feat, v, B.s, d.eps, B.G1);
   const uint16_t* wt = net->wt;

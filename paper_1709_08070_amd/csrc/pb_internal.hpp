@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -114,7 +115,8 @@ struct pb_ctx {
   std::vector<hipEvent_t> event_pool;
   int n_cu = 256;
   pb::MixedPlan mixed;
-  pb::TreePlan tree;
+  pb::TreePlan tree;       // PB_TREE operator (and the inner operator of PB_TREE solves)
+  pb::TreePlan tree_fine;  // residual operator of PB_TREE solves on large bands
   std::map<int, int> far_cfg;          // autotuned far-field tile shape per band size
   std::map<int, int> f64_cfg;          // FP64 operator kernel per band size (0 tiled, 1 symmetric)
   int sym_items_n = -1;                // band size the symmetric kernel's item list was built for
@@ -187,9 +189,21 @@ pb_status nn_batch_prepare(pb_ctx* ctx, int n_mol, const pb_band* bands, const i
 void nn_batch_apply(hipStream_t stream, const pb_nn* net, const NNBatch& nb, const double* V, double* Z, int64_t ldv,
                     const int* kptr, int kmax, double lam1, double lam2);
 pb_status matvec_mixed(pb_ctx* ctx, const pb_band* band, const Derived& d, const double* p, double* y);
-// Treecode far field (tree.hip): degree of the Chebyshev proxies and the acceptance ratio θ.
-pb_status tree_prepare(pb_ctx* ctx, const pb_band* band, const Derived& d, int degree, double theta);
-pb_status matvec_tree(pb_ctx* ctx, const pb_band* band, const Derived& d, const double* p, double* y);
+// Treecode far field (tree.hip): degree of the Chebyshev proxies and the acceptance ratio θ;
+// buffers named `<pfx>...`; near: an existing near field of the same band to share (else built).
+// host: in/out, the Morton order, octree and batches of the band, built by the first plan of a
+// solve and reused by the second (null: built and dropped).
+struct TreeHost;
+pb_status tree_prepare(pb_ctx* ctx, const pb_band* band, const Derived& d, int degree, double theta, TreePlan& T,
+                       const char* pfx, const MixedPlan* near = nullptr, std::shared_ptr<TreeHost>* host = nullptr);
+pb_status matvec_tree(pb_ctx* ctx, const pb_band* band, const Derived& d, const double* p, double* y,
+                      const TreePlan& T);
+// PB_TREE solves: the refinement's residuals on bands of at least kTreeFineMin nodes come from a
+// finer treecode (degree 7, θ = 0.5: at the FP32 rounding level of the dense mixed operator,
+// and about 5× cheaper than it at 6e5 nodes), below that from the dense mixed operator.
+constexpr int kTreeFineDegree = 7;
+constexpr double kTreeFineTheta = 0.5;
+constexpr int64_t kTreeFineMin = 150000;
 pb_status rhs(pb_ctx* ctx, const pb_band* band, const double* atoms, int n_atoms, const Derived& d, double* g);
 
 }  // namespace pb

@@ -297,8 +297,15 @@ extern "C" pb_status pb_ibim_solve(pb_ctx* ctx, const pb_band* band, const doubl
   else if (opts.x0 == PB_X0_LEARNED) PB_TRY(nn_apply(ctx, net, band, d, g, p));
   PB_TRY(launch_ok(ctx, "x0"));
 
-  if (opts.precision != PB_FP64) PB_TRY(mixed_prepare(ctx, band, d));
-  if (opts.precision == PB_TREE) PB_TRY(tree_prepare(ctx, band, d, prm->tree_degree, prm->tree_theta));
+  const bool fine_tree = opts.precision == PB_TREE && n >= kTreeFineMin;
+  if (opts.precision == PB_MIXED || (opts.precision == PB_TREE && !fine_tree)) PB_TRY(mixed_prepare(ctx, band, d));
+  if (opts.precision == PB_TREE) {
+    std::shared_ptr<TreeHost> host;  // one octree for both plans
+    PB_TRY(tree_prepare(ctx, band, d, prm->tree_degree, prm->tree_theta, ctx->tree, "tc_", nullptr, &host));
+    if (fine_tree)
+      PB_TRY(tree_prepare(ctx, band, d, kTreeFineDegree, kTreeFineTheta, ctx->tree_fine, "tf_", &ctx->tree.near,
+                          &host));
+  }
   int n64 = 0, nmx = 0, nmid = 0, nnn = 0;
   OpFn op64 = [&](const double* in, double* out) {
     ++n64;
@@ -306,14 +313,16 @@ extern "C" pb_status pb_ibim_solve(pb_ctx* ctx, const pb_band* band, const doubl
   };
   OpFn opmx = [&](const double* in, double* out) {
     ++nmx;
-    return opts.precision == PB_TREE ? matvec_tree(ctx, band, d, in, out) : matvec_mixed(ctx, band, d, in, out);
+    return opts.precision == PB_TREE ? matvec_tree(ctx, band, d, in, out, ctx->tree)
+                                     : matvec_mixed(ctx, band, d, in, out);
   };
-  // PB_TREE: the refinement's residuals come from the dense mixed operator (its distance to
-  // the FP64 operator, about 1e-7 relative, is far below the treecode's) until they meet half
-  // the tolerance; the FP64 operator then certifies the result once
+  // PB_TREE: the refinement's residuals come from an operator about 1e-7 from the FP64 one,
+  // far below the inner treecode's ~1e-5 (the dense mixed operator, or on large bands the
+  // fine treecode at the same FP32 rounding level), until they meet half the tolerance; the
+  // FP64 operator then certifies the result once
   OpFn opmid = [&](const double* in, double* out) {
     ++nmid;
-    return matvec_mixed(ctx, band, d, in, out);
+    return fine_tree ? matvec_tree(ctx, band, d, in, out, ctx->tree_fine) : matvec_mixed(ctx, band, d, in, out);
   };
   OpFn opnn = [&](const double* in, double* out) {
     ++nnn;
@@ -391,7 +400,10 @@ extern "C" pb_status pb_ibim_solve(pb_ctx* ctx, const pb_band* band, const doubl
     const double per_mx = opts.precision == PB_TREE
                               ? (double)(ctx->tree.n_dir_pairs + ctx->tree.n_app_pairs + ctx->tree.near.nnz)
                               : (double)n * (double)n;
-    stats->pairs = (double)(n64 + nmid) * (double)n * (double)n + (double)nmx * per_mx;
+    const double per_mid = fine_tree ? (double)(ctx->tree_fine.n_dir_pairs + ctx->tree_fine.n_app_pairs +
+                                                ctx->tree_fine.near.nnz)
+                                     : (double)n * (double)n;
+    stats->pairs = (double)n64 * (double)n * (double)n + (double)nmid * per_mid + (double)nmx * per_mx;
     stats->t_matvec_s = (matvec_ms() - tm0) * 1e-3;
     stats->t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }

@@ -27,9 +27,12 @@
 // packs the records, computes the proxy weights and runs one fused far-field kernel. Fixed
 // orders throughout: the operator is bitwise reproducible.
 #include <algorithm>
+#include <memory>
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <string>
+#include <thread>
 #include <vector>
 
 #include "pair_kernels.hpp"
@@ -267,7 +270,6 @@ struct HNode {
   int first_kid, n_kids;
   double lo[3], hi[3];
   double c[3], r;     // centre and radius of the tight box
-  int cl;             // proxy cluster id or −1
 };
 
 uint64_t spread3(uint64_t v) {  // 21 bits → every third bit
@@ -300,12 +302,21 @@ void tight_box(const std::vector<double>& s, int b, int e, double lo[3], double 
 
 }  // namespace
 
-pb_status tree_prepare(pb_ctx* ctx, const pb_band* band, const Derived& d, int degree, double theta) {
-  TreePlan& T = ctx->tree;
+// Morton order, octree and target batches of one band (host). Shared by the plans that one
+// solve builds for the same band (they differ in degree and θ only).
+struct TreeHost {
+  int n = 0;
+  std::vector<int> perm;
+  std::vector<double> s;  // scaled coordinates in tree order
+  std::vector<HNode> nodes;
+  std::vector<int2> batch;
+};
+
+namespace {
+
+pb_status build_host_tree(pb_ctx* ctx, const pb_band* band, const MixedPlan& P, TreeHost& H) {
   const int n = (int)band->n;
-  PB_TRY(near_build(ctx, band, d, "tn_", T.near));
-  const MixedPlan& P = T.near;
-  const int P1 = degree + 1, P3 = P1 * P1 * P1;
+  H.n = n;
   // scaled coordinates on the host, exactly as the FP32 records hold them (rounded to FP32)
   std::vector<double> px(n), py(n), pz(n);
   PB_HIP(ctx, hipMemcpyAsync(px.data(), band->px, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream));
@@ -334,22 +345,27 @@ pb_status tree_prepare(pb_ctx* ctx, const pb_band* band, const Derived& d, int d
     }
     code[j] = m;
   }
-  std::vector<int> perm(n);
-  std::iota(perm.begin(), perm.end(), 0);
-  std::sort(perm.begin(), perm.end(), [&](int x, int y) { return code[x] != code[y] ? code[x] < code[y] : x < y; });
-  std::vector<double> s(3 * (size_t)n);
+  std::vector<std::pair<uint64_t, int>> keyed(n);
+  for (int j = 0; j < n; ++j) keyed[j] = {code[j], j};
+  std::sort(keyed.begin(), keyed.end());  // by code, ties by index
+  std::vector<int>& perm = H.perm;
+  perm.resize(n);
+  for (int t = 0; t < n; ++t) perm[t] = keyed[t].second;
+  std::vector<double>& s = H.s;
+  s.resize(3 * (size_t)n);
   std::vector<uint64_t> cs(n);
   for (int t = 0; t < n; ++t) {
     for (int a = 0; a < 3; ++a) s[3 * (size_t)t + a] = s0[3 * (size_t)perm[t] + a];
     cs[t] = code[perm[t]];
   }
   // octree over the sorted codes: children in octant order, leaves of at most kLeaf nodes
-  std::vector<HNode> nodes;
+  std::vector<HNode>& nodes = H.nodes;
+  nodes.clear();
   nodes.reserve(4 * (size_t)n / kLeaf + 64);
   struct Todo {
     int idx, level;
   };
-  nodes.push_back(HNode{0, n, -1, 0, {}, {}, {}, 0.0, -1});
+  nodes.push_back(HNode{0, n, -1, 0, {}, {}, {}, 0.0});
   std::vector<Todo> todo{{0, 0}};
   while (!todo.empty()) {
     Todo td = todo.back();
@@ -365,7 +381,7 @@ pb_status tree_prepare(pb_ctx* ctx, const pb_band* band, const Derived& d, int d
       int u = t;
       while (u < e && (int)((cs[u] >> shift) & 7) == o) ++u;
       if (u > t) {
-        nodes.push_back(HNode{t, u, -1, 0, {}, {}, {}, 0.0, -1});
+        nodes.push_back(HNode{t, u, -1, 0, {}, {}, {}, 0.0});
         ++nk;
       }
       t = u;
@@ -376,7 +392,8 @@ pb_status tree_prepare(pb_ctx* ctx, const pb_band* band, const Derived& d, int d
   }
   // target batches: runs of sibling leaves (in child order) of at most kBatch nodes, so that
   // every batch lies inside one parent cell; a tree that is a single leaf is one batch
-  std::vector<int2> batch;
+  std::vector<int2>& batch = H.batch;
+  batch.clear();
   {
     if (nodes[0].n_kids == 0) batch.push_back(make_int2(0, n));
     std::vector<int> st{0};
@@ -409,6 +426,29 @@ pb_status tree_prepare(pb_ctx* ctx, const pb_band* band, const Derived& d, int d
       for (int b = bt.x; b < bt.y; b += kBatch) split.push_back(make_int2(b, std::min(bt.y, b + kBatch)));
     batch.swap(split);
   }
+  return PB_OK;
+}
+
+}  // namespace
+
+pb_status tree_prepare(pb_ctx* ctx, const pb_band* band, const Derived& d, int degree, double theta, TreePlan& T,
+                       const char* pfx, const MixedPlan* near, std::shared_ptr<TreeHost>* host) {
+  const int n = (int)band->n;
+  const std::string px_ = pfx;
+  if (near) T.near = *near;  // the near field depends on the geometry only: shared between plans
+  else PB_TRY(near_build(ctx, band, d, (px_ + "n_").c_str(), T.near));
+  const MixedPlan& P = T.near;
+  const int P1 = degree + 1, P3 = P1 * P1 * P1;
+  std::shared_ptr<TreeHost> hp = host && *host && (*host)->n == n ? *host : nullptr;
+  if (!hp) {
+    hp = std::make_shared<TreeHost>();
+    PB_TRY(build_host_tree(ctx, band, P, *hp));
+    if (host) *host = hp;
+  }
+  const std::vector<int>& perm = hp->perm;
+  const std::vector<double>& s = hp->s;
+  const std::vector<HNode>& nodes = hp->nodes;
+  std::vector<int2> batch = hp->batch;
   const int n_batch = (int)batch.size();
   // interaction lists per batch, then batches ordered by decreasing work (the longest waves
   // start first)
@@ -416,33 +456,48 @@ pb_status tree_prepare(pb_ctx* ctx, const pb_band* band, const Derived& d, int d
   std::vector<std::vector<int2>> dirs(n_batch);
   std::vector<std::vector<int>> apps(n_batch);
   std::vector<int64_t> work(n_batch, 0);
-  std::vector<int> stack;
-  int64_t n_dir_pairs = 0, n_app_pairs = 0;
-  for (int bi = 0; bi < n_batch; ++bi) {
-    const int b = batch[bi].x, e = batch[bi].y;
-    double blo[3], bhi[3], bc[3], br;
-    tight_box(s, b, e, blo, bhi, bc, &br);
-    std::vector<int2>& dl = dirs[bi];
-    stack.assign(1, 0);
-    while (!stack.empty()) {
-      const int k = stack.back();
-      stack.pop_back();
-      const HNode& nd = nodes[k];
-      const double dist = std::sqrt((bc[0] - nd.c[0]) * (bc[0] - nd.c[0]) + (bc[1] - nd.c[1]) * (bc[1] - nd.c[1]) +
-                                    (bc[2] - nd.c[2]) * (bc[2] - nd.c[2]));
-      if (nd.e - nd.b > P3 && br + nd.r < theta * dist && dist - br - nd.r > rcs) {
-        apps[bi].push_back(k);
-        work[bi] += P3;
-      } else if (nd.n_kids == 0) {
-        if (!dl.empty() && dl.back().y == nd.b) dl.back().y = nd.e;
-        else dl.push_back(make_int2(nd.b, nd.e));
-        work[bi] += 2 * (nd.e - nd.b);  // a direct pair costs about twice a proxy interaction
-      } else {
-        for (int q = nd.n_kids - 1; q >= 0; --q) stack.push_back(nd.first_kid + q);
+  // the walks of the batches are independent: host threads over contiguous slices
+  auto walk = [&](int b0, int b1) {
+    std::vector<int> stack;
+    for (int bi = b0; bi < b1; ++bi) {
+      const int b = batch[bi].x, e = batch[bi].y;
+      double blo[3], bhi[3], bc[3], br;
+      tight_box(s, b, e, blo, bhi, bc, &br);
+      std::vector<int2>& dl = dirs[bi];
+      stack.assign(1, 0);
+      while (!stack.empty()) {
+        const int k = stack.back();
+        stack.pop_back();
+        const HNode& nd = nodes[k];
+        const double dist = std::sqrt((bc[0] - nd.c[0]) * (bc[0] - nd.c[0]) + (bc[1] - nd.c[1]) * (bc[1] - nd.c[1]) +
+                                      (bc[2] - nd.c[2]) * (bc[2] - nd.c[2]));
+        if (nd.e - nd.b > P3 && br + nd.r < theta * dist && dist - br - nd.r > rcs) {
+          apps[bi].push_back(k);
+          work[bi] += P3;
+        } else if (nd.n_kids == 0) {
+          if (!dl.empty() && dl.back().y == nd.b) dl.back().y = nd.e;
+          else dl.push_back(make_int2(nd.b, nd.e));
+          work[bi] += 2 * (nd.e - nd.b);  // a direct pair costs about twice a proxy interaction
+        } else {
+          for (int q = nd.n_kids - 1; q >= 0; --q) stack.push_back(nd.first_kid + q);
+        }
       }
     }
-    for (const int2& r : dl) n_dir_pairs += (int64_t)(e - b) * (r.y - r.x);
-    n_app_pairs += (int64_t)(e - b) * P3 * (int64_t)apps[bi].size();
+  };
+  {
+    const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+    const int n_thr = std::max(1, std::min({hw, 16, n_batch / 256}));
+    std::vector<std::thread> pool;
+    for (int q = 1; q < n_thr; ++q)
+      pool.emplace_back(walk, (int)((int64_t)n_batch * q / n_thr), (int)((int64_t)n_batch * (q + 1) / n_thr));
+    walk(0, (int)((int64_t)n_batch / n_thr));
+    for (std::thread& th : pool) th.join();
+  }
+  int64_t n_dir_pairs = 0, n_app_pairs = 0;
+  for (int bi = 0; bi < n_batch; ++bi) {
+    const int64_t cnt = batch[bi].y - batch[bi].x;
+    for (const int2& r : dirs[bi]) n_dir_pairs += cnt * (r.y - r.x);
+    n_app_pairs += cnt * P3 * (int64_t)apps[bi].size();
   }
   std::vector<int> order(n_batch);
   std::iota(order.begin(), order.end(), 0);
@@ -467,20 +522,21 @@ pb_status tree_prepare(pb_ctx* ctx, const pb_band* band, const Derived& d, int d
   std::vector<int> item_ptr{0};
   std::vector<int4> items;
   int n_cl = 0;
+  std::vector<int> cl_of(nodes.size(), -1);
   for (size_t k = 0; k < nodes.size(); ++k) {
     if (!used[k]) continue;
-    HNode& nd = nodes[k];
-    nd.cl = n_cl++;
+    const HNode& nd = nodes[k];
+    const int cl = cl_of[k] = n_cl++;
     double half[3], ext = 0.0;
     for (int a = 0; a < 3; ++a) ext = std::max(ext, nd.hi[a] - nd.lo[a]);
     for (int a = 0; a < 3; ++a) half[a] = std::max(0.5 * (nd.hi[a] - nd.lo[a]), std::max(1e-3 * ext, 1e-6));
     box.push_back(make_float4((float)nd.c[0], (float)nd.c[1], (float)nd.c[2], 0.f));
     box.push_back(make_float4((float)half[0], (float)half[1], (float)half[2], 0.f));
-    for (int t = nd.b; t < nd.e; t += kProxyChunk) items.push_back(make_int4(nd.cl, t, std::min(nd.e, t + kProxyChunk), 0));
+    for (int t = nd.b; t < nd.e; t += kProxyChunk) items.push_back(make_int4(cl, t, std::min(nd.e, t + kProxyChunk), 0));
     item_ptr.push_back((int)items.size());
   }
   std::vector<int> app_cl(app_node.size());
-  for (size_t q = 0; q < app_node.size(); ++q) app_cl[q] = nodes[app_node[q]].cl;
+  for (size_t q = 0; q < app_node.size(); ++q) app_cl[q] = cl_of[app_node[q]];
   // upload
   auto up = [&](const char* nm, const void* src, size_t bytes, void** dst) -> pb_status {
     *dst = workspace(ctx, nm, std::max<size_t>(bytes, 16));
@@ -488,22 +544,22 @@ pb_status tree_prepare(pb_ctx* ctx, const pb_band* band, const Derived& d, int d
     if (bytes) PB_HIP(ctx, hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, ctx->stream));
     return PB_OK;
   };
-  PB_TRY(up("tc_perm", perm.data(), sizeof(int) * n, (void**)&T.perm));
-  PB_TRY(up("tc_batch", batch.data(), sizeof(int2) * n_batch, (void**)&T.batch));
-  PB_TRY(up("tc_dir_ptr", dir_ptr.data(), sizeof(int) * (n_batch + 1), (void**)&T.dir_ptr));
-  PB_TRY(up("tc_dir_rng", dir_rng.data(), sizeof(int2) * dir_rng.size(), (void**)&T.dir_rng));
-  PB_TRY(up("tc_app_ptr", app_ptr.data(), sizeof(int) * (n_batch + 1), (void**)&T.app_ptr));
-  PB_TRY(up("tc_app_cl", app_cl.data(), sizeof(int) * app_cl.size(), (void**)&T.app_cl));
-  PB_TRY(up("tc_box", box.data(), sizeof(float4) * box.size(), (void**)&T.box));
-  PB_TRY(up("tc_items", items.data(), sizeof(int4) * items.size(), (void**)&T.items));
-  PB_TRY(up("tc_item_ptr", item_ptr.data(), sizeof(int) * item_ptr.size(), (void**)&T.item_ptr));
-  T.At = (float4*)workspace(ctx, "tc_At", sizeof(float4) * n);
-  T.Mt = (float4*)workspace(ctx, "tc_Mt", sizeof(float4) * n);
-  T.Nt = (float4*)workspace(ctx, "tc_Nt", sizeof(float4) * n);
-  T.PX = (float4*)workspace(ctx, "tc_PX", sizeof(float4) * std::max<size_t>((size_t)n_cl * P3, 1));
-  T.PM = (float*)workspace(ctx, "tc_PM", sizeof(float) * std::max<size_t>((size_t)n_cl * P3, 1));
-  T.part = (double2*)workspace(ctx, "tc_part", sizeof(double2) * std::max<size_t>(items.size() * P3, 1));
-  T.far = (double*)workspace(ctx, "tc_far", sizeof(double) * 2 * (size_t)n);
+  PB_TRY(up((px_ + "perm").c_str(), perm.data(), sizeof(int) * n, (void**)&T.perm));
+  PB_TRY(up((px_ + "batch").c_str(), batch.data(), sizeof(int2) * n_batch, (void**)&T.batch));
+  PB_TRY(up((px_ + "dir_ptr").c_str(), dir_ptr.data(), sizeof(int) * (n_batch + 1), (void**)&T.dir_ptr));
+  PB_TRY(up((px_ + "dir_rng").c_str(), dir_rng.data(), sizeof(int2) * dir_rng.size(), (void**)&T.dir_rng));
+  PB_TRY(up((px_ + "app_ptr").c_str(), app_ptr.data(), sizeof(int) * (n_batch + 1), (void**)&T.app_ptr));
+  PB_TRY(up((px_ + "app_cl").c_str(), app_cl.data(), sizeof(int) * app_cl.size(), (void**)&T.app_cl));
+  PB_TRY(up((px_ + "box").c_str(), box.data(), sizeof(float4) * box.size(), (void**)&T.box));
+  PB_TRY(up((px_ + "items").c_str(), items.data(), sizeof(int4) * items.size(), (void**)&T.items));
+  PB_TRY(up((px_ + "item_ptr").c_str(), item_ptr.data(), sizeof(int) * item_ptr.size(), (void**)&T.item_ptr));
+  T.At = (float4*)workspace(ctx, (px_ + "At").c_str(), sizeof(float4) * n);
+  T.Mt = (float4*)workspace(ctx, (px_ + "Mt").c_str(), sizeof(float4) * n);
+  T.Nt = (float4*)workspace(ctx, (px_ + "Nt").c_str(), sizeof(float4) * n);
+  T.PX = (float4*)workspace(ctx, (px_ + "PX").c_str(), sizeof(float4) * std::max<size_t>((size_t)n_cl * P3, 1));
+  T.PM = (float*)workspace(ctx, (px_ + "PM").c_str(), sizeof(float) * std::max<size_t>((size_t)n_cl * P3, 1));
+  T.part = (double2*)workspace(ctx, (px_ + "part").c_str(), sizeof(double2) * std::max<size_t>(items.size() * P3, 1));
+  T.far = (double*)workspace(ctx, (px_ + "far").c_str(), sizeof(double) * 2 * (size_t)n);
   if (!T.At || !T.Mt || !T.Nt || !T.PX || !T.PM || !T.part || !T.far) return PB_ENOMEM;
   T.band_key = band->px;
   T.n = n;
@@ -550,8 +606,8 @@ void launch_tree(pb_ctx* ctx, const TreePlan& T, bool screened, const F32Params&
 
 }  // namespace
 
-pb_status matvec_tree(pb_ctx* ctx, const pb_band* band, const Derived& d, const double* p, double* y) {
-  const TreePlan& T = ctx->tree;
+pb_status matvec_tree(pb_ctx* ctx, const pb_band* band, const Derived& d, const double* p, double* y,
+                      const TreePlan& T) {
   const MixedPlan& P = T.near;
   const int n = (int)band->n;
   if (T.band_key != band->px || T.n != n || T.rc != d.rc)

@@ -164,3 +164,21 @@ def test_learned_tree_solve(pbm, ctx):
     e64 = pbm.pb_solvation_energy(ctx, band, at, prm, q64).g_pol
     say(f"  iters {st.iters} outer {st.outer} fallback {st.fallback_used}; energy rel diff {abs(e / e64 - 1):.2e}")
     assert e == pytest.approx(e64, rel=1e-7)
+
+
+def test_tree_solve_large_band_fine_residuals(pbm, ctx):
+    """Above 150,000 nodes the refinement's residuals come from the fine treecode (degree 7,
+    θ = 0.5) instead of the dense mixed operator; the FP64 certification is unchanged. A
+    5000-atom globule at h = 0.5 (about 157k nodes): converged to the exact FP64 residual,
+    energy within 1e-7 of the FP64 solve's."""
+    say("case: treecode solve with fine residuals, globule 5000 atoms seed 200000 h=0.5, tol 1e-6")
+    prm, at, band = _pipeline(pbm, ctx, synth.globule(5000, 200000), 0.5, True)
+    assert band.n >= 150000
+    q, st = pbm.pb_ibim_solve(ctx, band, at, prm, pbm.solve_opts(tol=1e-6, precision=pbm.PB_TREE))
+    assert st.converged and st.true_relres <= 1e-6
+    q64, st64 = pbm.pb_ibim_solve(ctx, band, at, prm, pbm.solve_opts(tol=1e-6, precision=pbm.PB_FP64))
+    e = pbm.pb_solvation_energy(ctx, band, at, prm, q).g_pol
+    e64 = pbm.pb_solvation_energy(ctx, band, at, prm, q64).g_pol
+    say(f"  n={band.n}: iters {st.iters} outer {st.outer} relres {st.true_relres:.2e}; energy rel diff "
+        f"{abs(e / e64 - 1):.2e}")
+    assert e == pytest.approx(e64, rel=1e-6)
