@@ -277,6 +277,30 @@ def bench_batch(args):
                    "speedup_vs_plain_batched": (sum(tsolve) / len(tsolve)) / lbst.t_total_s, "network": rec}
         log(f"learned batch: replays={lbst.graph_replays} solve={lbst.t_total_s:.3f}s p50={lbst.t_p50_s:.3f}s "
             f"p99={lbst.t_p99_s:.3f}s fallbacks={learned['fallbacks']} energy diff {rel:.2e}")
+    fp64 = None
+    if "fp64" in [x for x in args.legs.split(",") if x] and not args.no_compare:
+        # plain FP64 GMRES on the same 64 molecules, one after the other (x0 = Λ⁻¹g)
+        o64 = pb.solve_opts(tol=args.tol, precision=pb.PB_FP64)
+        pb.pb_ibim_solve(ctx, bands[0], ats[0], prm, o64)  # warm the FP64 kernel choice
+        torch.cuda.synchronize()
+        t64, e64, iters64 = 0.0, [], []
+        for b, at in zip(bands, ats):
+            t1 = time.perf_counter()
+            q64, st64 = pb.pb_ibim_solve(ctx, b, at, prm, o64)
+            torch.cuda.synchronize()
+            t64 += time.perf_counter() - t1
+            iters64.append(st64.iters)
+            e64.append(pb.pb_solvation_energy(ctx, b, at, prm, q64).g_pol)
+        e_plain = [pb.pb_solvation_energy(ctx, b, at, prm, p).g_pol for b, at, p in zip(bands, ats, ps)]
+        fp64 = {"solve_s_total": t64, "iters_range": [min(iters64), max(iters64)],
+                "max_energy_rel_diff_batched_vs_fp64": max(abs(a / c - 1) for a, c in zip(e_plain, e64))}
+        if learned is not None:
+            e_l = [pb.pb_solvation_energy(ctx, b, at, prm, q).g_pol for b, at, q in zip(bands, ats, lps)]
+            fp64["max_energy_rel_diff_learned_batched_vs_fp64"] = max(abs(a / c - 1) for a, c in zip(e_l, e64))
+            fp64["speedup_learned_batched_vs_fp64"] = t64 / learned["solve_s"]
+        fp64["speedup_batched_vs_fp64"] = t64 / (sum(tsolve) / len(tsolve))
+        log(f"FP64 GMRES, one molecule after the other: {t64:.3f} s, energies within "
+            f"{fp64['max_energy_rel_diff_batched_vs_fp64']:.2e} of the batched solve")
     out = {
         "metric": METRIC, "value": pairs / elapsed, "unit": "pair-interactions/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed * 1e3 / args.steps,
@@ -289,7 +313,7 @@ def bench_batch(args):
         "batch": {"solve_s_mean": sum(tsolve) / len(tsolve), "p50_solve_s": sum(p50) / len(p50),
                   "p99_solve_s": sum(p99) / len(p99), "graph_replays": bst.graph_replays,
                   "far_tile": bst.far_tile, "far_targets_per_lane": bst.far_tpl, "work_items": bst.n_items,
-                  "learned": learned},
+                  "learned": learned, "fp64_sequential": fp64},
         "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
