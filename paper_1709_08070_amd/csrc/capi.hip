@@ -80,19 +80,26 @@ static hipEvent_t get_event(pb_ctx* ctx) {
   return e;
 }
 
-Scope::Scope(pb_ctx* c, const char* n) : ctx(c), name(n) {
-  if (!ctx->timing) return;
+// The far-field families: what timing level 2 measures (events around every other launch
+// would add their own gaps to a timed run).
+static bool far_family(const char* n) {
+  return !std::strcmp(n, "p2p_f32") || !std::strcmp(n, "p2p_f64") || !std::strcmp(n, "tree_f32");
+}
+
+Scope::Scope(pb_ctx* c, const char* n)
+    : ctx(c), name(n), on(c->timing == 1 || (c->timing == 2 && far_family(n))) {
+  if (!on) return;
   a = get_event(ctx);
   b = get_event(ctx);
   (void)hipEventRecord(a, ctx->stream);
 }
 
 Scope::~Scope() {
-  if (!ctx->timing) return;
+  if (!on) return;
   (void)hipEventRecord(b, ctx->stream);
   ctx->pending.emplace_back(a, b);
   ctx->pending_name.emplace_back(name);
-  if (ctx->pending.size() > 4096) {
+  if (ctx->pending.size() > 32768) {
     (void)hipStreamSynchronize(ctx->stream);
     flush_timers(ctx);
   }
@@ -111,6 +118,17 @@ void flush_timers(pb_ctx* ctx) {
   }
   ctx->pending.clear();
   ctx->pending_name.clear();
+}
+
+void drop_timers(pb_ctx* ctx, size_t mark) {
+  for (size_t i = mark; i < ctx->pending.size(); ++i) {
+    ctx->event_pool.push_back(ctx->pending[i].first);
+    ctx->event_pool.push_back(ctx->pending[i].second);
+  }
+  if (mark < ctx->pending.size()) {
+    ctx->pending.resize(mark);
+    ctx->pending_name.resize(mark);
+  }
 }
 
 pb_status sync(pb_ctx* ctx, const char* where) {
@@ -253,6 +271,9 @@ void pb_destroy(pb_ctx* ctx) {
     (void)hipEventDestroy(e.second);
   }
   for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
+  for (auto e : ctx->step_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (ctx->host_state) (void)hipHostFree(ctx->host_state);
   if (ctx->batch_stream) {
     (void)hipStreamSynchronize(ctx->batch_stream);
     (void)hipStreamDestroy(ctx->batch_stream);
@@ -331,7 +352,8 @@ pb_status pb_grid_for_atoms(const double* atoms, int n_atoms, const pb_params* p
 pb_status pb_set_timing(pb_ctx* ctx, int enable) {
   if (!ctx) return PB_EINVAL;
   PB_TRY(pb::sync(ctx, "pb_set_timing"));
-  ctx->timing = enable != 0;
+  if (enable < 0 || enable > 2) return ctx->fail(PB_EINVAL, "timing level %d", enable);
+  ctx->timing = enable;
   ctx->timers.clear();
   return PB_OK;
 }

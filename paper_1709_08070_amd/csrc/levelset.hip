@@ -10,6 +10,7 @@
 // neighbours are served from L2. Products and sums are rounded as written (no FMA
 // contraction), so the grid values are reproducible to the last bit from run to run.
 #include <cmath>
+#include <utility>
 
 #include "pb_internal.hpp"
 #include "stencil.hpp"
@@ -195,18 +196,22 @@ __global__ void __launch_bounds__(kBlock) k_cav_dilate(GridDev g, const double* 
 
 unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-// Three-stage TVD-RK3 for `steps` steps of size dt; φ is updated in place.
+// Three-stage TVD-RK3 for `steps` steps of size dt; φ is updated in place. The step's result
+// goes to the buffer its first stage used, which then holds φ (the two swap every step);
+// after an odd number of steps it is copied back into phi.
 pb_status tvd_rk3(pb_ctx* ctx, const GridDev& g, double* phi, double* p1, double* p2, const double* S, int mode,
                   int steps, double dt) {
   int64_t total = (int64_t)g.nx * g.ny * g.nz;
   unsigned nb = blocks_for(total);
+  double *cur = phi, *spare = p1;
   for (int s = 0; s < steps; ++s) {
     Scope t(ctx, "levelset");
-    k_rk_stage<<<nb, kBlock, 0, ctx->stream>>>(g, phi, phi, S, p1, mode, 0, dt);
-    k_rk_stage<<<nb, kBlock, 0, ctx->stream>>>(g, p1, phi, S, p2, mode, 1, dt);
-    k_rk_stage<<<nb, kBlock, 0, ctx->stream>>>(g, p2, phi, S, p1, mode, 2, dt);
-    PB_HIP(ctx, hipMemcpyAsync(phi, p1, sizeof(double) * total, hipMemcpyDeviceToDevice, ctx->stream));
+    k_rk_stage<<<nb, kBlock, 0, ctx->stream>>>(g, cur, cur, S, spare, mode, 0, dt);
+    k_rk_stage<<<nb, kBlock, 0, ctx->stream>>>(g, spare, cur, S, p2, mode, 1, dt);
+    k_rk_stage<<<nb, kBlock, 0, ctx->stream>>>(g, p2, cur, S, spare, mode, 2, dt);
+    std::swap(cur, spare);
   }
+  if (cur != phi) PB_HIP(ctx, hipMemcpyAsync(phi, cur, sizeof(double) * total, hipMemcpyDeviceToDevice, ctx->stream));
   return launch_ok(ctx, "levelset rk3");
 }
 

@@ -74,36 +74,37 @@ int far_chunks(pb_ctx* ctx, int n, int targets_per_block, int tile, int* chunk) 
 
 template <int TILE, int TPL>
 int launch_far_t(pb_ctx* ctx, bool screened, const float4* A, const float4* M, const float4* N, const float4* box,
-                 int n, const F32Params& fp, double sig1, double sig2, double* partial) {
+                 int n, const F32Params& fp, double sig1, double sig2, double* partial, const int* skip) {
   int chunk = 0;
   const int S = far_chunks(ctx, n, kBlock * TPL, TILE, &chunk);
   dim3 grid((unsigned)((n + kBlock * TPL - 1) / (kBlock * TPL)), (unsigned)S);
   if (screened)
-    k_p2p_f32<TILE, TPL, true><<<grid, kBlock, 0, ctx->stream>>>(A, M, N, box, n, chunk, fp, sig1, sig2, partial);
+    k_p2p_f32<TILE, TPL, true><<<grid, kBlock, 0, ctx->stream>>>(A, M, N, box, n, chunk, fp, sig1, sig2, partial, skip);
   else
-    k_p2p_f32<TILE, TPL, false><<<grid, kBlock, 0, ctx->stream>>>(A, M, N, box, n, chunk, fp, sig1, sig2, partial);
+    k_p2p_f32<TILE, TPL, false><<<grid, kBlock, 0, ctx->stream>>>(A, M, N, box, n, chunk, fp, sig1, sig2, partial, skip);
   return S;
 }
 
 int launch_far(pb_ctx* ctx, int cfg, bool screened, const float4* A, const float4* M, const float4* N,
-               const float4* box, int n, const F32Params& fp, double sig1, double sig2, double* partial) {
+               const float4* box, int n, const F32Params& fp, double sig1, double sig2, double* partial,
+               const int* skip) {
   if (cfg == kSymCfg) {
     int n_items = 0;
     const int2* items = sym_items_dev(ctx, n, &n_items);
     if (!items) return -1;
     if (screened)
       k_p2p_f32_sym<true><<<(unsigned)n_items, kBlock, 0, ctx->stream>>>(A, N, box, n, sym_nsub(n), items,
-                                                                          n_items, fp, sig1, sig2, partial);
+                                                                          n_items, fp, sig1, sig2, partial, skip);
     else
       k_p2p_f32_sym<false><<<(unsigned)n_items, kBlock, 0, ctx->stream>>>(A, N, box, n, sym_nsub(n), items,
-                                                                           n_items, fp, sig1, sig2, partial);
+                                                                           n_items, fp, sig1, sig2, partial, skip);
     return sym_chunks(n);
   }
   switch (cfg) {
-    case 0: return launch_far_t<256, 1>(ctx, screened, A, M, N, box, n, fp, sig1, sig2, partial);
-    case 1: return launch_far_t<512, 1>(ctx, screened, A, M, N, box, n, fp, sig1, sig2, partial);
-    case 2: return launch_far_t<256, 2>(ctx, screened, A, M, N, box, n, fp, sig1, sig2, partial);
-    default: return launch_far_t<512, 2>(ctx, screened, A, M, N, box, n, fp, sig1, sig2, partial);
+    case 0: return launch_far_t<256, 1>(ctx, screened, A, M, N, box, n, fp, sig1, sig2, partial, skip);
+    case 1: return launch_far_t<512, 1>(ctx, screened, A, M, N, box, n, fp, sig1, sig2, partial, skip);
+    case 2: return launch_far_t<256, 2>(ctx, screened, A, M, N, box, n, fp, sig1, sig2, partial, skip);
+    default: return launch_far_t<512, 2>(ctx, screened, A, M, N, box, n, fp, sig1, sig2, partial, skip);
   }
 }
 
@@ -140,10 +141,10 @@ pb_status far_autotune(pb_ctx* ctx, int n, bool screened, const float4* A, const
   int best = 0;
   float best_ms = 1e30f;
   for (int c = 0; c < kNumFarCfgs; ++c) {
-    if (launch_far(ctx, c, screened, A, M, N, box, n, fp, 1.0, 1.0, partial) < 0)
+    if (launch_far(ctx, c, screened, A, M, N, box, n, fp, 1.0, 1.0, partial, nullptr) < 0)
       return ctx->fail(PB_ENOMEM, "far-field work list");
     PB_HIP(ctx, hipEventRecord(e0, ctx->stream));
-    launch_far(ctx, c, screened, A, M, N, box, n, fp, 1.0, 1.0, partial);
+    launch_far(ctx, c, screened, A, M, N, box, n, fp, 1.0, 1.0, partial, nullptr);
     PB_HIP(ctx, hipEventRecord(e1, ctx->stream));
     PB_TRY(launch_ok(ctx, "far autotune"));
     PB_HIP(ctx, hipEventSynchronize(e1));
@@ -165,20 +166,21 @@ namespace {
 
 // FP64 operator kernel: 0 = one target per lane over source chunks, 1 = symmetric.
 int launch_f64(pb_ctx* ctx, int cfg, const pb_band* band, const double* wpsi, const double* wpsn, const KParams& kp,
-               double* partial) {
+               double* partial, const int* skip) {
   const int n = (int)band->n;
   if (cfg == 1) {
     int n_items = 0;
     const int2* items = sym_items_dev(ctx, n, &n_items);
     if (!items) return -1;
     k_p2p_f64_sym<<<(unsigned)n_items, kBlock, 0, ctx->stream>>>(band_dev(band), wpsi, wpsn, n, sym_nsub(n), items,
-                                                                 n_items, kp, partial);
+                                                                 n_items, kp, partial, skip);
     return sym_chunks(n);
   }
   int chunk = 0;
   const int S = far_chunks(ctx, n, kBlock, kBlock, &chunk);
   const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
-  k_p2p_f64<<<dim3(nb, S), kBlock, 0, ctx->stream>>>(band_dev(band, kp.curved), wpsi, wpsn, n, chunk, partial, kp);
+  k_p2p_f64<<<dim3(nb, S), kBlock, 0, ctx->stream>>>(band_dev(band, kp.curved), wpsi, wpsn, n, chunk, partial, kp,
+                                                                     skip);
   return S;
 }
 
@@ -206,7 +208,8 @@ pb_status f64_autotune(pb_ctx* ctx, const pb_band* band, const double* wpsi, con
   float best_ms = 1e30f;
   for (int c = 0; c < 2; ++c) {
     PB_HIP(ctx, hipEventRecord(e0, ctx->stream));
-    if (launch_f64(ctx, c, band, wpsi, wpsn, kp, partial) < 0) return ctx->fail(PB_ENOMEM, "FP64 work list");
+    if (launch_f64(ctx, c, band, wpsi, wpsn, kp, partial, nullptr) < 0)
+      return ctx->fail(PB_ENOMEM, "FP64 work list");
     PB_HIP(ctx, hipEventRecord(e1, ctx->stream));
     PB_TRY(launch_ok(ctx, "f64 autotune"));
     PB_HIP(ctx, hipEventSynchronize(e1));
@@ -242,7 +245,7 @@ pb_status matvec_fp64(pb_ctx* ctx, const pb_band* band, const Derived& d, const 
   int S = 0;
   {
     Scope t(ctx, "p2p_f64");
-    S = launch_f64(ctx, cfg, band, wpsi, wpsn, kp, partial);
+    S = launch_f64(ctx, cfg, band, wpsi, wpsn, kp, partial, ctx->skip);
   }
   if (S < 0) return ctx->fail(PB_ENOMEM, "FP64 work list");
   {
@@ -333,7 +336,8 @@ pb_status near_build(pb_ctx* ctx, const pb_band* band, const Derived& d, const c
   k_group_box<<<(unsigned)ngroup, kGroup, 0, ctx->stream>>>(n, A, box);
   const CellsDev cells{start, nodes, cell_of, P.ncx, P.ncy, P.ncz};
   PB_HIP(ctx, hipMemsetAsync(row + n, 0, sizeof(int64_t), ctx->stream));
-  k_near_count<<<nb, kBlock, 0, ctx->stream>>>(n, A, cells, P.rc2f, row);
+  const unsigned nbw = (unsigned)((n + kNearWaves - 1) / kNearWaves);
+  k_near_count<<<nbw, kBlock, 0, ctx->stream>>>(n, A, cells, P.rc2f, row);
   PB_TRY(launch_ok(ctx, "near count"));
   int64_t nnz = 0;
   PB_TRY(exclusive_scan_i64(ctx, row, n + 1, &nnz));
@@ -341,8 +345,8 @@ pb_status near_build(pb_ctx* ctx, const pb_band* band, const Derived& d, const c
   int* col = (int*)workspace(ctx, name("near_col"), sizeof(int) * (size_t)std::max<int64_t>(nnz, 1));
   double4* coef = (double4*)workspace(ctx, name("near_coef"), sizeof(double4) * (size_t)std::max<int64_t>(nnz, 1));
   if (!col || !coef) return PB_ENOMEM;
-  k_near_fill<<<nb, kBlock, 0, ctx->stream>>>(n, band_dev(band, d.curved), band->w, d.h3 / (4.0 * kPi), A, cells, P.rc2f,
-                                              kparams(d), row, col, coef);
+  k_near_fill<<<nbw, kBlock, 0, ctx->stream>>>(n, band_dev(band, d.curved), band->w, d.h3 / (4.0 * kPi), A, cells,
+                                               P.rc2f, kparams(d), row, col, coef);
   PB_TRY(launch_ok(ctx, "near fill"));
   P.A = A;
   P.M = M;
@@ -378,7 +382,7 @@ pb_status matvec_mixed(pb_ctx* ctx, const pb_band* band, const Derived& d, const
   {
     Scope t(ctx, "p2p_f32");
     S = launch_far(ctx, P.far_cfg, d.kappa > 0.0, P.A, P.M, P.N, P.box, n, f32params(d, P.sigma), P.sigma,
-                   P.sigma * P.sigma, partial);
+                   P.sigma * P.sigma, partial, ctx->skip);
   }
   if (S < 0) return ctx->fail(PB_ENOMEM, "far-field work list");
   {

@@ -241,7 +241,9 @@ constexpr int kWPad = 8;
 template <bool kDense, int CIN, int COUT, bool kAct>
 __global__ void __launch_bounds__(256) k_layer_fwd(int n, const uint16_t* __restrict__ G1, const float* __restrict__ X,
                                                    const int* __restrict__ nbr, const uint16_t* __restrict__ Wt,
-                                                   const float* __restrict__ bias, float* __restrict__ Y) {
+                                                   const float* __restrict__ bias, float* __restrict__ Y,
+                                                   const int* __restrict__ skip) {
+  if (skip && *skip) return;
   constexpr int K = kSlots * CIN;
   constexpr int NT = COUT / 16;
   constexpr int KC = K < kWChunk ? K : kWChunk;
@@ -677,13 +679,13 @@ pb_status nn_apply(pb_ctx* ctx, const pb_nn* net, const pb_band* band, const Der
   const uint16_t* wt = net->wt;
   const float* prm = net->params;
   k_layer_fwd<true, 16, 64, true><<<nbl, 256, 0, ctx->stream>>>(n, B.G1, nullptr, B.nbr, wt + wbf_off(0),
-                                                                 prm + b_off(0), B.X[1]);
+                                                                 prm + b_off(0), B.X[1], ctx->skip);
   k_layer_fwd<false, 64, 64, true><<<nbl, 256, 0, ctx->stream>>>(n, nullptr, B.X[1], B.nbr, wt + wbf_off(1),
-                                                                  prm + b_off(1), B.X[2]);
+                                                                  prm + b_off(1), B.X[2], ctx->skip);
   k_layer_fwd<false, 64, 64, true><<<nbl, 256, 0, ctx->stream>>>(n, nullptr, B.X[2], B.nbr, wt + wbf_off(2),
-                                                                  prm + b_off(2), B.X[3]);
+                                                                  prm + b_off(2), B.X[3], ctx->skip);
   k_layer_fwd<false, 64, 16, false><<<nbl, 256, 0, ctx->stream>>>(n, nullptr, B.X[3], B.nbr, wt + wbf_off(3),
-                                                                   prm + b_off(3), O);
+                                                                   prm + b_off(3), O, ctx->skip);
   k_apply_out<<<nb, kBlock, 0, ctx->stream>>>(n, v, O, B.s, d.lam1, d.lam2, p);
   return launch_ok(ctx, "nn apply");
 }
@@ -916,13 +918,13 @@ void nn_batch_apply(hipStream_t stream, const pb_nn* net, const NNBatch& nb, con
   const uint16_t* wt = net->wt;
   const float* prm = net->params;
   k_layer_fwd<true, 16, 64, true><<<nbl, 256, 0, stream>>>(ntot, nb.G1, nullptr, nb.nbr, wt + wbf_off(0),
-                                                          prm + b_off(0), nb.X[1]);
+                                                          prm + b_off(0), nb.X[1], nullptr);
   k_layer_fwd<false, 64, 64, true><<<nbl, 256, 0, stream>>>(ntot, nullptr, nb.X[1], nb.nbr, wt + wbf_off(1),
-                                                           prm + b_off(1), nb.X[2]);
+                                                           prm + b_off(1), nb.X[2], nullptr);
   k_layer_fwd<false, 64, 64, true><<<nbl, 256, 0, stream>>>(ntot, nullptr, nb.X[2], nb.nbr, wt + wbf_off(2),
-                                                           prm + b_off(2), nb.X[3]);
+                                                           prm + b_off(2), nb.X[3], nullptr);
   k_layer_fwd<false, 64, 16, false><<<nbl, 256, 0, stream>>>(ntot, nullptr, nb.X[3], nb.nbr, wt + wbf_off(3),
-                                                            prm + b_off(3), nb.O);
+                                                            prm + b_off(3), nb.O, nullptr);
   k_apply_out_batch<<<(unsigned)((ntot + kBlock - 1) / kBlock), kBlock, 0, stream>>>(
       ntot, nb.mol_of, nb.off, nb.cnt, V, Z, ldv, kptr, kmax, nb.O, nb.s, lam1, lam2);
 }

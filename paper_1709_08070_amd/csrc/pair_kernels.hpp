@@ -140,13 +140,12 @@ __device__ __forceinline__ void pair_f32(const float4& ta, const float4& tn, con
   const float r2 = r2_f32(ta.x, ta.y, ta.z, sa.x, sa.y, sa.z);
   float rinv = __builtin_amdgcn_rsqf(r2);
   if (kCheck && r2 < fp.rc2) rinv = 0.f;
-  float E = 1.f, Ez = 0.f, z = 0.f;
+  float E = 1.f, z = 0.f;
   if (kScreened) {
     z = r2 * rinv;
     E = __builtin_amdgcn_exp2f(fp.mlog2e * z);
-    Ez = E * z;
   }
-  const float a = E + Ez;
+  const float a = __fmaf_rn(E, z, E);  // E(1 + r')
   const float dnx = __fmaf_rn(dz, tn.z, __fmaf_rn(dy, tn.y, dx * tn.x));
   const float D = __fmaf_rn(dz, sm.z, __fmaf_rn(dy, sm.y, dx * sm.x));
   const float Nw = __fmaf_rn(tn.z, sm.z, __fmaf_rn(tn.y, sm.y, tn.x * sm.x));
@@ -159,10 +158,10 @@ __device__ __forceinline__ void pair_f32(const float4& ta, const float4& tn, con
   if (kScreened) {
     const float f0w = __fmaf_rn(-E, sa.w, sa.w);  // (1 − E) w̃n_j
     a1 = __fmaf_rn(-f0w, rinv, a1);
-    const float g = __fmaf_rn(Ez, z, __fmaf_rn(3.f, a, -3.f));
+    const float gr = __fmaf_rn(__fmaf_rn(3.f, a, -3.f), ri2, E);  // g/r'² = E − 3(1 − a)/r'²
     t = __fmaf_rn(-a, Nw, Nw);
     t = __fmaf_rn(c2 * dnx, sa.w, t);
-    t = __fmaf_rn(dnx * D * ri2, g, t);
+    t = __fmaf_rn(dnx * D, gr, t);
   } else {  // κ = 0: E = a = 1 and z = 0, so only the θ terms remain
     t = c2 * dnx * sa.w;
   }
@@ -317,7 +316,9 @@ __device__ __forceinline__ void far64_tile_loop(const BandDev& b, const double* 
 // FP64 operator, one target per lane; block (x: target block, y: source chunk).
 static __global__ void __attribute__((unused)) __launch_bounds__(kBlock) k_p2p_f64(BandDev b, const double* __restrict__ wpsi,
                                                            const double* __restrict__ wpsn, int n, int chunk,
-                                                           double* __restrict__ partial, KParams kp) {
+                                                           double* __restrict__ partial, KParams kp,
+                                                           const int* __restrict__ skip) {
+  if (skip && *skip) return;
   __shared__ double smem[8 * kBlock];
   const int t0 = blockIdx.x * kBlock;
   const int j0 = blockIdx.y * chunk;
@@ -334,6 +335,8 @@ static __global__ void __attribute__((unused)) __launch_bounds__(kBlock) k_reduc
   int e = blockIdx.x * kBlock + threadIdx.x;
   if (e >= 2 * n) return;
   double s = 0.0;
+  // unrolled so that eight loads are in flight; the sum keeps its chunk order
+#pragma unroll 8
   for (int c = 0; c < n_chunks; ++c) s += partial[(size_t)c * 2 * n + e];
   if (near) s += near[e];
   y[e] = (e < n ? lam1 : lam2) * p[e] + s;
@@ -390,7 +393,9 @@ static __global__ void __attribute__((unused)) __launch_bounds__(kBlock) k_p2p_f
                                                            const float4* __restrict__ N,
                                                            const float4* __restrict__ box, int n, int chunk,
                                                            F32Params fp, double sig1, double sig2,
-                                                           double* __restrict__ partial) {
+                                                           double* __restrict__ partial,
+                                                           const int* __restrict__ skip) {
+  if (skip && *skip) return;
   __shared__ float4 sA[TILE], sM[TILE];
   const int t0 = blockIdx.x * kBlock * TPL;
   const int j0 = blockIdx.y * chunk;
@@ -469,32 +474,48 @@ static __global__ void __attribute__((unused)) __launch_bounds__(kBlock) k_cell_
   }
 }
 
-// Visits the near sources of target i (FP32 distance below r_c) in a fixed order: the
-// 27 neighbouring cells in lexicographic order, each cell's nodes in increasing index.
+// Visits the near sources of target i (FP32 distance below r_c) in a fixed order: the 27
+// neighbouring cells in lexicographic order, each cell's nodes in increasing index. One
+// wave per target: the lanes test a cell's candidates 64 at a time and a ballot numbers the
+// hits in that order; f(j, slot) runs on each hit lane, and the wave's hit count returns.
 template <typename F>
-__device__ __forceinline__ void for_near(int i, const float4* __restrict__ A, const CellsDev& cells, float rc2, F f) {
+__device__ __forceinline__ int64_t for_near_wave(int i, const float4* __restrict__ A, const CellsDev& cells,
+                                                 float rc2, F f) {
+  const int lane = threadIdx.x & 63;
   const float4 ta = A[i];
   const int c = cells.cell_of[i];
   const int cz = c % cells.ncz, cy = (c / cells.ncz) % cells.ncy, cx = c / (cells.ncz * cells.ncy);
+  int64_t base = 0;
   for (int ax = max(cx - 1, 0); ax <= min(cx + 1, cells.ncx - 1); ++ax)
     for (int ay = max(cy - 1, 0); ay <= min(cy + 1, cells.ncy - 1); ++ay)
       for (int az = max(cz - 1, 0); az <= min(cz + 1, cells.ncz - 1); ++az) {
         const int cc = (ax * cells.ncy + ay) * cells.ncz + az;
-        for (int64_t q = cells.start[cc]; q < cells.start[cc + 1]; ++q) {
-          const int j = cells.nodes[q];
-          const float4 sa = A[j];
-          if (r2_f32(ta.x, ta.y, ta.z, sa.x, sa.y, sa.z) < rc2) f(j);
+        const int64_t e = cells.start[cc + 1];
+        for (int64_t q0 = cells.start[cc]; q0 < e; q0 += 64) {
+          const int64_t q = q0 + lane;
+          int j = -1;
+          bool hit = false;
+          if (q < e) {
+            j = cells.nodes[q];
+            const float4 sa = A[j];
+            hit = r2_f32(ta.x, ta.y, ta.z, sa.x, sa.y, sa.z) < rc2;
+          }
+          const unsigned long long mask = __ballot(hit);
+          if (hit) f(j, base + __popcll(mask & ((1ull << lane) - 1ull)));
+          base += __popcll(mask);
         }
       }
+  return base;
 }
+
+constexpr int kNearWaves = kBlock / 64;  // targets per block of the near-list kernels
 
 static __global__ void __attribute__((unused)) __launch_bounds__(kBlock) k_near_count(int n, const float4* __restrict__ A, CellsDev cells, float rc2,
                                                        int64_t* __restrict__ counts) {
-  int i = blockIdx.x * kBlock + threadIdx.x;
+  const int i = blockIdx.x * kNearWaves + (threadIdx.x >> 6);
   if (i >= n) return;
-  int64_t c = 0;
-  for_near(i, A, cells, rc2, [&](int) { ++c; });
-  counts[i] = c;
+  const int64_t c = for_near_wave(i, A, cells, rc2, [&](int, int64_t) {});
+  if ((threadIdx.x & 63) == 0) counts[i] = c;
 }
 
 // Near-field block matrix: for each near pair the FP64 coefficients of
@@ -505,18 +526,17 @@ static __global__ void __attribute__((unused)) __launch_bounds__(kBlock) k_near_
                                                       const float4* __restrict__ A, CellsDev cells, float rc2,
                                                       KParams kp, const int64_t* __restrict__ row,
                                                       int* __restrict__ col, double4* __restrict__ coef) {
-  int i = blockIdx.x * kBlock + threadIdx.x;
+  const int i = blockIdx.x * kNearWaves + (threadIdx.x >> 6);
   if (i >= n) return;
   const double xi = b.px[i], yi = b.py[i], zi = b.pz[i], nxi = b.nx[i], nyi = b.ny[i], nzi = b.nz[i];
   const double ci = b.curv ? b.curv[i] : 0.0;
-  int64_t q = row[i];
-  for_near(i, A, cells, rc2, [&](int j) {
+  const int64_t r0 = row[i];
+  for_near_wave(i, A, cells, rc2, [&](int j, int64_t slot) {
     double k[4];
     kern4_f64(xi, yi, zi, nxi, nyi, nzi, b.px[j], b.py[j], b.pz[j], b.nx[j], b.ny[j], b.nz[j], kp, ci, k);
     const double sj = scale * w[j];
-    col[q] = j;
-    coef[q] = make_double4(k[0] * sj, -k[1] * sj, k[2] * sj, -k[3] * sj);
-    ++q;
+    col[r0 + slot] = j;
+    coef[r0 + slot] = make_double4(k[0] * sj, -k[1] * sj, k[2] * sj, -k[3] * sj);
   });
 }
 

@@ -108,7 +108,7 @@ struct pb_ctx {
   hipStream_t stream = nullptr;
   std::string err;
   std::map<std::string, pb::DevBuf> bufs;
-  bool timing = false;
+  int timing = 0;  // 0 off, 1 every kernel family, 2 the far-field families only
   std::map<std::string, pb::Timer> timers;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;  // per launch, resolved at sync
   std::vector<std::string> pending_name;
@@ -126,6 +126,13 @@ struct pb_ctx {
   hipStream_t batch_stream = nullptr;  // capture stream of the batched solve
   const void* nn_key = nullptr;        // band prepared for the learned preconditioner
   int64_t nn_n = 0;
+  // Device flag read by the operator's heavy kernels (far field, FP64 pairs, treecode,
+  // network layers): while GMRES runs one Arnoldi step ahead of its convergence test, a
+  // step enqueued after the test has been met finds the flag set and does no work.
+  // nullptr outside such a cycle.
+  const int* skip = nullptr;
+  int* host_state = nullptr;      // pinned host copy of the per-step GMRES state (2 ints per step)
+  hipEvent_t step_ev[2] = {};     // completion of the last two enqueued Arnoldi steps
   // status of the last allocation/launch
   pb_status fail(pb_status s, const char* fmt, ...);
 };
@@ -139,11 +146,14 @@ void* workspace(pb_ctx* ctx, const char* name, size_t bytes);
 struct Scope {
   pb_ctx* ctx;
   const char* name;
+  bool on;
   hipEvent_t a{}, b{};
   Scope(pb_ctx* c, const char* n);
   ~Scope();
 };
 void flush_timers(pb_ctx* ctx);  // after a stream synchronize
+// Forgets the timings recorded since pending.size() was `mark` (launches that did no work).
+void drop_timers(pb_ctx* ctx, size_t mark);
 
 pb_status check_params(pb_ctx* ctx, const pb_params* p);
 pb_status check_band(pb_ctx* ctx, const pb_band* b);

@@ -1,9 +1,9 @@
 // Stage 3: GMRES on Λp + KWp = g (section "Fast linear solvers").
 //
-// Restarted GMRES with classical Gram–Schmidt applied twice (CGS2). The Krylov basis and
-// every vector operation live in FP64 device memory; each Arnoldi step copies one
-// Hessenberg column (2(j+1)+1 doubles) to the host, where the Givens rotations and the
-// residual estimate are updated. Dot products are two-stage fixed-order reductions.
+// Restarted GMRES with classical Gram–Schmidt applied twice (CGS2). The Krylov basis, every
+// vector operation and the Givens rotations with the residual estimate live in FP64 device
+// memory; the host reads one step's convergence flag while the next step runs and solves the
+// small triangular system once per cycle. Dot products are two-stage fixed-order reductions.
 //
 // Initial guess: Λ⁻¹g by default, the paper's "solution of the diagonal part" with D = 0.
 // Mixed precision: GMRES on A_mixed x = g from the initial guess, then iterative refinement:
@@ -24,6 +24,47 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kDotBlocks = 512;
 constexpr int kGroup = 8;
+constexpr int kMaxRestart = 2000;  // the largest restart length pb_ibim_solve accepts
+
+// Arguments of the Givens step that ends an Arnoldi step (see givens_step).
+struct GivensArgs {
+  int k, m;
+  const double* hcol;  // [pass 1 (m+1) | pass 2 (m+1) | ‖w‖]
+  double *H, *cs, *sn, *s;
+  double tol_abs;
+  int* state;
+};
+
+// Arnoldi column k into the QR factor of the Hessenberg matrix (row-major, (m+1) × m):
+// H(i,k) = sum of the two Gram–Schmidt passes' coefficients (i ≤ k), H(k+1,k) = ‖w‖; the
+// earlier rotations are applied, a new one (cs[k], sn[k]) zeroes H(k+1,k), and s is rotated
+// so that |s[k+1]| is the residual estimate. state[0] is set once that estimate is at most
+// tol_abs or ‖w‖ is not positive (breakdown); state[1] counts the steps taken. Once state[0]
+// is set, later steps leave everything as it is. One thread.
+__device__ void givens_step(const GivensArgs& g) {
+  const int k = g.k, m = g.m;
+  double* H = g.H;
+  if (g.state[0]) return;
+  const double hn = g.hcol[2 * (m + 1)];
+  for (int i = 0; i <= k; ++i) H[(size_t)i * m + k] = g.hcol[i] + g.hcol[(m + 1) + i];
+  for (int i = 0; i < k; ++i) {
+    const double a = H[(size_t)i * m + k], b = H[(size_t)(i + 1) * m + k];
+    H[(size_t)i * m + k] = g.cs[i] * a + g.sn[i] * b;
+    H[(size_t)(i + 1) * m + k] = -g.sn[i] * a + g.cs[i] * b;
+  }
+  const double a = H[(size_t)k * m + k];
+  const double den = sqrt(a * a + hn * hn);
+  const double c = den > 0.0 ? a / den : 1.0, sg = den > 0.0 ? hn / den : 0.0;
+  g.cs[k] = c;
+  g.sn[k] = sg;
+  H[(size_t)k * m + k] = den;
+  H[(size_t)(k + 1) * m + k] = 0.0;
+  const double sk = g.s[k];
+  g.s[k + 1] = -sg * sk;
+  g.s[k] = c * sk;
+  g.state[1] = k + 1;
+  if (fabs(g.s[k + 1]) <= g.tol_abs || !(hn > 0.0)) g.state[0] = 1;
+}
 
 // partial[q·nb + block] = Σ_{e in block's stride} w[e]·V[q][e], q < k, in groups of 8
 // vectors so that w is read once per group.
@@ -55,9 +96,12 @@ __global__ void __launch_bounds__(kBlock) k_dots(int64_t M, const double* __rest
   }
 }
 
-// out[q] = Σ_b partial[q·nb + b] (one block per q, fixed tree); if sq, out[q] = sqrt(out[q]).
+// out[q] = Σ_b partial[q·nb + b] (one block per q, fixed tree); if sqrt_out, out[q] =
+// sqrt(out[q]). With do_givens (a single block, the norm that ends an Arnoldi step) the
+// Givens step follows.
 __global__ void __launch_bounds__(kBlock) k_dots_finish(const double* __restrict__ partial, int nb,
-                                                        double* __restrict__ out, int sqrt_out) {
+                                                        double* __restrict__ out, int sqrt_out, int do_givens,
+                                                        GivensArgs ga) {
   __shared__ double red[kBlock];
   const int q = blockIdx.x;
   double a = 0.0;
@@ -68,7 +112,10 @@ __global__ void __launch_bounds__(kBlock) k_dots_finish(const double* __restrict
     if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[q] = sqrt_out ? sqrt(red[0]) : red[0];
+  if (threadIdx.x == 0) {
+    out[q] = sqrt_out ? sqrt(red[0]) : red[0];
+    if (do_givens) givens_step(ga);
+  }
 }
 
 // w[e] += sign · Σ_q c[q] V[q][e]
@@ -111,7 +158,25 @@ __global__ void __launch_bounds__(kBlock) k_zero(int64_t M, double* __restrict__
   for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < M; e += (int64_t)gridDim.x * kBlock) x[e] = 0.0;
 }
 
+// w = w / *nrm when *nrm > 0 (after a breakdown w is left as it is).
+__global__ void __launch_bounds__(kBlock) k_scale_pos(int64_t M, const double* __restrict__ nrm,
+                                                      double* __restrict__ w) {
+  const double v = *nrm;
+  if (!(v > 0.0)) return;
+  const double s = 1.0 / v;
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < M; e += (int64_t)gridDim.x * kBlock) w[e] *= s;
+}
+
+// A new restart cycle: clears the step state and sets s = (β, 0, ...).
+__global__ void k_cycle_start(int* __restrict__ state, double* __restrict__ s, double beta) {
+  if (threadIdx.x != 0) return;
+  state[0] = 0;
+  state[1] = 0;
+  s[0] = beta;
+}
+
 unsigned vec_blocks(int64_t M) { return (unsigned)std::min<int64_t>(2048, (M + kBlock - 1) / kBlock); }
+unsigned dot_blocks(int64_t M) { return (unsigned)std::min<int64_t>(kDotBlocks, (M + kBlock - 1) / kBlock); }
 
 using OpFn = std::function<pb_status(const double*, double*)>;
 
@@ -125,12 +190,31 @@ struct Krylov {
 
 // ‖v‖₂ to host
 pb_status norm2(pb_ctx* ctx, Krylov& K, const double* v, double* out) {
-  k_dots<<<kDotBlocks, kBlock, 0, ctx->stream>>>(K.M, v, 0, 1, v, K.partial);
-  k_dots_finish<<<1, kBlock, 0, ctx->stream>>>(K.partial, kDotBlocks, K.hcol + 2 * (K.m + 1), 1);
+  const unsigned db = dot_blocks(K.M);
+  k_dots<<<db, kBlock, 0, ctx->stream>>>(K.M, v, 0, 1, v, K.partial);
+  k_dots_finish<<<1, kBlock, 0, ctx->stream>>>(K.partial, (int)db, K.hcol + 2 * (K.m + 1), 1, 0, GivensArgs{});
   PB_TRY(launch_ok(ctx, "norm"));
   PB_HIP(ctx, hipMemcpyAsync(out, K.hcol + 2 * (K.m + 1), sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
   return sync(ctx, "norm");
 }
+
+// Sets up the pinned host slots and events through which GMRES reads each step's state.
+pb_status step_sync_init(pb_ctx* ctx) {
+  if (!ctx->host_state) {
+    void* h = nullptr;
+    PB_HIP(ctx, hipHostMalloc(&h, sizeof(int) * 2 * kMaxRestart, hipHostMallocDefault));
+    ctx->host_state = (int*)h;
+  }
+  for (auto& e : ctx->step_ev)
+    if (!e) PB_HIP(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  return PB_OK;
+}
+
+// Clears the operator's skip flag when a cycle ends, also on an error return.
+struct SkipGuard {
+  pb_ctx* ctx;
+  ~SkipGuard() { ctx->skip = nullptr; }
+};
 
 // Restarted GMRES(m) for A x = b from the given x until ‖b − Ax‖ ≤ max(tol_abs, rel·‖b − Ax₀‖)
 // (estimate, then confirmed with the operator at each restart) or max_iter operator
@@ -138,17 +222,28 @@ pb_status norm2(pb_ctx* ctx, Krylov& K, const double* v, double* out) {
 // stopped on its estimate did not halve the true residual.
 // With prec (flexible GMRES, right preconditioning): z_k = prec(v_k), w = A z_k, and the
 // update is x += Z y; the preconditioner may change from step to step (it may be nonlinear).
+//
+// The Givens rotations and the convergence test run on the device (givens_step, after the
+// norm that ends each step), and the host
+// enqueues step k before it reads the test of step k − 1, so the GPU never waits for the
+// host inside a cycle. A step enqueued after the test was met finds the operator's skip flag
+// set: its heavy kernels return at once and the step is not counted (*skipped counts them).
 pb_status gmres(pb_ctx* ctx, Krylov& K, const OpFn& op, const OpFn* prec, const double* b, double* x, double tol_abs,
-                double rel, int max_iter, int* iters, double* res_out) {
+                double rel, int max_iter, int* iters, double* res_out, int* skipped) {
   const int64_t M = K.M;
   const int m = K.m;
   double* V = (double*)workspace(ctx, "kr_V", sizeof(double) * (size_t)M * (m + 1));
   double* Z = prec ? (double*)workspace(ctx, "kr_Z", sizeof(double) * (size_t)M * m) : nullptr;
   double* r = (double*)workspace(ctx, "kr_r", sizeof(double) * (size_t)M);
   double* ydev = (double*)workspace(ctx, "kr_y", sizeof(double) * (size_t)(m + 1));
-  if (!V || !r || !ydev || (prec && !Z)) return PB_ENOMEM;
-  const unsigned vb = vec_blocks(M);
-  std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), s(m + 1), y(m), col(2 * (m + 1) + 1);
+  double* Hd = (double*)workspace(ctx, "kr_H", sizeof(double) * (size_t)(m + 1) * m);
+  double* gv = (double*)workspace(ctx, "kr_rot", sizeof(double) * (size_t)(3 * m + 1));  // cs | sn | s
+  int* state = (int*)workspace(ctx, "kr_state", 2 * sizeof(int));
+  if (!V || !r || !ydev || !Hd || !gv || !state || (prec && !Z)) return PB_ENOMEM;
+  PB_TRY(step_sync_init(ctx));
+  double *cs = gv, *sn = gv + m, *sd = gv + 2 * m;
+  const unsigned vb = vec_blocks(M), db = dot_blocks(M);
+  std::vector<double> H((size_t)(m + 1) * m, 0.0), s(m + 1), y(m);
   PB_TRY(op(x, r));
   k_residual<<<vb, kBlock, 0, ctx->stream>>>(M, b, r);
   double beta = 0.0;
@@ -161,70 +256,67 @@ pb_status gmres(pb_ctx* ctx, Krylov& K, const OpFn& op, const OpFn* prec, const 
     if (!(beta > tol_abs) || it >= max_iter) break;
     if (rel > 0.0 && early && beta > 0.5 * beta_prev) break;  // stalled at the operator's rounding level
     beta_prev = beta;
-    early = false;
     {
       Scope t(ctx, "gmres");
+      k_cycle_start<<<1, 64, 0, ctx->stream>>>(state, sd, beta);
       k_scale<<<vb, kBlock, 0, ctx->stream>>>(M, r, K.hcol + 2 * (m + 1), V);  // norm2 left ‖r‖ there
     }
-    std::fill(s.begin(), s.end(), 0.0);
-    s[0] = beta;
-    int k = 0;
-    for (; k < m && it < max_iter; ++k) {
-      double* w = V + (size_t)(k + 1) * M;
-      if (prec) {
-        PB_TRY((*prec)(V + (size_t)k * M, Z + (size_t)k * M));
-        PB_TRY(op(Z + (size_t)k * M, w));
-      } else {
-        PB_TRY(op(V + (size_t)k * M, w));
-      }
-      ++it;
-      {
-        Scope t(ctx, "gmres");
-        for (int pass = 0; pass < 2; ++pass) {
-          double* hv = K.hcol + pass * (m + 1);
-          k_dots<<<kDotBlocks, kBlock, 0, ctx->stream>>>(M, V, M, k + 1, w, K.partial);
-          k_dots_finish<<<k + 1, kBlock, 0, ctx->stream>>>(K.partial, kDotBlocks, hv, 0);
-          k_axpy_multi<<<vb, kBlock, 0, ctx->stream>>>(M, V, M, k + 1, hv, -1.0, w);
+    const int steps = std::min(m, max_iter - it);
+    int enq = 0;
+    size_t mark = 0;  // timers pending before the last enqueued step
+    {
+      SkipGuard guard{ctx};
+      ctx->skip = state;
+      for (int k = 0; k < steps; ++k) {
+        mark = ctx->pending.size();
+        double* w = V + (size_t)(k + 1) * M;
+        if (prec) {
+          PB_TRY((*prec)(V + (size_t)k * M, Z + (size_t)k * M));
+          PB_TRY(op(Z + (size_t)k * M, w));
+        } else {
+          PB_TRY(op(V + (size_t)k * M, w));
         }
-        k_dots<<<kDotBlocks, kBlock, 0, ctx->stream>>>(M, w, 0, 1, w, K.partial);
-        k_dots_finish<<<1, kBlock, 0, ctx->stream>>>(K.partial, kDotBlocks, K.hcol + 2 * (m + 1), 1);
-      }
-      PB_TRY(launch_ok(ctx, "arnoldi"));
-      PB_HIP(ctx, hipMemcpyAsync(col.data(), K.hcol, sizeof(double) * col.size(), hipMemcpyDeviceToHost, ctx->stream));
-      PB_TRY(sync(ctx, "arnoldi"));
-      const double hn = col[2 * (m + 1)];
-      for (int i = 0; i <= k; ++i) H[(size_t)i * m + k] = col[i] + col[(m + 1) + i];
-      H[(size_t)(k + 1) * m + k] = hn;
-      if (hn > 0.0) {
-        Scope t(ctx, "gmres");
-        k_scale<<<vb, kBlock, 0, ctx->stream>>>(M, w, K.hcol + 2 * (m + 1), w);
-      }
-      for (int i = 0; i < k; ++i) {
-        double a = H[(size_t)i * m + k], bb = H[(size_t)(i + 1) * m + k];
-        H[(size_t)i * m + k] = cs[i] * a + sn[i] * bb;
-        H[(size_t)(i + 1) * m + k] = -sn[i] * a + cs[i] * bb;
-      }
-      double a = H[(size_t)k * m + k], bb = H[(size_t)(k + 1) * m + k];
-      double den = std::sqrt(a * a + bb * bb);
-      cs[k] = den > 0 ? a / den : 1.0;
-      sn[k] = den > 0 ? bb / den : 0.0;
-      H[(size_t)k * m + k] = den;
-      H[(size_t)(k + 1) * m + k] = 0.0;
-      s[k + 1] = -sn[k] * s[k];
-      s[k] = cs[k] * s[k];
-      if (std::fabs(s[k + 1]) <= tol_abs || !(hn > 0.0)) {
-        ++k;
-        early = true;
-        break;
+        ++enq;
+        {
+          Scope t(ctx, "gmres");
+          for (int pass = 0; pass < 2; ++pass) {
+            double* hv = K.hcol + pass * (m + 1);
+            k_dots<<<db, kBlock, 0, ctx->stream>>>(M, V, M, k + 1, w, K.partial);
+            k_dots_finish<<<k + 1, kBlock, 0, ctx->stream>>>(K.partial, (int)db, hv, 0, 0, GivensArgs{});
+            k_axpy_multi<<<vb, kBlock, 0, ctx->stream>>>(M, V, M, k + 1, hv, -1.0, w);
+          }
+          const GivensArgs ga{k, m, K.hcol, Hd, cs, sn, sd, tol_abs, state};
+          k_dots<<<db, kBlock, 0, ctx->stream>>>(M, w, 0, 1, w, K.partial);
+          k_dots_finish<<<1, kBlock, 0, ctx->stream>>>(K.partial, (int)db, K.hcol + 2 * (m + 1), 1, 1, ga);
+          k_scale_pos<<<vb, kBlock, 0, ctx->stream>>>(M, K.hcol + 2 * (m + 1), w);
+        }
+        PB_TRY(launch_ok(ctx, "arnoldi"));
+        PB_HIP(ctx, hipMemcpyAsync(ctx->host_state + 2 * k, state, 2 * sizeof(int), hipMemcpyDeviceToHost,
+                                   ctx->stream));
+        PB_HIP(ctx, hipEventRecord(ctx->step_ev[k & 1], ctx->stream));
+        if (k >= 1) {
+          PB_HIP(ctx, hipEventSynchronize(ctx->step_ev[(k - 1) & 1]));
+          if (ctx->host_state[2 * (k - 1)]) break;  // step k − 1 met the test; step k did nothing
+        }
       }
     }
-    for (int i = k - 1; i >= 0; --i) {
+    PB_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    const int kd = ctx->host_state[2 * (enq - 1) + 1];  // steps taken
+    early = ctx->host_state[2 * (enq - 1)] != 0;
+    if (kd < 1 || kd > enq) return ctx->fail(PB_EDEVICE, "GMRES: inconsistent step count %d of %d", kd, enq);
+    if (enq > kd) drop_timers(ctx, mark);  // the last step was skipped
+    *skipped += enq - kd;
+    it += kd;
+    PB_HIP(ctx, hipMemcpyAsync(H.data(), Hd, sizeof(double) * (size_t)kd * m, hipMemcpyDeviceToHost, ctx->stream));
+    PB_HIP(ctx, hipMemcpyAsync(s.data(), sd, sizeof(double) * (size_t)kd, hipMemcpyDeviceToHost, ctx->stream));
+    PB_TRY(sync(ctx, "arnoldi"));
+    for (int i = kd - 1; i >= 0; --i) {
       double acc = s[i];
-      for (int j = i + 1; j < k; ++j) acc -= H[(size_t)i * m + j] * y[j];
+      for (int j = i + 1; j < kd; ++j) acc -= H[(size_t)i * m + j] * y[j];
       y[i] = acc / H[(size_t)i * m + i];
     }
-    PB_HIP(ctx, hipMemcpyAsync(ydev, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, ctx->stream));
-    k_axpy_multi<<<vb, kBlock, 0, ctx->stream>>>(M, prec ? Z : V, M, k, ydev, 1.0, x);
+    PB_HIP(ctx, hipMemcpyAsync(ydev, y.data(), sizeof(double) * kd, hipMemcpyHostToDevice, ctx->stream));
+    k_axpy_multi<<<vb, kBlock, 0, ctx->stream>>>(M, prec ? Z : V, M, kd, ydev, 1.0, x);
     PB_TRY(launch_ok(ctx, "update"));
     PB_TRY(op(x, r));
     k_residual<<<vb, kBlock, 0, ctx->stream>>>(M, b, r);
@@ -252,7 +344,7 @@ extern "C" pb_status pb_ibim_solve(pb_ctx* ctx, const pb_band* band, const doubl
   else pb_default_solve_opts(&opts);
   if (!atoms || n_atoms <= 0 || !p) return ctx->fail(PB_EINVAL, "pb_ibim_solve: NULL or empty input");
   if (!(opts.tol > 0.0) || !std::isfinite(opts.tol)) return ctx->fail(PB_EINVAL, "tolerance must be positive");
-  if (opts.max_iter < 1 || opts.restart < 1 || opts.restart > 2000) return ctx->fail(PB_EINVAL, "bad iteration limits");
+  if (opts.max_iter < 1 || opts.restart < 1 || opts.restart > kMaxRestart) return ctx->fail(PB_EINVAL, "bad iteration limits");
   if (opts.precision != PB_FP64 && opts.precision != PB_MIXED && opts.precision != PB_TREE)
     return ctx->fail(PB_EINVAL, "unknown precision");
   if (opts.precision != PB_FP64 && prm->reg_metric == PB_REG_TANGENT)
@@ -335,7 +427,10 @@ extern "C" pb_status pb_ibim_solve(pb_ctx* ctx, const pb_band* band, const doubl
     if (opts.precision == PB_FP64) {
       double res = 0.0;
       int it = 0;
-      PB_TRY(gmres(ctx, K, op64, prec, g, p, opts.tol * gnorm, 0.0, iter_budget, &it, &res));
+      int sk = 0;
+      PB_TRY(gmres(ctx, K, op64, prec, g, p, opts.tol * gnorm, 0.0, iter_budget, &it, &res, &sk));
+      n64 -= sk;
+      if (prec) nnn -= sk;
       iters += it;
       relres = res / gnorm;
       outer += 1;
@@ -347,7 +442,10 @@ extern "C" pb_status pb_ibim_solve(pb_ctx* ctx, const pb_band* band, const doubl
       // the treecode's); the residual below then decides whether a correction step is needed
       int it = 0;
       double res = 0.0;
-      PB_TRY(gmres(ctx, K, opmx, prec, g, p, 0.5 * opts.tol * gnorm, kInnerEta, iter_budget, &it, &res));
+      int sk = 0;
+      PB_TRY(gmres(ctx, K, opmx, prec, g, p, 0.5 * opts.tol * gnorm, kInnerEta, iter_budget, &it, &res, &sk));
+      nmx -= sk;
+      if (prec) nnn -= sk;
       used += it;
       ++steps;
     }
@@ -369,7 +467,11 @@ extern "C" pb_status pb_ibim_solve(pb_ctx* ctx, const pb_band* band, const doubl
       k_zero<<<vb, kBlock, 0, ctx->stream>>>(M, dx);
       int it = 0;
       double res = 0.0;
-      PB_TRY(gmres(ctx, K, opmx, prec, r, dx, 0.5 * opts.tol * gnorm, kInnerEta, iter_budget - used, &it, &res));
+      int sk = 0;
+      PB_TRY(gmres(ctx, K, opmx, prec, r, dx, 0.5 * opts.tol * gnorm, kInnerEta, iter_budget - used, &it, &res,
+                   &sk));
+      nmx -= sk;
+      if (prec) nnn -= sk;
       used += it;
       k_add<<<vb, kBlock, 0, ctx->stream>>>(M, dx, p);
       PB_TRY(launch_ok(ctx, "refine"));

@@ -245,7 +245,9 @@ __device__ __forceinline__ void sym64_item(const BandDev& b, const double* __res
 // Symmetric FP64 operator of one band: one block per work item.
 static __global__ void __attribute__((unused)) __launch_bounds__(kBlock)
     k_p2p_f64_sym(BandDev b, const double* __restrict__ wpsi, const double* __restrict__ wpsn, int n, int nsub,
-                  const int2* __restrict__ items, int n_items, KParams kp, double* __restrict__ partial) {
+                  const int2* __restrict__ items, int n_items, KParams kp, double* __restrict__ partial,
+                  const int* __restrict__ skip) {
+  if (skip && *skip) return;
   __shared__ Sym64Shared sh;
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     const int2 w = items[it];

@@ -11,9 +11,9 @@
 //   to j:  a1 += −(c1/r'³)(d·n_i) W_i − ((1 − E)/r') V_i,
 //          a2 += [W_i Q − c2 (d·n_j) V_i]/r'³,
 // with Q = (1 − a)(n_i·n_j) + (d·n_i)(d·n_j) g/r'² the weight-free K21 core, symmetric in
-// (i, j). Everything but the last products is shared: 46 FP32 operations and 2
-// transcendentals per unordered pair, 23 + 1 per ordered pair (36 + 2 for one direction at a
-// time). Records: A = (σ(x − c), V) and N = (n, W), two float4 per node.
+// (i, j); it is evaluated with g/r'² = E − 3(1 − a)/r'² and a = E(1 + r') as one FMA each.
+// Everything but the last products is shared: 43 FP32 operations and 2 transcendentals per
+// unordered pair, 21.5 + 1 per ordered pair (34 + 2 for one direction at a time). Records: A = (σ(x − c), V) and N = (n, W), two float4 per node.
 //
 // Work decomposition. The band is cut into chunks of C = 512·nsub nodes (nC chunks). One
 // work item is a chunk pair (Ic, Jc) with Ic ≤ Jc; the partial sums keep the chunked layout
@@ -61,13 +61,12 @@ __device__ __forceinline__ PairTerms pair_terms(const float4& ta, const float4& 
   const float r2 = r2_f32(ta.x, ta.y, ta.z, sa.x, sa.y, sa.z);
   float rinv = __builtin_amdgcn_rsqf(r2);
   if (kCheck && r2 < fp.rc2) rinv = 0.f;
-  float E = 1.f, Ez = 0.f, z = 0.f;
+  float E = 1.f, z = 0.f;
   if (kScreened) {
     z = r2 * rinv;
     E = __builtin_amdgcn_exp2f(fp.mlog2e * z);
-    Ez = E * z;
   }
-  const float a = E + Ez;
+  const float a = __fmaf_rn(E, z, E);  // E(1 + r')
   const float ri2 = rinv * rinv;
   PairTerms t;
   t.r3 = ri2 * rinv;
@@ -77,9 +76,9 @@ __device__ __forceinline__ PairTerms pair_terms(const float4& ta, const float4& 
   t.c2 = __fmaf_rn(-fp.th2, a, 1.f);
   if (kScreened) {
     const float nn = __fmaf_rn(tn.z, sn.z, __fmaf_rn(tn.y, sn.y, tn.x * sn.x));
-    const float g = __fmaf_rn(Ez, z, __fmaf_rn(3.f, a, -3.f));
+    const float gr = __fmaf_rn(__fmaf_rn(3.f, a, -3.f), ri2, E);  // g/r'² = E − 3(1 − a)/r'²
     t.f0r = __fmaf_rn(-E, rinv, rinv);
-    t.Q = __fmaf_rn((t.dnx * t.dny) * ri2, g, __fmaf_rn(-a, nn, nn));
+    t.Q = __fmaf_rn(t.dnx * t.dny, gr, __fmaf_rn(-a, nn, nn));
   } else {  // κ = 0: E = a = 1 and z = 0, so 1 − E = 0 and Q = 0
     t.f0r = 0.f;
     t.Q = 0.f;
@@ -278,7 +277,9 @@ template <bool kScreened>
 static __global__ void __attribute__((unused)) __launch_bounds__(kBlock)
     k_p2p_f32_sym(const float4* __restrict__ A, const float4* __restrict__ N,
                   const float4* __restrict__ box, int n, int nsub, const int2* __restrict__ items, int n_items,
-                  F32Params fp, double sig1, double sig2, double* __restrict__ partial) {
+                  F32Params fp, double sig1, double sig2, double* __restrict__ partial,
+                  const int* __restrict__ skip) {
+  if (skip && *skip) return;
   __shared__ SymShared sh;
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     const int2 w = items[it];

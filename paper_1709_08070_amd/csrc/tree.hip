@@ -93,7 +93,9 @@ __global__ void __launch_bounds__(kBlock) k_tree_gather(int n, const int* __rest
 template <int P1>
 __global__ void __launch_bounds__(kProxyBlock) k_proxy(const int4* __restrict__ items, const float4* __restrict__ box,
                                                        const float4* __restrict__ At, const float4* __restrict__ Nt,
-                                                       ChebNodes cn, double2* __restrict__ part) {
+                                                       ChebNodes cn, double2* __restrict__ part,
+                                                       const int* __restrict__ skip) {
+  if (skip && *skip) return;
   constexpr int P3 = P1 * P1 * P1;
   constexpr int kPer = (P3 + kProxyBlock - 1) / kProxyBlock;
   __shared__ float sL[kProxyTile][3][P1], sD[kProxyTile][3][P1];
@@ -221,7 +223,8 @@ __global__ void __launch_bounds__(kBatch) k_tree_far(const int2* __restrict__ ba
                                                      const float4* __restrict__ At, const float4* __restrict__ Mt,
                                                      const float4* __restrict__ Nt, const int* __restrict__ perm,
                                                      F32Params fp, int n, double sig1, double sig2,
-                                                     double* __restrict__ out) {
+                                                     double* __restrict__ out, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   const int2 bt = batch[blockIdx.x];
   const int t = bt.x + (int)threadIdx.x;
   const bool live = t < bt.y;
@@ -579,7 +582,8 @@ namespace {
 
 template <int P1>
 void launch_proxy(pb_ctx* ctx, const TreePlan& T, const ChebNodes& cn) {
-  k_proxy<P1><<<(unsigned)T.n_items, kProxyBlock, 0, ctx->stream>>>(T.items, T.box, T.At, T.Nt, cn, T.part);
+  k_proxy<P1><<<(unsigned)T.n_items, kProxyBlock, 0, ctx->stream>>>(T.items, T.box, T.At, T.Nt, cn, T.part,
+                                                                        ctx->skip);
 }
 
 void launch_tree(pb_ctx* ctx, const TreePlan& T, bool screened, const F32Params& fp, double sig1, double sig2) {
@@ -601,7 +605,8 @@ void launch_tree(pb_ctx* ctx, const TreePlan& T, bool screened, const F32Params&
   }
   auto far = screened ? k_tree_far<true> : k_tree_far<false>;
   far<<<(unsigned)T.n_batch, kBatch, 0, ctx->stream>>>(T.batch, T.dir_ptr, T.dir_rng, T.app_ptr, T.app_cl, P3, T.PX,
-                                                        T.PM, T.At, T.Mt, T.Nt, T.perm, fp, (int)T.n, sig1, sig2, T.far);
+                                                        T.PM, T.At, T.Mt, T.Nt, T.perm, fp, (int)T.n, sig1, sig2, T.far,
+                                                        ctx->skip);
 }
 
 }  // namespace

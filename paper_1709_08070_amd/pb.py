@@ -177,8 +177,9 @@ class Context:
         except Exception:
             pass
 
-    def set_timing(self, on: bool):
-        self.check(lib.pb_set_timing(self.handle, int(on)))
+    def set_timing(self, level):
+        """0/False off, 1/True every kernel family, 2 the far-field families only."""
+        self.check(lib.pb_set_timing(self.handle, int(level)))
 
     def kernel_time(self, name: str):
         ms, cnt = C.c_double(), C.c_int64()
