@@ -150,9 +150,35 @@ def test_born_solve_and_energy(pbm, ctx, born):
     assert 0.0288 <= (en.g_pol - Gs) / Gs <= 0.0576
 
 
-def test_born_solve_mixed(pbm, ctx, born):
-    say("case: Born solve mixed tol 1e-8")
-    opts = pbm.solve_opts(tol=1e-8, precision=pbm.PB_MIXED)
+@pytest.mark.parametrize("restart", [3, 7])
+def test_born_solve_short_restarts(pbm, ctx, born, restart):
+    """Restart cycles that end mid-way on the residual estimate: the device-side Givens step
+    and the host's one-step lookahead (a step enqueued after convergence does no work and is
+    not counted). Against the oracle's GMRES with the same restart length: the solution, and
+    the Arnoldi step count within one (CGS2 here, MGS there); operator applications =
+    steps + one residual per cycle + the initial residual."""
+    say(f"case: Born solve fp64 tol 1e-10 restart {restart}")
+    atoms, nodes = born["atoms"], born["band"].table()
+    opts = pbm.solve_opts(tol=1e-10, precision=pbm.PB_FP64, restart=restart, max_iter=400)
+    p, st = pbm.pb_ibim_solve(ctx, born["band"], born["at"], born["prm"], opts)
+    assert st.converged and st.true_relres <= 1e-10
+    og = oracle.rhs(nodes, atoms, born["oprm"])
+    ox, it, rr, ok = oracle.gmres(nodes, born["oprm"], og, tol=1e-10, max_iter=400, restart=restart)
+    assert ok
+    say(f"  iterations {st.iters} (oracle {it}), FP64 applications {st.matvecs_fp64}")
+    assert abs(st.iters - it) <= 1
+    cycles = st.matvecs_fp64 - st.iters - 1  # one true residual per cycle
+    assert math.ceil(st.iters / restart) <= cycles <= math.ceil(st.iters / restart) + 1
+    assert np.linalg.norm(p.cpu().numpy() - ox) / np.linalg.norm(ox) < 1e-8
+    # a second solve on the same context repeats the first bit for bit
+    p2, st2 = pbm.pb_ibim_solve(ctx, born["band"], born["at"], born["prm"], opts)
+    assert st2.iters == st.iters and np.array_equal(p.cpu().numpy(), p2.cpu().numpy())
+
+
+@pytest.mark.parametrize("restart", [100, 5])
+def test_born_solve_mixed(pbm, ctx, born, restart):
+    say(f"case: Born solve mixed tol 1e-8 restart {restart}")
+    opts = pbm.solve_opts(tol=1e-8, precision=pbm.PB_MIXED, restart=restart, max_iter=400)
     p, st = pbm.pb_ibim_solve(ctx, born["band"], born["at"], born["prm"], opts)
     assert st.converged and st.true_relres <= 1e-8 and st.matvecs_mixed > 0
     en = pbm.pb_solvation_energy(ctx, born["band"], born["at"], born["prm"], p)
