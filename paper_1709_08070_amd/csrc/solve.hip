@@ -43,16 +43,22 @@ struct GivensArgs {
 // is set, later steps leave everything as it is. One thread.
 __device__ void givens_step(const GivensArgs& g) {
   const int k = g.k, m = g.m;
-  double* H = g.H;
+  double* __restrict__ H = g.H;
+  const double* __restrict__ hc = g.hcol;
+  const double* __restrict__ cs = g.cs;
+  const double* __restrict__ sn = g.sn;
   if (g.state[0]) return;
-  const double hn = g.hcol[2 * (m + 1)];
-  for (int i = 0; i <= k; ++i) H[(size_t)i * m + k] = g.hcol[i] + g.hcol[(m + 1) + i];
+  const double hn = hc[2 * (m + 1)];
+  // rotation i acts on rows i (already rotated by the earlier ones: `a`) and i + 1 (still
+  // the raw coefficient); the loads do not depend on the chain and run ahead of it
+  double a = hc[0] + hc[m + 1];
+#pragma unroll 4
   for (int i = 0; i < k; ++i) {
-    const double a = H[(size_t)i * m + k], b = H[(size_t)(i + 1) * m + k];
-    H[(size_t)i * m + k] = g.cs[i] * a + g.sn[i] * b;
-    H[(size_t)(i + 1) * m + k] = -g.sn[i] * a + g.cs[i] * b;
+    const double b = hc[i + 1] + hc[(m + 1) + i + 1];
+    const double c = cs[i], s = sn[i];
+    H[(size_t)i * m + k] = c * a + s * b;
+    a = -s * a + c * b;
   }
-  const double a = H[(size_t)k * m + k];
   const double den = sqrt(a * a + hn * hn);
   const double c = den > 0.0 ? a / den : 1.0, sg = den > 0.0 ? hn / den : 0.0;
   g.cs[k] = c;
