@@ -25,6 +25,7 @@ paper_1709_08070_amd.learn`), or one trained in-process with --learned-train N.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -52,6 +53,38 @@ WEIGHTS = os.path.join(ROOT, "paper_1709_08070_amd", "weights", "learned_h0.5.np
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def one_thread_rate(oracle, nodes, oprm, x, cores: int):
+    """The oracle's pair rate on one host thread: 256 operator rows against every source,
+    with the OpenMP runtime the oracle library runs on set to one thread for the sample."""
+    try:
+        gomp = ctypes.CDLL("libgomp.so.1")
+    except OSError:
+        return None
+    import numpy as np
+
+    rows = np.arange(min(len(nodes), 256))
+    gomp.omp_set_num_threads(1)
+    try:
+        t1 = time.perf_counter()
+        oracle.matvec_rows(nodes, oprm, x, rows)
+        dt = time.perf_counter() - t1
+    finally:
+        gomp.omp_set_num_threads(cores)
+    return {"value": len(rows) * float(len(nodes)) / dt, "unit": "pair-interactions/s", "cores": 1,
+            "sample": f"{len(rows)} operator rows x {len(nodes)} sources, {dt:.2f} s"}
 
 
 def kernel_source_hash(path: str) -> str:
@@ -498,7 +531,8 @@ def main():
         cpu = {"value": reps * float(n) * float(n) / t_cpu, "unit": "pair-interactions/s", "cores": cores,
                "kind": "oracle",
                "sample": f"{reps} full FP64 operator applications (matvec) on the same {n}-node band, "
-                         f"{t_cpu:.1f} s"}
+                         f"{t_cpu:.1f} s",
+               "cpu_model": cpu_model(), "one_thread": one_thread_rate(oracle, nodes, oprm, x, cores)}
 
     out = {
         "metric": METRIC, "value": value, "unit": "pair-interactions/s", "n_gpus": 1,
