@@ -175,6 +175,21 @@ def test_born_solve_short_restarts(pbm, ctx, born, restart):
     assert st2.iters == st.iters and np.array_equal(p.cpu().numpy(), p2.cpu().numpy())
 
 
+def test_born_solve_iteration_budget(pbm, ctx, born):
+    """An unreachable tolerance: the solve stops at exactly max_iter Arnoldi steps (cycles of
+    4, 4 and 2 here; no step past the budget is enqueued), reports PB_ENOCONV and still
+    returns its iterate and statistics; then the same context solves normally."""
+    say("case: Born solve fp64, tol 1e-15, restart 4, max_iter 10")
+    opts = pbm.solve_opts(tol=1e-15, precision=pbm.PB_FP64, restart=4, max_iter=10)
+    p, st = pbm.pb_ibim_solve(ctx, born["band"], born["at"], born["prm"], opts, allow_noconv=True)
+    assert not st.converged and st.iters == 10
+    assert st.matvecs_fp64 == 10 + 1 + 3  # steps + initial residual + one residual per cycle
+    assert np.all(np.isfinite(p.cpu().numpy())) and st.true_relres < 1e-2
+    opts = pbm.solve_opts(tol=1e-10, precision=pbm.PB_FP64)
+    _, st2 = pbm.pb_ibim_solve(ctx, born["band"], born["at"], born["prm"], opts)
+    assert st2.converged and st2.true_relres <= 1e-10
+
+
 @pytest.mark.parametrize("restart", [100, 5])
 def test_born_solve_mixed(pbm, ctx, born, restart):
     say(f"case: Born solve mixed tol 1e-8 restart {restart}")
