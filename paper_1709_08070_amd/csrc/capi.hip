@@ -271,8 +271,6 @@ void pb_destroy(pb_ctx* ctx) {
     (void)hipEventDestroy(e.second);
   }
   for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
-  for (auto e : ctx->step_ev)
-    if (e) (void)hipEventDestroy(e);
   if (ctx->host_state) (void)hipHostFree(ctx->host_state);
   if (ctx->batch_stream) {
     (void)hipStreamSynchronize(ctx->batch_stream);

@@ -131,8 +131,8 @@ struct pb_ctx {
   // step enqueued after the test has been met finds the flag set and does no work.
   // nullptr outside such a cycle.
   const int* skip = nullptr;
-  int* host_state = nullptr;      // pinned host copy of the per-step GMRES state (2 ints per step)
-  hipEvent_t step_ev[2] = {};     // completion of the last two enqueued Arnoldi steps
+  int* host_state = nullptr;      // pinned host slots of the per-step GMRES state (2 ints per step)
+  int* host_state_dev = nullptr;  // the same memory as the device addresses it
   // status of the last allocation/launch
   pb_status fail(pb_status s, const char* fmt, ...);
 };

@@ -33,6 +33,7 @@ struct GivensArgs {
   double *H, *cs, *sn, *s;
   double tol_abs;
   int* state;
+  int* host_out;  // the step's slot in pinned host memory: state after the step
 };
 
 // Arnoldi column k into the QR factor of the Hessenberg matrix (row-major, (m+1) × m):
@@ -47,7 +48,11 @@ __device__ void givens_step(const GivensArgs& g) {
   const double* __restrict__ hc = g.hcol;
   const double* __restrict__ cs = g.cs;
   const double* __restrict__ sn = g.sn;
-  if (g.state[0]) return;
+  if (g.state[0]) {  // a step after the test was met: report the state unchanged
+    g.host_out[0] = g.state[0];
+    g.host_out[1] = g.state[1];
+    return;
+  }
   const double hn = hc[2 * (m + 1)];
   // rotation i acts on rows i (already rotated by the earlier ones: `a`) and i + 1 (still
   // the raw coefficient); the loads do not depend on the chain and run ahead of it
@@ -68,8 +73,11 @@ __device__ void givens_step(const GivensArgs& g) {
   const double sk = g.s[k];
   g.s[k + 1] = -sg * sk;
   g.s[k] = c * sk;
+  const int done = fabs(g.s[k + 1]) <= g.tol_abs || !(hn > 0.0);
   g.state[1] = k + 1;
-  if (fabs(g.s[k + 1]) <= g.tol_abs || !(hn > 0.0)) g.state[0] = 1;
+  if (done) g.state[0] = 1;
+  g.host_out[0] = done;
+  g.host_out[1] = k + 1;
 }
 
 // partial[q·nb + block] = Σ_{e in block's stride} w[e]·V[q][e], q < k, in groups of 8
@@ -204,15 +212,36 @@ pb_status norm2(pb_ctx* ctx, Krylov& K, const double* v, double* out) {
   return sync(ctx, "norm");
 }
 
-// Sets up the pinned host slots and events through which GMRES reads each step's state.
+// Sets up the pinned host slots through which GMRES reads each step's state.
 pb_status step_sync_init(pb_ctx* ctx) {
   if (!ctx->host_state) {
     void* h = nullptr;
-    PB_HIP(ctx, hipHostMalloc(&h, sizeof(int) * 2 * kMaxRestart, hipHostMallocDefault));
+    // coherent and mapped: the Givens step writes each step's state straight into it
+    PB_HIP(ctx, hipHostMalloc(&h, sizeof(int) * 2 * kMaxRestart, hipHostMallocCoherent | hipHostMallocMapped));
     ctx->host_state = (int*)h;
+    void* d = nullptr;
+    PB_HIP(ctx, hipHostGetDevicePointer(&d, h, 0));
+    ctx->host_state_dev = (int*)d;
   }
-  for (auto& e : ctx->step_ev)
-    if (!e) PB_HIP(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  return PB_OK;
+}
+
+// Waits until the Givens step of Arnoldi step k has written its slot (the host set it to −1
+// before enqueuing the step). Polling the pinned memory puts no marker into the stream (an
+// event record costs a few microseconds of idle GPU per step); the stream is queried now and
+// then so that a device error, or a stream that drained without writing, ends the wait.
+pb_status wait_slot(pb_ctx* ctx, const volatile int* hs, int k) {
+  for (unsigned spin = 1; hs[2 * k] < 0; ++spin) {
+    if ((spin & 255u) == 0u) {
+      const hipError_t e = hipStreamQuery(ctx->stream);
+      if (e == hipSuccess) {
+        if (hs[2 * k] >= 0) break;
+        return ctx->fail(PB_EDEVICE, "GMRES: step %d ended without reporting its state", k);
+      }
+      if (e != hipErrorNotReady) return ctx->fail(PB_EDEVICE, "GMRES step %d: %s", k, hipGetErrorString(e));
+    }
+    __builtin_ia32_pause();
+  }
   return PB_OK;
 }
 
@@ -248,6 +277,7 @@ pb_status gmres(pb_ctx* ctx, Krylov& K, const OpFn& op, const OpFn* prec, const 
   if (!V || !r || !ydev || !Hd || !gv || !state || (prec && !Z)) return PB_ENOMEM;
   PB_TRY(step_sync_init(ctx));
   double *cs = gv, *sn = gv + m, *sd = gv + 2 * m;
+  volatile int* hs = ctx->host_state;  // step slots, written by the device (k_dots_finish)
   const unsigned vb = vec_blocks(M), db = dot_blocks(M);
   std::vector<double> H((size_t)(m + 1) * m, 0.0), s(m + 1), y(m);
   PB_TRY(op(x, r));
@@ -275,6 +305,7 @@ pb_status gmres(pb_ctx* ctx, Krylov& K, const OpFn& op, const OpFn* prec, const 
       ctx->skip = state;
       for (int k = 0; k < steps; ++k) {
         mark = ctx->pending.size();
+        hs[2 * k] = -1;
         double* w = V + (size_t)(k + 1) * M;
         if (prec) {
           PB_TRY((*prec)(V + (size_t)k * M, Z + (size_t)k * M));
@@ -291,24 +322,21 @@ pb_status gmres(pb_ctx* ctx, Krylov& K, const OpFn& op, const OpFn* prec, const 
             k_dots_finish<<<k + 1, kBlock, 0, ctx->stream>>>(K.partial, (int)db, hv, 0, 0, GivensArgs{});
             k_axpy_multi<<<vb, kBlock, 0, ctx->stream>>>(M, V, M, k + 1, hv, -1.0, w);
           }
-          const GivensArgs ga{k, m, K.hcol, Hd, cs, sn, sd, tol_abs, state};
+          const GivensArgs ga{k, m, K.hcol, Hd, cs, sn, sd, tol_abs, state, ctx->host_state_dev + 2 * k};
           k_dots<<<db, kBlock, 0, ctx->stream>>>(M, w, 0, 1, w, K.partial);
           k_dots_finish<<<1, kBlock, 0, ctx->stream>>>(K.partial, (int)db, K.hcol + 2 * (m + 1), 1, 1, ga);
           k_scale_pos<<<vb, kBlock, 0, ctx->stream>>>(M, K.hcol + 2 * (m + 1), w);
         }
         PB_TRY(launch_ok(ctx, "arnoldi"));
-        PB_HIP(ctx, hipMemcpyAsync(ctx->host_state + 2 * k, state, 2 * sizeof(int), hipMemcpyDeviceToHost,
-                                   ctx->stream));
-        PB_HIP(ctx, hipEventRecord(ctx->step_ev[k & 1], ctx->stream));
         if (k >= 1) {
-          PB_HIP(ctx, hipEventSynchronize(ctx->step_ev[(k - 1) & 1]));
-          if (ctx->host_state[2 * (k - 1)]) break;  // step k − 1 met the test; step k did nothing
+          PB_TRY(wait_slot(ctx, hs, k - 1));
+          if (hs[2 * (k - 1)]) break;  // step k − 1 met the test; step k did nothing
         }
       }
     }
     PB_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    const int kd = ctx->host_state[2 * (enq - 1) + 1];  // steps taken
-    early = ctx->host_state[2 * (enq - 1)] != 0;
+    const int kd = hs[2 * (enq - 1) + 1];  // steps taken
+    early = hs[2 * (enq - 1)] != 0;
     if (kd < 1 || kd > enq) return ctx->fail(PB_EDEVICE, "GMRES: inconsistent step count %d of %d", kd, enq);
     if (enq > kd) drop_timers(ctx, mark);  // the last step was skipped
     *skipped += enq - kd;
