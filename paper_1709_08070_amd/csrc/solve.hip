@@ -81,10 +81,11 @@ __device__ void givens_step(const GivensArgs& g) {
 }
 
 // partial[q·nb + block] = Σ_{e in block's stride} w[e]·V[q][e], q < k, in groups of 8
-// vectors so that w is read once per group.
-__global__ void __launch_bounds__(kBlock) k_dots(int64_t M, const double* __restrict__ V, int64_t ldv, int k,
-                                                 const double* __restrict__ w, double* __restrict__ partial) {
-  __shared__ double red[kGroup][kBlock];
+// vectors so that w is read once per group. The block's elements are e = block·kBlock + tid
+// + i·nb·kBlock.
+__device__ __forceinline__ void block_dots(int64_t M, const double* __restrict__ V, int64_t ldv, int k,
+                                           const double* __restrict__ w, double* __restrict__ partial,
+                                           double (*red)[kBlock]) {
   for (int q0 = 0; q0 < k; q0 += kGroup) {
     double acc[kGroup];
 #pragma unroll
@@ -108,6 +109,29 @@ __global__ void __launch_bounds__(kBlock) k_dots(int64_t M, const double* __rest
     if (threadIdx.x < nq) partial[(int64_t)(q0 + threadIdx.x) * gridDim.x + blockIdx.x] = red[threadIdx.x][0];
     __syncthreads();
   }
+}
+
+__global__ void __launch_bounds__(kBlock) k_dots(int64_t M, const double* __restrict__ V, int64_t ldv, int k,
+                                                 const double* __restrict__ w, double* __restrict__ partial) {
+  __shared__ double red[kGroup][kBlock];
+  block_dots(M, V, ldv, k, w, partial, red);
+}
+
+// One Gram–Schmidt update and the next reduction in one launch: w[e] −= Σ_q c[q]·V[q][e]
+// (q < k) over the block's elements, then the partial sums of w·V[q] (q < k; kd = k) or of w·w
+// (kd = 1, V = w, ldv = 0). Each block reads back only the elements it wrote itself, so no
+// grid-wide synchronization is needed between the two phases.
+__global__ void __launch_bounds__(kBlock) k_axpy_dots(int64_t M, const double* __restrict__ V, int64_t ldv, int k,
+                                                      const double* __restrict__ c, double* __restrict__ w,
+                                                      int norm_only, double* __restrict__ partial) {
+  __shared__ double red[kGroup][kBlock];
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < M; e += (int64_t)gridDim.x * kBlock) {
+    double s = 0.0;
+    for (int q = 0; q < k; ++q) s += c[q] * V[(int64_t)q * ldv + e];
+    w[e] -= s;
+  }
+  if (norm_only) block_dots(M, w, 0, 1, w, partial, red);
+  else block_dots(M, V, ldv, k, w, partial, red);
 }
 
 // out[q] = Σ_b partial[q·nb + b] (one block per q, fixed tree); if sqrt_out, out[q] =
@@ -316,14 +340,15 @@ pb_status gmres(pb_ctx* ctx, Krylov& K, const OpFn& op, const OpFn* prec, const 
         ++enq;
         {
           Scope t(ctx, "gmres");
-          for (int pass = 0; pass < 2; ++pass) {
-            double* hv = K.hcol + pass * (m + 1);
-            k_dots<<<db, kBlock, 0, ctx->stream>>>(M, V, M, k + 1, w, K.partial);
-            k_dots_finish<<<k + 1, kBlock, 0, ctx->stream>>>(K.partial, (int)db, hv, 0, 0, GivensArgs{});
-            k_axpy_multi<<<vb, kBlock, 0, ctx->stream>>>(M, V, M, k + 1, hv, -1.0, w);
-          }
+          // CGS2: h1 = Vᵀw, w −= V h1, h2 = Vᵀw, w −= V h2, ‖w‖; each update is fused with
+          // the reduction that follows it
+          double *h1 = K.hcol, *h2 = K.hcol + (m + 1);
+          k_dots<<<db, kBlock, 0, ctx->stream>>>(M, V, M, k + 1, w, K.partial);
+          k_dots_finish<<<k + 1, kBlock, 0, ctx->stream>>>(K.partial, (int)db, h1, 0, 0, GivensArgs{});
+          k_axpy_dots<<<db, kBlock, 0, ctx->stream>>>(M, V, M, k + 1, h1, w, 0, K.partial);
+          k_dots_finish<<<k + 1, kBlock, 0, ctx->stream>>>(K.partial, (int)db, h2, 0, 0, GivensArgs{});
+          k_axpy_dots<<<db, kBlock, 0, ctx->stream>>>(M, V, M, k + 1, h2, w, 1, K.partial);
           const GivensArgs ga{k, m, K.hcol, Hd, cs, sn, sd, tol_abs, state, ctx->host_state_dev + 2 * k};
-          k_dots<<<db, kBlock, 0, ctx->stream>>>(M, w, 0, 1, w, K.partial);
           k_dots_finish<<<1, kBlock, 0, ctx->stream>>>(K.partial, (int)db, K.hcol + 2 * (m + 1), 1, 1, ga);
           k_scale_pos<<<vb, kBlock, 0, ctx->stream>>>(M, K.hcol + 2 * (m + 1), w);
         }
