@@ -283,10 +283,10 @@ struct SkipGuard {
 // update is x += Z y; the preconditioner may change from step to step (it may be nonlinear).
 //
 // The Givens rotations and the convergence test run on the device (givens_step, after the
-// norm that ends each step), and the host
-// enqueues step k before it reads the test of step k − 1, so the GPU never waits for the
-// host inside a cycle. A step enqueued after the test was met finds the operator's skip flag
-// set: its heavy kernels return at once and the step is not counted (*skipped counts them).
+// norm that ends each step), and the host enqueues step k before it reads the test of step
+// k − 1, so the GPU never waits for the host inside a cycle. A step enqueued after the test
+// was met finds the operator's skip flag set: its heavy kernels return at once and the step
+// is not counted (*skipped counts them).
 pb_status gmres(pb_ctx* ctx, Krylov& K, const OpFn& op, const OpFn* prec, const double* b, double* x, double tol_abs,
                 double rel, int max_iter, int* iters, double* res_out, int* skipped) {
   const int64_t M = K.M;
