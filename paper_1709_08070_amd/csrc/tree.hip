@@ -17,10 +17,13 @@
 // G0 − θ1Gκ and G0 − Gκ, K12 = G0 − Gκ, K22 as the target-normal derivative of G0 − θ2Gκ)
 // applied to the interpolated density. y1 = σS1 and y2 = σ²S2 as for the dense FP32 kernel.
 //
-// Target batches are runs of sibling leaves of at most kBatch nodes (each inside one parent
-// cell, so its radius stays small; consecutive Morton runs can straddle a jump of the curve
-// and then interpolate almost nothing). For each batch the host walks the tree once: a cluster with more than (p+1)³ sources goes to the batch's
-// proxy list when (r_B + r_C) < θ·dist and the two balls are at least 1.01·r_c apart (so it
+// Target batches are runs of consecutive leaves in Morton order of at most kBatch nodes whose
+// union box has a radius of at most kPackRadius times that of their largest leaf: a run that
+// straddles a jump of the curve would have a wide box and interpolate almost nothing, while
+// neighbouring leaves of different parents fill the wave's lanes (a batch costs one wave
+// whatever its size). On bands too small to give every compute unit kMinWavesPerCU such
+// batches, runs of sibling leaves (smaller, more waves) are used instead. For each batch the host walks the tree once: a cluster with more than
+// (p+1)³ sources goes to the batch's proxy list when (r_B + r_C) < θ·dist and the two balls are at least 1.01·r_c apart (so it
 // holds no near pair); leaves that fail the test go to the direct list, evaluated with the
 // dense FP32 pair function (near pairs excluded by the shared FP32 predicate, the FP64 near
 // field supplies them). Lists, ranges and boxes are built once per band; each application
@@ -41,6 +44,8 @@ namespace pb {
 namespace {
 
 constexpr int kBatch = 64;        // targets per batch = lanes of the far-field wave
+constexpr double kPackRadius = 4.0;  // batch box radius / largest leaf radius in the batch
+constexpr int kMinWavesPerCU = 16;   // packed batches per compute unit below which siblings are used
 constexpr int kLeaf = 64;         // source leaves hold at most this many nodes
 static_assert(kLeaf <= kBatch, "a leaf fits one target batch");
 constexpr int kProxyChunk = 2048; // sources per proxy work item
@@ -393,11 +398,51 @@ pb_status build_host_tree(pb_ctx* ctx, const pb_band* band, const MixedPlan& P, 
     nodes[td.idx].n_kids = nk;
     for (int k = nk - 1; k >= 0; --k) todo.push_back(Todo{first + k, td.level + 1});
   }
-  // target batches: runs of sibling leaves (in child order) of at most kBatch nodes, so that
-  // every batch lies inside one parent cell; a tree that is a single leaf is one batch
+  // target batches: the leaves in Morton order (depth first, children in octant order),
+  // packed greedily into runs of at most kBatch nodes whose union box stays within
+  // kPackRadius times the radius of the run's largest leaf. Packing trades waves for fuller
+  // waves; when it would leave fewer than kMinWavesPerCU batches per compute unit, the
+  // batches are the runs of sibling leaves instead (more, smaller waves fill the GPU better).
   std::vector<int2>& batch = H.batch;
   batch.clear();
   {
+    int cb = -1, ce = -1;
+    double blo[3] = {}, bhi[3] = {}, maxr = 0.0;
+    std::vector<int> st{0};
+    while (!st.empty()) {
+      const HNode& nd = nodes[st.back()];
+      st.pop_back();
+      if (nd.n_kids > 0) {
+        for (int q = nd.n_kids - 1; q >= 0; --q) st.push_back(nd.first_kid + q);
+        continue;
+      }
+      if (cb >= 0 && nd.e - cb <= kBatch) {
+        double ulo[3], uhi[3], r2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+          ulo[a] = std::min(blo[a], nd.lo[a]);
+          uhi[a] = std::max(bhi[a], nd.hi[a]);
+          r2 += 0.25 * (uhi[a] - ulo[a]) * (uhi[a] - ulo[a]);
+        }
+        const double mr = std::max(maxr, nd.r);
+        if (std::sqrt(r2) <= kPackRadius * mr) {
+          ce = nd.e;
+          std::copy(ulo, ulo + 3, blo);
+          std::copy(uhi, uhi + 3, bhi);
+          maxr = mr;
+          continue;
+        }
+      }
+      if (cb >= 0) batch.push_back(make_int2(cb, ce));
+      cb = nd.b;
+      ce = nd.e;
+      std::copy(nd.lo, nd.lo + 3, blo);
+      std::copy(nd.hi, nd.hi + 3, bhi);
+      maxr = nd.r;
+    }
+    if (cb >= 0) batch.push_back(make_int2(cb, ce));
+  }
+  if ((int64_t)batch.size() < (int64_t)kMinWavesPerCU * ctx->n_cu) {  // sibling runs
+    batch.clear();
     if (nodes[0].n_kids == 0) batch.push_back(make_int2(0, n));
     std::vector<int> st{0};
     while (!st.empty()) {

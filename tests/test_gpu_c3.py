@@ -6,7 +6,8 @@ size rests on outputs it computes one by one from the GPU's own inputs:
   * band compaction of the GPU level set by the oracle: node order and indices bit-exact,
     node values to 1e-12;
   * 64 sampled operator rows (FP64 path: 1e-10 of max|y|; mixed path: 1e-5 relative, with
-    the autotuner's far-field kernel and with the symmetric and one-directional ones forced);
+    the autotuner's far-field kernel and with the symmetric and one-directional ones forced;
+    the treecode operator with its packed target batches: 3e-5 relative);
   * the mixed solve to 1e-6: its residual on the sampled rows recomputed by the oracle
     (1e-5 relative), and the energy of its solution recomputed by the oracle (1e-10).
 The level-set kernels are compared node by node with the oracle at the smaller sizes of
@@ -91,6 +92,15 @@ def test_globule5000_sampled(pbm):
         relk = np.linalg.norm(gk - ref) / np.linalg.norm(ref)
         say(f"far-field kernel {cfg}: sampled rel err {relk:.3e}")
         assert relk < 1e-5
+    # the treecode operator at this size: target batches packed across parent cells (a band
+    # this large gives every compute unit more than 16 of them); degree 4, θ = 0.6
+    yt = pbm.pb_ibim_matvec(ctx, band, prm, pt, pbm.PB_TREE).cpu().numpy()
+    info = ctx.tree_info()
+    gt = np.concatenate([yt[rows], yt[n + rows]])
+    relt = np.linalg.norm(gt - ref) / np.linalg.norm(ref)
+    say(f"treecode: {info['batches']} batches (mean {n / info['batches']:.1f} targets), sampled rel err {relt:.3e}")
+    assert n / info["batches"] > 45
+    assert relt < 3e-5
     # mixed solve to 1e-6, checked by the oracle on the sampled rows and through the energy
     sol, st = pbm.pb_ibim_solve(ctx, band, at, prm, pbm.solve_opts(tol=1e-6, precision=pbm.PB_MIXED))
     say(f"mixed solve: iters={st.iters} outer={st.outer} relres={st.true_relres:.2e} {st.t_total_s:.1f}s")
