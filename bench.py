@@ -496,19 +496,23 @@ def main():
         if ttsol.get("mixed_s") and ttsol.get("learned_mixed_s"):
             ttsol["speedup_learned_mixed_vs_mixed"] = ttsol["mixed_s"] / ttsol["learned_mixed_s"]
         if any("tree" in x for x in legs):
-            ctx.set_timing(True)
-            ms0, c0 = ctx.kernel_time("tree_f32")
-            for _ in range(3):
-                pb.pb_ibim_matvec(ctx, band, prm, p, pb.PB_TREE)
+            # the treecode far field as it runs inside a solve (one more plain treecode solve,
+            # events around the far-field launches only); isolated applications would each
+            # rebuild the plan and start on an idle, clocked-down GPU
+            ctx.set_timing(2)
+            q = torch.zeros_like(p)
+            pb.pb_ibim_solve(ctx, band, at, prm, pb.solve_opts(tol=args.tol, precision=pb.PB_TREE), q)
             ms1, c1 = ctx.kernel_time("tree_f32")
-            ctx.set_timing(False)
+            msf, cf = ctx.kernel_time("tree_fine_f32")
+            ctx.set_timing(0)
             info = ctx.tree_info()
-            far_ms = (ms1 - ms0) / max(c1 - c0, 1)
+            far_ms = ms1 / max(c1, 1)
             # algorithmic work: 61 FLOP per direct pair (the dense definition), 36 per
             # target-proxy interaction; the far-field kernels are bound by the FP32 VALUs
             flops = 61.0 * info["direct_pairs"] + 36.0 * info["proxy_interactions"]
             ttsol["tree_operator"] = dict(
-                degree=prm.tree_degree, theta=prm.tree_theta, far_ms=far_ms,
+                degree=prm.tree_degree, theta=prm.tree_theta, far_ms=far_ms, applications=c1,
+                fine_far_ms=msf / cf if cf else None, fine_applications=cf,
                 algorithmic_tflops=flops / (far_ms * 1e-3) / 1e12 if far_ms > 0 else None,
                 dense_equivalent_pairs_per_s=float(n) * n / (far_ms * 1e-3) if far_ms > 0 else None,
                 mean_batch=n / max(info["batches"], 1), **info)

@@ -290,9 +290,11 @@ pb_status pb_nn_geometry(pb_ctx* ctx, const pb_band* band, int* nbr_host, float*
 
 /* Device time (ms) and launch count of one kernel family since the last reset, measured
    with HIP events around each launch on the context stream when timing is enabled.
-   name: "p2p_f32", "p2p_f64", "tree_f32", "near_f64", "reduce", "gmres", "levelset", "band",
-   "rhs", "energy", "nn". pb_set_timing: enable = 0 off, 1 every family, 2 the far-field
-   families only ("p2p_f32", "p2p_f64", "tree_f32"; each event pair adds a few microseconds
+   name: "p2p_f32", "p2p_f64", "tree_f32" (the treecode far field: proxies and k_tree_far),
+   "tree_fine_f32" (the same for the fine residual treecode of PB_TREE solves on large bands),
+   "near_f64", "reduce", "gmres", "levelset", "band", "rhs", "energy", "nn". pb_set_timing:
+   enable = 0 off, 1 every family, 2 the far-field families only ("p2p_f32", "p2p_f64",
+   "tree_f32", "tree_fine_f32"; each event pair adds a few microseconds
    between launches, so a timed run measures only what it reports). It synchronizes the
    context stream and resets the counters; other values give PB_EINVAL. */
 pb_status pb_set_timing(pb_ctx* ctx, int enable);

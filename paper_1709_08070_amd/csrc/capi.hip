@@ -83,7 +83,8 @@ static hipEvent_t get_event(pb_ctx* ctx) {
 // The far-field families: what timing level 2 measures (events around every other launch
 // would add their own gaps to a timed run).
 static bool far_family(const char* n) {
-  return !std::strcmp(n, "p2p_f32") || !std::strcmp(n, "p2p_f64") || !std::strcmp(n, "tree_f32");
+  return !std::strcmp(n, "p2p_f32") || !std::strcmp(n, "p2p_f64") || !std::strcmp(n, "tree_f32") ||
+         !std::strcmp(n, "tree_fine_f32");
 }
 
 Scope::Scope(pb_ctx* c, const char* n)

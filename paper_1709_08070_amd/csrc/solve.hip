@@ -419,7 +419,7 @@ extern "C" pb_status pb_ibim_solve(pb_ctx* ctx, const pb_band* band, const doubl
   PB_TRY(sync(ctx, "pb_ibim_solve"));
   auto matvec_ms = [&]() {
     double tm = 0.0;
-    for (const char* nm : {"p2p_f64", "p2p_f32", "tree_f32", "near_f64", "reduce"}) {
+    for (const char* nm : {"p2p_f64", "p2p_f32", "tree_f32", "tree_fine_f32", "near_f64", "reduce"}) {
       auto itt = ctx->timers.find(nm);
       if (itt != ctx->timers.end()) tm += itt->second.ms;
     }

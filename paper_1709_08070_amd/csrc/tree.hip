@@ -671,7 +671,7 @@ pb_status matvec_tree(pb_ctx* ctx, const pb_band* band, const Derived& d, const 
   const F32Params fp = f32params(d, P.sigma);
   const bool screened = d.kappa > 0.0;
   {
-    Scope t(ctx, "tree_f32");
+    Scope t(ctx, &T == &ctx->tree_fine ? "tree_fine_f32" : "tree_f32");
     launch_tree(ctx, T, screened, fp, P.sigma, P.sigma * P.sigma);
   }
   {
