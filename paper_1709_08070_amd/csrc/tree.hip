@@ -353,12 +353,25 @@ pb_status build_host_tree(pb_ctx* ctx, const pb_band* band, const MixedPlan& P, 
     }
     code[j] = m;
   }
-  std::vector<std::pair<uint64_t, int>> keyed(n);
-  for (int j = 0; j < n; ++j) keyed[j] = {code[j], j};
-  std::sort(keyed.begin(), keyed.end());  // by code, ties by index
+  // sort by code, ties by index: a stable LSD radix sort of the indices, 16 bits per pass
   std::vector<int>& perm = H.perm;
   perm.resize(n);
-  for (int t = 0; t < n; ++t) perm[t] = keyed[t].second;
+  {
+    std::vector<int> tmp(n);
+    std::iota(perm.begin(), perm.end(), 0);
+    std::vector<int> count(65537);
+    for (int pass = 0; pass < 4; ++pass) {
+      const int shift = 16 * pass;
+      std::fill(count.begin(), count.end(), 0);
+      for (int j = 0; j < n; ++j) ++count[((code[j] >> shift) & 0xffff) + 1];
+      for (int v = 0; v < 65536; ++v) count[v + 1] += count[v];
+      for (int t = 0; t < n; ++t) {
+        const int j = perm[t];
+        tmp[count[(code[j] >> shift) & 0xffff]++] = j;
+      }
+      perm.swap(tmp);
+    }
+  }
   std::vector<double>& s = H.s;
   s.resize(3 * (size_t)n);
   std::vector<uint64_t> cs(n);
@@ -378,8 +391,7 @@ pb_status build_host_tree(pb_ctx* ctx, const pb_band* band, const MixedPlan& P, 
   while (!todo.empty()) {
     Todo td = todo.back();
     todo.pop_back();
-    HNode& nd = nodes[td.idx];
-    tight_box(s, nd.b, nd.e, nd.lo, nd.hi, nd.c, &nd.r);
+    const HNode& nd = nodes[td.idx];
     if (nd.e - nd.b <= kLeaf || td.level >= 21) continue;
     const int shift = 3 * (20 - td.level);
     const int b = nd.b, e = nd.e;
@@ -397,6 +409,27 @@ pb_status build_host_tree(pb_ctx* ctx, const pb_band* band, const MixedPlan& P, 
     nodes[td.idx].first_kid = first;
     nodes[td.idx].n_kids = nk;
     for (int k = nk - 1; k >= 0; --k) todo.push_back(Todo{first + k, td.level + 1});
+  }
+  // tight boxes bottom up (children are created after their parent): leaves scan their
+  // nodes, a parent takes the union of its children's boxes
+  for (int k = (int)nodes.size() - 1; k >= 0; --k) {
+    HNode& nd = nodes[k];
+    if (nd.n_kids == 0) {
+      tight_box(s, nd.b, nd.e, nd.lo, nd.hi, nd.c, &nd.r);
+      continue;
+    }
+    double r2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      nd.lo[a] = INFINITY;
+      nd.hi[a] = -INFINITY;
+      for (int q = 0; q < nd.n_kids; ++q) {
+        nd.lo[a] = std::min(nd.lo[a], nodes[nd.first_kid + q].lo[a]);
+        nd.hi[a] = std::max(nd.hi[a], nodes[nd.first_kid + q].hi[a]);
+      }
+      nd.c[a] = 0.5 * (nd.lo[a] + nd.hi[a]);
+      r2 += 0.25 * (nd.hi[a] - nd.lo[a]) * (nd.hi[a] - nd.lo[a]);
+    }
+    nd.r = std::sqrt(r2);
   }
   // target batches: the leaves in Morton order (depth first, children in octant order),
   // packed greedily into runs of at most kBatch nodes whose union box stays within
