@@ -154,15 +154,21 @@ __global__ void __launch_bounds__(kBlock) k_knn(int n, BandDev b, CellsDev cells
           const int j = cells.nodes[q];
           const double dx = xi - b.px[j], dy = yi - b.py[j], dz = zi - b.pz[j];
           const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
-          if (d2 > bd[kSlots - 1] || (d2 == bd[kSlots - 1] && j >= bi[kSlots - 1])) continue;
-          int s = kSlots - 1;
-          while (s > 0 && (bd[s - 1] > d2 || (bd[s - 1] == d2 && bi[s - 1] > j))) {
-            bd[s] = bd[s - 1];
-            bi[s] = bi[s - 1];
-            --s;
-          }
-          bd[s] = d2;
-          bi[s] = j;
+          if (!knn_before(d2, j, bd[kSlots - 1], bi[kSlots - 1])) continue;
+          // replace the last entry and bubble it into place: static indices keep the list in
+          // registers and the lanes of a wave on one instruction stream
+          bd[kSlots - 1] = d2;
+          bi[kSlots - 1] = j;
+#pragma unroll
+          for (int s = kSlots - 1; s > 0; --s)
+            if (knn_before(bd[s], bi[s], bd[s - 1], bi[s - 1])) {
+              const double td = bd[s];
+              const int ti = bi[s];
+              bd[s] = bd[s - 1];
+              bi[s] = bi[s - 1];
+              bd[s - 1] = td;
+              bi[s - 1] = ti;
+            }
         }
       }
   knn_merge(bd, bi, 1);
