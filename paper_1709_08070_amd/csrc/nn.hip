@@ -91,50 +91,10 @@ __device__ __forceinline__ float dact(float x) { return x > 0.f ? 1.f : kSlope; 
 
 // ---------------------------------------------------------------- geometry
 
-constexpr int kKnnLanes = 4;  // lanes per node in the neighbour search
-
-// (d, j) before (e, k): nearer first, the smaller index on equal distances
-__device__ __forceinline__ bool knn_before(double d, int j, double e, int k) { return d < e || (d == e && j < k); }
-
-// The 16 first of the union of this lane's sorted list and lane (l xor m)'s: the elementwise
-// minimum of one list and the other reversed holds them as a bitonic sequence, which three
-// half-cleaners sort. Static indices only, so the lists stay in registers.
-__device__ __forceinline__ void knn_merge(double (&bd)[kSlots], int (&bi)[kSlots], int m) {
-  double od[kSlots];
-  int oi[kSlots];
-#pragma unroll
-  for (int s = 0; s < kSlots; ++s) {
-    od[s] = __shfl_xor(bd[kSlots - 1 - s], m, kKnnLanes);
-    oi[s] = __shfl_xor(bi[kSlots - 1 - s], m, kKnnLanes);
-  }
-#pragma unroll
-  for (int s = 0; s < kSlots; ++s)
-    if (knn_before(od[s], oi[s], bd[s], bi[s])) {
-      bd[s] = od[s];
-      bi[s] = oi[s];
-    }
-#pragma unroll
-  for (int k = kSlots / 2; k > 0; k >>= 1)
-#pragma unroll
-    for (int s = 0; s < kSlots; ++s)
-      if ((s & k) == 0 && knn_before(bd[s + k], bi[s + k], bd[s], bi[s])) {
-        const double td = bd[s];
-        const int ti = bi[s];
-        bd[s] = bd[s + k];
-        bi[s] = bi[s + k];
-        bd[s + k] = td;
-        bi[s + k] = ti;
-      }
-}
-
 // 16 nearest band nodes by projection distance (self first), from the near-field cell list.
-// Four lanes per node: lane l scans the neighbouring cells numbered l, l + 4, ... (in the
-// lexicographic order of the 27), each keeps its 16 nearest, and two merges combine them.
-// The result is the 16 first in the (distance, index) order, whatever lane found them.
 __global__ void __launch_bounds__(kBlock) k_knn(int n, BandDev b, CellsDev cells, int* __restrict__ nbr) {
-  const int gt = blockIdx.x * kBlock + threadIdx.x;
-  const int i = gt / kKnnLanes, sub = gt % kKnnLanes;
-  if (i >= n) return;  // the node's four lanes leave together
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
   double bd[kSlots];
   int bi[kSlots];
   for (int s = 0; s < kSlots; ++s) {
@@ -144,37 +104,26 @@ __global__ void __launch_bounds__(kBlock) k_knn(int n, BandDev b, CellsDev cells
   const double xi = b.px[i], yi = b.py[i], zi = b.pz[i];
   const int c = cells.cell_of[i];
   const int cz = c % cells.ncz, cy = (c / cells.ncz) % cells.ncy, cx = c / (cells.ncz * cells.ncy);
-  int cell_no = 0;
   for (int ax = max(cx - 1, 0); ax <= min(cx + 1, cells.ncx - 1); ++ax)
     for (int ay = max(cy - 1, 0); ay <= min(cy + 1, cells.ncy - 1); ++ay)
       for (int az = max(cz - 1, 0); az <= min(cz + 1, cells.ncz - 1); ++az) {
-        if (cell_no++ % kKnnLanes != sub) continue;
         const int cc = (ax * cells.ncy + ay) * cells.ncz + az;
         for (int64_t q = cells.start[cc]; q < cells.start[cc + 1]; ++q) {
           const int j = cells.nodes[q];
           const double dx = xi - b.px[j], dy = yi - b.py[j], dz = zi - b.pz[j];
           const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
-          if (!knn_before(d2, j, bd[kSlots - 1], bi[kSlots - 1])) continue;
-          // replace the last entry and bubble it into place: static indices keep the list in
-          // registers and the lanes of a wave on one instruction stream
-          bd[kSlots - 1] = d2;
-          bi[kSlots - 1] = j;
-#pragma unroll
-          for (int s = kSlots - 1; s > 0; --s)
-            if (knn_before(bd[s], bi[s], bd[s - 1], bi[s - 1])) {
-              const double td = bd[s];
-              const int ti = bi[s];
-              bd[s] = bd[s - 1];
-              bi[s] = bi[s - 1];
-              bd[s - 1] = td;
-              bi[s - 1] = ti;
-            }
+          if (d2 > bd[kSlots - 1] || (d2 == bd[kSlots - 1] && j >= bi[kSlots - 1])) continue;
+          int s = kSlots - 1;
+          while (s > 0 && (bd[s - 1] > d2 || (bd[s - 1] == d2 && bi[s - 1] > j))) {
+            bd[s] = bd[s - 1];
+            bi[s] = bi[s - 1];
+            --s;
+          }
+          bd[s] = d2;
+          bi[s] = j;
         }
       }
-  knn_merge(bd, bi, 1);
-  knn_merge(bd, bi, 2);
-  if (sub == 0)
-    for (int s = 0; s < kSlots; ++s) nbr[(int64_t)i * kSlots + s] = bd[s] < INFINITY ? bi[s] : i;
+  for (int s = 0; s < kSlots; ++s) nbr[(int64_t)i * kSlots + s] = bd[s] < INFINITY ? bi[s] : i;
 }
 
 // Per-node geometry features: φ/ε, n (3), H·ε with H = (2/m) Σ_{j≠i} (n_j − n_i)·(x_j − x_i)/|x_j − x_i|².
@@ -686,8 +635,7 @@ pb_status nn_prepare(pb_ctx* ctx, const pb_band* band, const Derived& d) {
   const CellsDev cells{(const int64_t*)ctx->bufs["nn_cell_start"].ptr, (const int*)ctx->bufs["nn_cell_nodes"].ptr,
                        (const int*)ctx->bufs["nn_cell_of"].ptr, P.ncx, P.ncy, P.ncz};
   const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
-  const unsigned nbk = (unsigned)(((int64_t)n * kKnnLanes + kBlock - 1) / kBlock);
-  k_knn<<<nbk, kBlock, 0, ctx->stream>>>(n, band_dev(band), cells, B.nbr);
+  k_knn<<<nb, kBlock, 0, ctx->stream>>>(n, band_dev(band), cells, B.nbr);
   k_geom<<<nb, kBlock, 0, ctx->stream>>>(n, band_dev(band), band->phi, d.eps, B.nbr, B.feat);
   // reverse lists of (node, slot) per neighbour
   const int64_t ne = (int64_t)n * kSlots;
@@ -951,9 +899,8 @@ pb_status nn_batch_prepare(pb_ctx* ctx, int n_mol, const pb_band* bands, const i
     const CellsDev cells{(const int64_t*)ctx->bufs["nnb_cell_start"].ptr, (const int*)ctx->bufs["nnb_cell_nodes"].ptr,
                          (const int*)ctx->bufs["nnb_cell_of"].ptr, P.ncx, P.ncy, P.ncz};
     const unsigned nbk = (unsigned)((n + kBlock - 1) / kBlock);
-    const unsigned nbq = (unsigned)(((int64_t)n * kKnnLanes + kBlock - 1) / kBlock);
     int* nbr_m = nb.nbr + (int64_t)o * kSlots;
-    k_knn<<<nbq, kBlock, 0, ctx->stream>>>(n, band_dev(band), cells, nbr_m);
+    k_knn<<<nbk, kBlock, 0, ctx->stream>>>(n, band_dev(band), cells, nbr_m);
     k_geom<<<nbk, kBlock, 0, ctx->stream>>>(n, band_dev(band), band->phi, d.eps, nbr_m, nb.feat + (int64_t)o * 5);
     k_batch_geometry<<<nbk, kBlock, 0, ctx->stream>>>(n, o, band_dev(band), nbr_m, nb.pos + 3 * (int64_t)o);
     PB_TRY(launch_ok(ctx, "nn batch prepare"));
