@@ -79,6 +79,43 @@ def test_batched_matches_single_solves(pbm):
     ctx.close()
 
 
+def test_batch64_full_size_sampled(pbm):
+    """The benchmark's batch at full size (64 globules, atom counts log-uniform over 50–2000,
+    seeds 64000 + m, h = 0.5, mixed solve to 1e-6 in one batched call). For the smallest,
+    the median and the largest molecule the oracle recomputes, from the batch's solution, the
+    residual on 64 sampled operator rows (1e-5 relative) and the energy (1e-10)."""
+    ctx = pbm.Context(0)
+    sizes = synth.batch_sizes(64, 64000)
+    atoms_list = [synth.globule(n, 64000 + m) for m, n in enumerate(sizes)]
+    say(f"case: batch64, atoms {min(sizes)}-{max(sizes)}, h=0.5, tol 1e-6")
+    prm, bands, ats = _prepare(pbm, ctx, atoms_list, 0.5)
+    ns = [b.n for b in bands]
+    say(f"  band nodes {min(ns)}-{max(ns)}, {sum(ns)} in total")
+    ps, stats, bst = pbm.pb_ibim_solve_batched(ctx, bands, ats, prm, pbm.solve_opts(tol=1e-6,
+                                                                                     precision=pbm.PB_MIXED))
+    say(f"  replays={bst.graph_replays} outer={bst.outer} items={bst.n_items} p50={bst.t_p50_s:.3f}s "
+        f"p99={bst.t_p99_s:.3f}s")
+    assert all(st.converged and st.true_relres <= 1e-6 for st in stats)
+    oprm = oracle.params(0.5)
+    order = np.argsort(ns)
+    for i in (int(order[0]), int(order[len(order) // 2]), int(order[-1])):
+        nodes = bands[i].table()
+        n = len(nodes)
+        s = ps[i].cpu().numpy()
+        rows = np.random.default_rng(i).choice(n, 64, replace=False)
+        g = oracle.rhs(nodes, atoms_list[i], oprm)
+        a1, a2 = oracle.matvec_rows(nodes, oprm, s, rows)
+        res = np.concatenate([a1 - g[rows], a2 - g[n + rows]])
+        rel = np.linalg.norm(res) / np.linalg.norm(np.concatenate([g[rows], g[n + rows]]))
+        e_gpu = pbm.pb_solvation_energy(ctx, bands[i], ats[i], prm, ps[i]).g_pol
+        oE, _ = oracle.energy(nodes, atoms_list[i], oprm, s)
+        say(f"  mol {i}: n={n} iters={stats[i].iters} sampled residual {rel:.2e}, energy {e_gpu:.10e} "
+            f"oracle {oE:.10e}")
+        assert rel < 1e-5
+        assert e_gpu == pytest.approx(oE, rel=1e-10)
+    ctx.close()
+
+
 def test_batched_rejects_bad_input(pbm):
     import torch
 
