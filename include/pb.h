@@ -296,7 +296,9 @@ pb_status pb_nn_geometry(pb_ctx* ctx, const pb_band* band, int* nbr_host, float*
    enable = 0 off, 1 every family, 2 the far-field families only ("p2p_f32", "p2p_f64",
    "tree_f32", "tree_fine_f32"; each event pair adds a few microseconds
    between launches, so a timed run measures only what it reports). It synchronizes the
-   context stream and resets the counters; other values give PB_EINVAL. */
+   context stream and resets the counters; other values give PB_EINVAL. The launches of a
+   GMRES step enqueued after the solve's convergence test was met (they return at once)
+   are not counted, so the counts equal the operator applications the solve reports. */
 pb_status pb_set_timing(pb_ctx* ctx, int enable);
 pb_status pb_kernel_time(pb_ctx* ctx, const char* name, double* total_ms, int64_t* launches);
 
