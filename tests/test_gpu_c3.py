@@ -1,5 +1,6 @@
-"""GPU parity at full size: the 5000-atom globule at h = 0.25 (about 0.8M band nodes), the
-largest single-molecule workload, in the launch configuration bench.py times.
+"""GPU parity at full size: the 5000-atom globule at h = 0.25 (638,391 band nodes), the
+largest single-molecule workload, and the 500-atom globule at h = 0.5 that bench.py times by
+default, each in the launch configuration bench.py uses.
 
 The oracle cannot rerun the level set of a 14M-node grid in test time, so parity at this
 size rests on outputs it computes one by one from the GPU's own inputs:
@@ -9,7 +10,9 @@ size rests on outputs it computes one by one from the GPU's own inputs:
     the autotuner's far-field kernel and with the symmetric and one-directional ones forced;
     the treecode operator with its packed target batches: 3e-5 relative);
   * the mixed solve to 1e-6: its residual on the sampled rows recomputed by the oracle
-    (1e-5 relative), and the energy of its solution recomputed by the oracle (1e-10).
+    (1e-5 relative), and the energy of its solution recomputed by the oracle (1e-10);
+  * at the benchmark's size the same band, residual and energy checks for the mixed solve
+    and for the learned solve with the committed network.
 The level-set kernels are compared node by node with the oracle at the smaller sizes of
 test_gpu_parity.py.
 """
@@ -114,4 +117,57 @@ def test_globule5000_sampled(pbm):
     oE, _ = oracle.energy(nodes, atoms, oprm, s)
     say(f"energy gpu {e_gpu:.12e} oracle {oE:.12e}, {time.perf_counter() - t0:.1f}s")
     assert e_gpu == pytest.approx(oE, rel=1e-10)
+    ctx.close()
+
+
+def test_globule500_bench_step(pbm):
+    """The benchmark's step at its own size (globule 500, seed 500, h = 0.5, SES): level set,
+    band, mixed GMRES-IR to 1e-6 and, with the committed network, the learned solve. The
+    oracle compacts the GPU level set (bit-exact band), and recomputes from each GPU solution
+    the residual on 64 sampled operator rows (1e-5 relative) and the energy (1e-10)."""
+    import os as _os
+
+    import torch
+
+    say("case: globule 500 atoms seed 500 h=0.5 SES (the benchmark step)")
+    ctx = pbm.Context(0)
+    atoms = synth.globule(500, 500)
+    prm = pbm.params(0.5, ls_mode=pbm.PB_LS_SES)
+    grid = pbm.pb_grid_for_atoms(atoms, prm)
+    at = torch.tensor(atoms, dtype=torch.float64, device="cuda")
+    phi = pbm.pb_build_levelset(ctx, at, prm, grid)
+    band = pbm.pb_narrowband_compact(ctx, grid, phi, prm)
+    n = band.n
+    dims, origin = (grid.nx, grid.ny, grid.nz), tuple(grid.origin)
+    onodes, ogidx = oracle.band(dims, origin, 0.5, phi.cpu().numpy(), 1.0)
+    assert n == len(onodes) == 36033
+    np.testing.assert_array_equal(band.gidx[:n].cpu().numpy(), ogidx)
+    nodes = band.table()
+    assert np.max(np.abs(nodes - onodes)) <= 1e-12 * max(1.0, np.max(np.abs(onodes)))
+    oprm = oracle.params(0.5)
+    g = oracle.rhs(nodes, atoms, oprm)
+    rows = np.random.default_rng(13).choice(n, 64, replace=False)
+    net = None
+    wpath = _os.path.join(_os.path.dirname(_os.path.dirname(_os.path.abspath(__file__))), "paper_1709_08070_amd",
+                          "weights", "learned_h0.5.npz")
+    if _os.path.exists(wpath):
+        net = pbm.Net(ctx, seed=1)
+        net.load(wpath)
+    legs = [("mixed", pbm.solve_opts(tol=1e-6, precision=pbm.PB_MIXED))]
+    if net is not None:
+        legs.append(("learned", pbm.solve_opts(tol=1e-6, precision=pbm.PB_MIXED, x0=pbm.PB_X0_LEARNED,
+                                               precond=pbm.PB_PRECOND_LEARNED, nn=net.handle)))
+    for name, opts in legs:
+        sol, st = pbm.pb_ibim_solve(ctx, band, at, prm, opts)
+        assert st.converged and st.true_relres <= 1e-6
+        s = sol.cpu().numpy()
+        a1, a2 = oracle.matvec_rows(nodes, oprm, s, rows)
+        res = np.concatenate([a1 - g[rows], a2 - g[n + rows]])
+        rel = np.linalg.norm(res) / np.linalg.norm(np.concatenate([g[rows], g[n + rows]]))
+        e_gpu = pbm.pb_solvation_energy(ctx, band, at, prm, sol).g_pol
+        oE, _ = oracle.energy(nodes, atoms, oprm, s)
+        say(f"  {name}: iters={st.iters} relres={st.true_relres:.2e} sampled residual {rel:.2e}, "
+            f"energy {e_gpu:.12e} oracle {oE:.12e}")
+        assert rel < 1e-5
+        assert e_gpu == pytest.approx(oE, rel=1e-10)
     ctx.close()
