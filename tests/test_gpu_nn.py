@@ -235,3 +235,42 @@ def test_fallback_to_plain_gmres(pbm, ctx, small):
         tol=1e-8, precision=pbm.PB_MIXED, precond=pbm.PB_PRECOND_LEARNED, nn=net.handle, max_iter=60))
     say(f"fallback: used={st.fallback_used} iters={st.iters} relres={st.true_relres:.2e}")
     assert st.converged and st.true_relres <= 1e-8
+
+
+def test_committed_network_on_heldout_globule(pbm, ctx):
+    """The committed network (trained on 200–1500-atom globules) on a held-out 5000-atom
+    globule (seed 200000, never in training; about 158k band nodes at h = 0.5), as x0 and
+    right preconditioner of the mixed solve to 1e-6: no fallback, fewer iterations than the
+    plain mixed solve, and the oracle recomputes the residual on 64 sampled operator rows
+    (1e-5 relative) and the energy (1e-10) from the learned solution."""
+    import os
+
+    wpath = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1709_08070_amd",
+                         "weights", "learned_h0.5.npz")
+    if not os.path.exists(wpath):
+        pytest.skip("no committed network")
+    say("case: committed network, held-out globule 5000 atoms seed 200000 h=0.5, tol 1e-6")
+    atoms = synth.globule(5000, 200000)
+    prm, at, band = _band(pbm, ctx, atoms)
+    n = band.n
+    net = pbm.Net(ctx, seed=1)
+    net.load(wpath)
+    _, st0 = pbm.pb_ibim_solve(ctx, band, at, prm, pbm.solve_opts(tol=1e-6, precision=pbm.PB_MIXED))
+    sol, st = pbm.pb_ibim_solve(ctx, band, at, prm, pbm.solve_opts(
+        tol=1e-6, precision=pbm.PB_MIXED, x0=pbm.PB_X0_LEARNED, precond=pbm.PB_PRECOND_LEARNED, nn=net.handle))
+    say(f"  n={n}: plain mixed {st0.iters} iterations, learned {st.iters} (fallback {st.fallback_used})")
+    assert st.converged and st.true_relres <= 1e-6 and not st.fallback_used
+    assert st.iters < st0.iters
+    nodes = band.table()
+    oprm = oracle.params(0.5)
+    g = oracle.rhs(nodes, atoms, oprm)
+    rows = np.random.default_rng(17).choice(n, 64, replace=False)
+    s = sol.cpu().numpy()
+    a1, a2 = oracle.matvec_rows(nodes, oprm, s, rows)
+    rel = np.linalg.norm(np.concatenate([a1 - g[rows], a2 - g[n + rows]])) / np.linalg.norm(
+        np.concatenate([g[rows], g[n + rows]]))
+    e_gpu = pbm.pb_solvation_energy(ctx, band, at, prm, sol).g_pol
+    oE, _ = oracle.energy(nodes, atoms, oprm, s)
+    say(f"  sampled residual {rel:.2e}; energy {e_gpu:.12e} oracle {oE:.12e}")
+    assert rel < 1e-5
+    assert e_gpu == pytest.approx(oE, rel=1e-10)
