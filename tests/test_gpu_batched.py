@@ -113,6 +113,29 @@ def test_batch64_full_size_sampled(pbm):
             f"oracle {oE:.10e}")
         assert rel < 1e-5
         assert e_gpu == pytest.approx(oE, rel=1e-10)
+    # the same batch with the committed network as x0 and right preconditioner
+    import os
+
+    wpath = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1709_08070_amd",
+                         "weights", "learned_h0.5.npz")
+    if os.path.exists(wpath):
+        net = pbm.Net(ctx, seed=1)
+        net.load(wpath)
+        lopts = pbm.solve_opts(tol=1e-6, precision=pbm.PB_MIXED, x0=pbm.PB_X0_LEARNED,
+                               precond=pbm.PB_PRECOND_LEARNED, nn=net.handle)
+        lps, lstats, lbst = pbm.pb_ibim_solve_batched(ctx, bands, ats, prm, lopts)
+        say(f"  learned: replays={lbst.graph_replays} (plain {bst.graph_replays}), "
+            f"fallbacks {sum(st.fallback_used for st in lstats)}")
+        assert all(st.converged and st.true_relres <= 1e-6 and not st.fallback_used for st in lstats)
+        assert lbst.graph_replays < bst.graph_replays
+        for i in range(len(bands)):
+            e_l = pbm.pb_solvation_energy(ctx, bands[i], ats[i], prm, lps[i]).g_pol
+            e_p = pbm.pb_solvation_energy(ctx, bands[i], ats[i], prm, ps[i]).g_pol
+            assert e_l == pytest.approx(e_p, rel=1e-6)
+        i = int(order[-1])
+        nodes = bands[i].table()
+        oE, _ = oracle.energy(nodes, atoms_list[i], oprm, lps[i].cpu().numpy())
+        assert pbm.pb_solvation_energy(ctx, bands[i], ats[i], prm, lps[i]).g_pol == pytest.approx(oE, rel=1e-10)
     ctx.close()
 
 
