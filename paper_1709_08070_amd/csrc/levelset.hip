@@ -166,6 +166,102 @@ __global__ void __launch_bounds__(kBlock) k_cav_sweep(GridDev g, const double* _
   if (any) *changed = 1;
 }
 
+constexpr int kLineChunks = 64;  // the wave-per-line sweep handles lines of up to 64·64 nodes
+constexpr int kLineWaves = kBlock / 64;
+
+// Bits t of F (< 64) that some seed s ≤ t reaches through set bits of P: a doubling scan
+// on a 64-node chunk (Kogge–Stone over the ballot masks; bits shifted in are 0).
+__device__ __forceinline__ uint64_t reach_up(uint64_t S, uint64_t P) {
+  uint64_t F = S, A = P;
+  for (int d = 1; d < 64; d <<= 1) {
+    F |= (F << d) & A;
+    A &= A << d;
+  }
+  return F;
+}
+__device__ __forceinline__ uint64_t reach_down(uint64_t S, uint64_t P) {
+  uint64_t F = S, A = P;
+  for (int d = 1; d < 64; d <<= 1) {
+    F |= (F >> d) & A;
+    A &= A >> d;
+  }
+  return F;
+}
+
+// The same sweep with one wave per line (lines of at most 64·kLineChunks nodes). The lanes
+// take 64 consecutive nodes of the line at a time; ballots give P (φ > 0), the exterior
+// nodes O and the seeds S (P-nodes exterior already or with an exterior neighbour across
+// the line). A node joins the exterior when a seed reaches it through P along the line, in
+// either direction: doubling scans per chunk, carries between chunks (forward pass, then
+// backward). Same fixed point as the one-thread-per-line sweep, with a wave per line
+// instead of a thread, so the launch fills the GPU.
+__global__ void __launch_bounds__(kBlock) k_cav_line(GridDev g, const double* __restrict__ phi, uint8_t* outside,
+                                                     int axis, int* changed) {
+  __shared__ uint64_t sP[kLineWaves][kLineChunks], sO[kLineWaves][kLineChunks], sF[kLineWaves][kLineChunks];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t line = (int64_t)blockIdx.x * kLineWaves + wave;
+  const int64_t n3[3] = {g.nx, g.ny, g.nz};
+  const int a1 = axis == 0 ? 1 : 0, a2 = axis == 2 ? 1 : 2;
+  if (line >= n3[a1] * n3[a2]) return;  // the whole wave
+  const int64_t L = n3[axis];
+  const int nch = (int)((L + 63) / 64);
+  int64_t c[3];
+  c[a1] = line / n3[a2];
+  c[a2] = line % n3[a2];
+  uint64_t carry = 0;  // the last node of the previous chunk was reached
+  for (int ch = 0; ch < nch; ++ch) {
+    const int64_t t = (int64_t)ch * 64 + lane;
+    bool pos = false, out = false, seed = false;
+    if (t < L) {
+      c[axis] = t;
+      const int64_t id = lin(g, c[0], c[1], c[2]);
+      pos = phi[id] > 0.0;
+      out = outside[id] != 0;
+      seed = pos && out;
+      if (pos && !out)
+        for (int ax = 0; ax < 3 && !seed; ++ax) {
+          if (ax == axis) continue;
+          for (int s = -1; s <= 1 && !seed; s += 2) {
+            int64_t q[3] = {c[0], c[1], c[2]};
+            q[ax] += s;
+            if (q[ax] < 0 || q[ax] >= n3[ax]) continue;
+            if (outside[lin(g, q[0], q[1], q[2])]) seed = true;
+          }
+        }
+    }
+    const uint64_t P = __ballot(pos), O = __ballot(out);
+    const uint64_t S = __ballot(seed) | (carry & P & 1ull);
+    const uint64_t F = reach_up(S, P);
+    carry = F >> 63;
+    if (lane == 0) {
+      sP[wave][ch] = P;
+      sO[wave][ch] = O;
+      sF[wave][ch] = F;
+    }
+  }
+  // lane 0's masks are read by every lane of the same wave below
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  carry = 0;  // the first node of the next chunk was reached
+  bool any = false;
+  for (int ch = nch - 1; ch >= 0; --ch) {
+    const uint64_t P = sP[wave][ch], O = sO[wave][ch], Ff = sF[wave][ch];
+    // seeds of the backward scan: everything the forward scan reached (it holds the seeds)
+    const uint64_t B = reach_down(Ff | ((carry << 63) & P), P);
+    carry = B & 1ull;
+    const uint64_t add = (Ff | B) & P & ~O;
+    if (add) {
+      any = true;
+      if ((add >> lane) & 1ull) {
+        c[axis] = (int64_t)ch * 64 + lane;
+        outside[lin(g, c[0], c[1], c[2])] = 1;
+      }
+    }
+  }
+  if (any && lane == 0) *changed = 1;
+}
+
 // Unreached nodes within (ε + h) of a cavity node (unreached, φ > 0) get −ε.
 __global__ void __launch_bounds__(kBlock) k_cav_dilate(GridDev g, const double* __restrict__ phi,
                                                        const uint8_t* __restrict__ outside, double eps, int m,
@@ -270,7 +366,12 @@ extern "C" pb_status pb_build_levelset(pb_ctx* ctx, const double* atoms, int n_a
     for (int ax = 0; ax < 3; ++ax) {
       int a1 = ax == 0 ? 1 : 0, a2 = ax == 2 ? 1 : 2;
       Scope t(ctx, "levelset");
-      k_cav_sweep<<<blocks_for(n3[a1] * n3[a2]), kBlock, 0, ctx->stream>>>(g, phi, outside, ax, flags);
+      const int64_t lines = n3[a1] * n3[a2];
+      if (n3[ax] <= 64 * kLineChunks)
+        k_cav_line<<<(unsigned)((lines + kLineWaves - 1) / kLineWaves), kBlock, 0, ctx->stream>>>(g, phi, outside,
+                                                                                                 ax, flags);
+      else
+        k_cav_sweep<<<blocks_for(lines), kBlock, 0, ctx->stream>>>(g, phi, outside, ax, flags);
     }
     PB_TRY(launch_ok(ctx, "cavity sweep"));
     int changed = 0;
