@@ -531,13 +531,19 @@ static __global__ void __attribute__((unused)) __launch_bounds__(kBlock) k_near_
   const double xi = b.px[i], yi = b.py[i], zi = b.pz[i], nxi = b.nx[i], nyi = b.ny[i], nzi = b.nz[i];
   const double ci = b.curv ? b.curv[i] : 0.0;
   const int64_t r0 = row[i];
-  for_near_wave(i, A, cells, rc2, [&](int j, int64_t slot) {
+  // the columns first (a few hits per 64 candidates), then the FP64 coefficients with every
+  // lane busy: entry q = r0 + lane, r0 + lane + 64, ... reads back the column its wave wrote
+  const int64_t cnt = for_near_wave(i, A, cells, rc2, [&](int j, int64_t slot) { col[r0 + slot] = j; });
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (int64_t q = r0 + (threadIdx.x & 63); q < r0 + cnt; q += 64) {
+    const int j = col[q];
     double k[4];
     kern4_f64(xi, yi, zi, nxi, nyi, nzi, b.px[j], b.py[j], b.pz[j], b.nx[j], b.ny[j], b.nz[j], kp, ci, k);
     const double sj = scale * w[j];
-    col[r0 + slot] = j;
-    coef[r0 + slot] = make_double4(k[0] * sj, -k[1] * sj, k[2] * sj, -k[3] * sj);
-  });
+    coef[q] = make_double4(k[0] * sj, -k[1] * sj, k[2] * sj, -k[3] * sj);
+  }
 }
 
 constexpr int kRowLanes = 16;  // lanes cooperating on one CSR row
