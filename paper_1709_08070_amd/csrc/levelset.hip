@@ -49,8 +49,14 @@ __global__ void __launch_bounds__(kBlock) k_vdw(GridDev g, const double* __restr
     int m = min(kBlock, n_atoms - base);
     for (int q = 0; q < m; ++q) {
       double4 at = tile[q];
-      double dist = sqrt((sq(x - at.x) + sq(y - at.y)) + sq(z - at.z)) - at.w;
-      best = dist < best ? dist : best;
+      const double d2 = (sq(x - at.x) + sq(y - at.y)) + sq(z - at.z);
+      // |x − z| − r < best needs |x − z| < best + r: atoms that fail that (with a relative
+      // margin far above the rounding of both sides) cannot lower best, and skip the sqrt
+      const double lim = best + at.w;
+      if (lim > 0.0 && d2 < lim * lim * (1.0 + 1e-12)) {
+        const double dist = sqrt(d2) - at.w;
+        best = dist < best ? dist : best;
+      }
     }
     __syncthreads();
   }
