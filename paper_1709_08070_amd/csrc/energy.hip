@@ -32,7 +32,9 @@ __global__ void __launch_bounds__(kBlock) k_rhs(int n, const double* __restrict_
   const double c4 = 1.0 / (4.0 * kPi);
   for (int base = 0; base < n_atoms; base += kBlock) {
     int k = base + threadIdx.x;
-    if (k < n_atoms) tile[threadIdx.x] = make_double4(atoms[5 * k], atoms[5 * k + 1], atoms[5 * k + 2], atoms[5 * k + 4]);
+    // the charge enters as q/ε_I/(4π), formed once per atom (the same operations, hoisted)
+    if (k < n_atoms)
+      tile[threadIdx.x] = make_double4(atoms[5 * k], atoms[5 * k + 1], atoms[5 * k + 2], atoms[5 * k + 4] / eps_in * c4);
     __syncthreads();
     int m = min(kBlock, n_atoms - base);
     if (live)
@@ -42,7 +44,7 @@ __global__ void __launch_bounds__(kBlock) k_rhs(int n, const double* __restrict_
         double r2 = dx * dx + dy * dy + dz * dz;
         double rinv = 1.0 / sqrt(r2);
         double dn = dx * a + dy * b + dz * c;
-        double qe = at.w / eps_in * c4;
+        double qe = at.w;
         s1 += qe * rinv;
         s2 -= qe * dn * rinv * rinv * rinv;
       }
