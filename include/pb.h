@@ -63,8 +63,9 @@ enum { PB_FP64 = 0, PB_MIXED = 1, PB_TREE = 2 };
 /* GMRES initial guess: zero, Λ⁻¹g (the paper's diagonal preconditioner), caller's p, learned. */
 enum { PB_X0_ZERO = 0, PB_X0_DIAG = 1, PB_X0_USER = 2, PB_X0_LEARNED = 3 };
 enum { PB_PRECOND_NONE = 0, PB_PRECOND_LEARNED = 1 };
-/* ∇φ at band nodes (section "Projections and weights"): second-order central differences,
-   or the average (p₋ + p₊)/2 of the two fifth-order WENO one-sided derivatives per axis. */
+/* ∇φ at band nodes (section "Projections and weights"): the average (p₋ + p₊)/2 of the two
+   fifth-order WENO one-sided derivatives per axis (the section's choice for its simulations;
+   the default), or second-order central differences. */
 enum { PB_GRAD_CENTRAL = 0, PB_GRAD_WENO = 1 };
 /* Jacobian in the band weight: J ≡ 1 (every experiment of the paper), or the explicit
    J = 1 − φΔφ + φ²⟨n, adj(∇²φ) n⟩ of section "Implicit boundary integral methods" (read
@@ -95,7 +96,7 @@ typedef struct {
   int reg_metric;    /* PB_REG_* */
   int ls_mode;       /* PB_LS_* */
   int reinit_steps;  /* reinitialization steps; 0 = 2·ceil((band_k + 4)/cfl) */
-  int grad_scheme;   /* PB_GRAD_* (default central differences) */
+  int grad_scheme;   /* PB_GRAD_* (default the WENO average) */
   int jacobian;      /* PB_JAC_* (default J ≡ 1) */
   int tree_degree;   /* PB_TREE: degree p of the Chebyshev proxies per axis, 2..8 (4) */
   int reg_avg;       /* PB_AVG_* (default the paper's flat disc averages) */
@@ -111,7 +112,7 @@ typedef struct {
   int64_t n;          /* out: band node count (on PB_ECAPACITY: the required count) */
   int64_t capacity;   /* in: entries available in every array below */
   double *px, *py, *pz;   /* device: closest-point projection x* = x − φ n */
-  double *nx, *ny, *nz;   /* device: unit normal ∇φ/|∇φ| (central differences) */
+  double *nx, *ny, *nz;   /* device: unit normal ∇φ/|∇φ|, ∇φ by pb_params.grad_scheme */
   double *phi;            /* device: level-set value at the node */
   double *w;              /* device: ω = J·δ_ε(φ), J per pb_params.jacobian (h³ is applied by the operator) */
   int64_t *gidx;          /* device: linear grid index of the node */
@@ -156,12 +157,14 @@ pb_status pb_create(pb_ctx** out, int device, void* hip_stream);
 void pb_destroy(pb_ctx* ctx);
 const char* pb_last_error(const pb_ctx* ctx);
 /* Parameters of the paper's experiments ("Numerical experiments": ε_I = 1, ε_E = 80,
-   κ = 0.1257, ε = 2h, τ = h) with ρ0 = 1.4, h = 0.5, cfl = 0.3, near_k = 2. */
+   κ = 0.1257, ε = 2h, τ = h; normals from the WENO average and J ≡ 1 as in section
+   "Projections and weights") with ρ0 = 1.4, h = 0.5, cfl = 0.3, near_k = 2. */
 void pb_default_params(pb_params* out);
 void pb_default_solve_opts(pb_solve_opts* out);
 
 /* Grid on hℤ³ covering the atoms (host, n_atoms × 5) with a margin of
-   r_max + ρ0 (SES only) + ε + 4h + 1 Å. Host-only; no device work. */
+   r_max + ρ0 (SES only) + ε + 4h + 1 Å. Host-only; no device work. PB_EINVAL for non-finite
+   atoms, negative radii, h ≤ 0, or an axis of more than 4096 nodes. */
 pb_status pb_grid_for_atoms(const double* atoms_host, int n_atoms, const pb_params* prm, pb_grid* grid);
 
 /* Stage 1 (section "Creating a signed distance function to the solvent accessible
@@ -171,10 +174,16 @@ pb_status pb_grid_for_atoms(const double* atoms_host, int n_atoms, const pb_para
    Hamiltonian, WENO5, zero-Neumann ghosts), cavity removal (flood fill from the grid
    boundary through φ > 0; unreached nodes within ε + h of a cavity set to −ε), then
    reinitialization φ_t + sgn_h(φ0)(|∇φ| − 1) = 0 (eqs. reinit, signum).
-   atoms: device, n_atoms × 5. phi: device, nx·ny·nz doubles. PB_EINVAL if an axis has
-   fewer than 7 nodes, grid->h differs from prm->h, or the grid has 2^31 nodes or more. */
+   grid: as from pb_grid_for_atoms (grid->h must equal prm->h). atoms: device, n_atoms × 5.
+   phi: device, cap doubles, caller-owned; on success its first nx·ny·nz entries hold φ in
+   the grid's linear order. Two-call size protocol: with phi == NULL the call only validates
+   and writes the element count nx·ny·nz to *needed (atoms may then be NULL); with
+   cap < nx·ny·nz it returns PB_ECAPACITY with *needed set, before any device work, and
+   writes nothing. needed may be NULL. PB_EINVAL if an axis has fewer than 7 or more than 4096
+   nodes, grid->h differs from prm->h, the grid has 2^31 nodes or more, or atoms is NULL or
+   empty in a call that builds φ. */
 pb_status pb_build_levelset(pb_ctx* ctx, const double* atoms, int n_atoms, const pb_params* prm,
-                            const pb_grid* grid, double* phi);
+                            const pb_grid* grid, double* phi, size_t cap, size_t* needed);
 
 /* Stage 2 (section "Projections and weights"): band nodes −ε < φ < ε in lexicographic
    order, n = ∇φ/|∇φ| with ∇φ by prm->grad_scheme, x* = x − φ n, ω = δ_ε(φ)·J
@@ -250,7 +259,8 @@ typedef struct {
    opts->nn set, every band's phi present): the network runs over all molecules at once;
    as right preconditioner inside the captured step (flexible GMRES), as x0 = M(g). A
    molecule that misses the tolerance on the learned path is solved again without the
-   network from its last iterate (from Λ⁻¹g if that is not finite); stats[m].fallback_used
+   network from its last iterate (from Λ⁻¹g if that is not finite) with what is left of
+   opts->max_iter (the preconditioned pass takes at most half of it); stats[m].fallback_used
    reports it. PB_EINVAL: precision other than PB_MIXED, the literal tangent metric, an
    unknown x0 or preconditioner mode, a learned mode without opts->nn or a band's phi. */
 pb_status pb_ibim_solve_batched(pb_ctx* ctx, int n_mol, const pb_band* bands, const double* const* atoms,
@@ -264,7 +274,10 @@ pb_status pb_ibim_solve_batched(pb_ctx* ctx, int n_mol, const pb_band* bands, co
    M(v) = Λ⁻¹(v + s ⊙ O(v)), s = per-half RMS of v: the paper's diagonal solve plus a learned
    correction (an untrained network is exactly Λ⁻¹). pb_ibim_solve uses it as x0 = M(g)
    (PB_X0_LEARNED) and as a right preconditioner inside FGMRES (PB_PRECOND_LEARNED), with plain
-   GMRES as the fallback. */
+   GMRES as the fallback: a learned solve that misses the tolerance (or whose iterate is not
+   finite) continues without the network from its last iterate (from Λ⁻¹g if that is not
+   finite) and reports fallback_used. Both passes share opts->max_iter; the preconditioned
+   pass takes at most half of it. */
 typedef struct pb_nn pb_nn;
 /* Network with He-uniform weights from a SplitMix64 stream of `seed`, last layer zero. */
 pb_status pb_nn_create(pb_ctx* ctx, uint64_t seed, pb_nn** out);

@@ -154,9 +154,10 @@ def weno_grad(dims, h, phi, node):
 GRAD_CENTRAL, GRAD_WENO = 0, 1
 
 
-def band(dims, origin, h, phi, eps, grad_scheme=GRAD_CENTRAL, jacobian=False):
+def band(dims, origin, h, phi, eps, grad_scheme=GRAD_WENO, jacobian=False):
     """Returns (nodes [n×8], gidx [n]); raises if a band node touches the grid edge.
-    grad_scheme: central differences or the WENO5 average; jacobian: ω carries the explicit J."""
+    grad_scheme: the WENO5 average (default, as in the paper's simulations) or central
+    differences; jacobian: ω carries the explicit J."""
     phi = _f64(phi)
     d3, o3 = (C.c_int * 3)(*dims), (C.c_double * 3)(*origin)
     n = lib().pbo_band(d3, o3, h, _d(phi), eps, grad_scheme, int(jacobian), None, None)
@@ -268,7 +269,7 @@ def grid_margin(atoms, h, band_k=2.0, probe=1.4, ses=True):
     return rmax + (probe if ses else 0.0) + band_k * h + 4 * h + 1.0
 
 
-def pipeline(atoms, h, ses=True, tau_k=1.0, grad_scheme=GRAD_CENTRAL, jacobian=False, **kw):
+def pipeline(atoms, h, ses=True, tau_k=1.0, grad_scheme=GRAD_WENO, jacobian=False, **kw):
     """Stage 1 + Stage 2 on the CPU: returns dims, origin, phi, nodes, gidx, prm."""
     prm = params(h, tau_k=tau_k, **kw)
     dims, origin = grid(atoms, h, grid_margin(atoms, h, prm[BAND] / h, prm[PROBE], ses))

@@ -1,7 +1,7 @@
 """Solvation energy of a molecule from a PQR file on the GPU:
 
     python -m paper_1709_08070_amd.cli molecule.pqr [--h 0.5] [--precision mixed|fp64|tree]
-        [--learned WEIGHTS] [--tol 1e-6] [--vdw] [--jacobian] [--weno] [--curved]
+        [--learned WEIGHTS] [--tol 1e-6] [--vdw] [--jacobian] [--central] [--curved]
 
 Runs the whole method (level set, band, right-hand side, GMRES, energy) through the C-ABI
 and prints one JSON object: band size, iterations, the true relative residual, the
@@ -15,7 +15,7 @@ import time
 
 
 def run(path: str, h: float = 0.5, precision: str = "mixed", tol: float = 1e-6, learned: str | None = None,
-        vdw: bool = False, jacobian: bool = False, weno: bool = False, curved: bool = False) -> dict:
+        vdw: bool = False, jacobian: bool = False, central: bool = False, curved: bool = False) -> dict:
     import torch
 
     from . import pb, pqr
@@ -24,7 +24,7 @@ def run(path: str, h: float = 0.5, precision: str = "mixed", tol: float = 1e-6, 
     ctx = pb.Context(0)
     prm = pb.params(h, ls_mode=pb.PB_LS_VDW if vdw else pb.PB_LS_SES,
                     jacobian=pb.PB_JAC_FULL if jacobian else pb.PB_JAC_ONE,
-                    grad_scheme=pb.PB_GRAD_WENO if weno else pb.PB_GRAD_CENTRAL,
+                    grad_scheme=pb.PB_GRAD_CENTRAL if central else pb.PB_GRAD_WENO,
                     reg_avg=pb.PB_AVG_CURVED if curved else pb.PB_AVG_FLAT)
     t0 = time.perf_counter()
     grid = pb.pb_grid_for_atoms(atoms, prm)
@@ -62,10 +62,10 @@ def main(argv=None) -> int:
     ap.add_argument("--learned", metavar="WEIGHTS", default=None, help="network weights (.npz) for x0 and preconditioner")
     ap.add_argument("--vdw", action="store_true", help="van der Waals surface instead of the SES")
     ap.add_argument("--jacobian", action="store_true", help="explicit Jacobian in the band weights")
-    ap.add_argument("--weno", action="store_true", help="WENO-average normals")
+    ap.add_argument("--central", action="store_true", help="central-difference normals instead of the WENO average")
     ap.add_argument("--curved", action="store_true", help="curvature-corrected disc averages")
     a = ap.parse_args(argv)
-    print(json.dumps(run(a.pqr, a.h, a.precision, a.tol, a.learned, a.vdw, a.jacobian, a.weno, a.curved)))
+    print(json.dumps(run(a.pqr, a.h, a.precision, a.tol, a.learned, a.vdw, a.jacobian, a.central, a.curved)))
     return 0
 
 

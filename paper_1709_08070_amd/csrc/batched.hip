@@ -1060,6 +1060,9 @@ extern "C" pb_status pb_ibim_solve_batched(pb_ctx* ctx, int n_mol, const pb_band
   };
 
   int replays = 0, outer = 0, outer_run = 0, iters_total = 0;
+  // iteration budget of the current pass: the learned-preconditioned pass gets at most half of
+  // max_iter, so that the plain fallback keeps at least the other half
+  int iter_cap = prec ? opts.max_iter - opts.max_iter / 2 : opts.max_iter;
   std::vector<int> mv64(n_mol, 0), mvmx(n_mol, 0), cyc_h(n_mol), sel_h(n_mol);
   PB_HIP(ctx, hipMemcpyAsync(sel, all_on, sizeof(int) * n_mol, hipMemcpyDeviceToDevice, B.st));
 
@@ -1080,7 +1083,7 @@ extern "C" pb_status pb_ibim_solve_batched(pb_ctx* ctx, int n_mol, const pb_band
       int nact = 0;
       PB_HIP(ctx, hipMemcpyAsync(&nact, B.n_active, sizeof(int), hipMemcpyDeviceToHost, B.st));
       PB_HIP(ctx, hipStreamSynchronize(B.st));
-      if (nact == 0 || iters_total >= opts.max_iter) break;
+      if (nact == 0 || iters_total >= iter_cap) break;
       PB_HIP(ctx, hipMemcpyAsync(cyc_h.data(), B.cycle, sizeof(int) * n_mol, hipMemcpyDeviceToHost, B.st));
       // V0 = r0/‖r0‖ (rhs_vec holds r0 when sol = 0, otherwise the refreshed residual in r)
       k_scale_batch<<<B.nseg, kBlock, 0, B.st>>>(B.nseg, B.segs, B.active, B.V, B.M, nullptr, m, 0, 0, rr, rn, 1);
@@ -1139,7 +1142,7 @@ extern "C" pb_status pb_ibim_solve_batched(pb_ctx* ctx, int n_mol, const pb_band
       PB_HIP(ctx, hipMemcpyAsync(&nsel, n_sel, sizeof(int), hipMemcpyDeviceToHost, B.st));
       PB_HIP(ctx, hipStreamSynchronize(B.st));
       for (int i = 0; i < n_mol; ++i) mv64[i] += sel_h[i];
-      if (nsel == 0 || outer_run >= opts.max_outer || iters_total >= opts.max_iter) return PB_OK;
+      if (nsel == 0 || outer_run >= opts.max_outer || iters_total >= iter_cap) return PB_OK;
       PB_TRY(inner(sel, r, dvec, with_prec));
       k_add_batch<<<B.nseg, kBlock, 0, B.st>>>(B.nseg, B.segs, sel, dvec, x);
       ++outer;
@@ -1148,8 +1151,10 @@ extern "C" pb_status pb_ibim_solve_batched(pb_ctx* ctx, int n_mol, const pb_band
   };
   std::vector<int> fallback(n_mol, 0);
   PB_TRY(outer_loop(prec));
-  if (prec) {
-    // plain GMRES judges the learned path: molecules still selected missed the tolerance
+  if (learned_x0 || prec) {
+    // plain GMRES judges the learned path (x0 = M(g) and/or the preconditioner): molecules
+    // still selected missed the tolerance; they continue without the network, from Λ⁻¹g where
+    // their iterate is not finite, with what is left of the iteration budget
     PB_HIP(ctx, hipMemcpyAsync(sel_h.data(), sel, sizeof(int) * n_mol, hipMemcpyDeviceToHost, B.st));
     PB_HIP(ctx, hipStreamSynchronize(B.st));
     bool any = false;
@@ -1160,7 +1165,7 @@ extern "C" pb_status pb_ibim_solve_batched(pb_ctx* ctx, int n_mol, const pb_band
     if (any) {
       k_reset_nonfinite<<<nbn, kBlock, 0, B.st>>>(B.ntot, B.mol_of, B.mols, relres, g, B.d.lam1, B.d.lam2, x);
       outer_run = 0;
-      iters_total = 0;
+      iter_cap = opts.max_iter;
       PB_TRY(outer_loop(false));
     }
   }

@@ -295,7 +295,7 @@ void pb_default_params(pb_params* p) {
   p->cfl = 0.3;
   p->near_k = 2.0;
   p->reg_metric = PB_REG_TANGENT_GUARDED;
-  p->grad_scheme = PB_GRAD_CENTRAL;
+  p->grad_scheme = PB_GRAD_WENO;
   p->jacobian = PB_JAC_ONE;
   p->tree_theta = 0.6;
   p->tree_degree = 4;
@@ -339,6 +339,7 @@ pb_status pb_grid_for_atoms(const double* atoms, int n_atoms, const pb_params* p
     long ilo = (long)std::floor((lo[a] - margin) / h);
     long ihi = (long)std::ceil((hi[a] + margin) / h);
     grid->origin[a] = (double)ilo * h;
+    if (ihi - ilo + 1 > 4096) return PB_EINVAL;  // the level set takes axes of at most 4096 nodes
     int n = (int)(ihi - ilo + 1);
     if (a == 0) grid->nx = n;
     if (a == 1) grid->ny = n;

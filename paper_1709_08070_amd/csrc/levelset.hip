@@ -136,43 +136,8 @@ __global__ void __launch_bounds__(kBlock) k_cav_init(GridDev g, const double* __
   outside[id] = (edge && phi[id] > 0.0) ? 1 : 0;
 }
 
-// One thread per grid line along `axis`: a forward and a backward pass, each node joining
-// the exterior if φ > 0 and any 6-neighbour is exterior. Labels only go 0 → 1, so reads of
-// neighbours being updated by other lines are harmless; repeated sweeps reach the unique
-// fixed point, the 6-connected component of {φ > 0} that touches the boundary.
-__global__ void __launch_bounds__(kBlock) k_cav_sweep(GridDev g, const double* __restrict__ phi,
-                                                      uint8_t* outside, int axis, int* changed) {
-  int64_t line = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  int64_t n3[3] = {g.nx, g.ny, g.nz};
-  int a1 = axis == 0 ? 1 : 0, a2 = axis == 2 ? 1 : 2;
-  if (line >= n3[a1] * n3[a2]) return;
-  int64_t c[3];
-  c[a1] = line / n3[a2];
-  c[a2] = line % n3[a2];
-  int any = 0;
-  for (int dir = 0; dir < 2; ++dir) {
-    for (int64_t t = 0; t < n3[axis]; ++t) {
-      c[axis] = dir == 0 ? t : n3[axis] - 1 - t;
-      int64_t id = lin(g, c[0], c[1], c[2]);
-      if (outside[id] || !(phi[id] > 0.0)) continue;
-      bool hit = false;
-      for (int ax = 0; ax < 3 && !hit; ++ax)
-        for (int s = -1; s <= 1 && !hit; s += 2) {
-          int64_t q[3] = {c[0], c[1], c[2]};
-          q[ax] += s;
-          if (q[ax] < 0 || q[ax] >= n3[ax]) continue;
-          if (outside[lin(g, q[0], q[1], q[2])]) hit = true;
-        }
-      if (hit) {
-        outside[id] = 1;
-        any = 1;
-      }
-    }
-  }
-  if (any) *changed = 1;
-}
-
 constexpr int kLineChunks = 64;  // the wave-per-line sweep handles lines of up to 64·64 nodes
+constexpr int kMaxAxis = 64 * kLineChunks;
 constexpr int kLineWaves = kBlock / 64;
 
 // Bits t of F (< 64) that some seed s ≤ t reaches through set bits of P: a doubling scan
@@ -194,13 +159,15 @@ __device__ __forceinline__ uint64_t reach_down(uint64_t S, uint64_t P) {
   return F;
 }
 
-// The same sweep with one wave per line (lines of at most 64·kLineChunks nodes). The lanes
-// take 64 consecutive nodes of the line at a time; ballots give P (φ > 0), the exterior
-// nodes O and the seeds S (P-nodes exterior already or with an exterior neighbour across
-// the line). A node joins the exterior when a seed reaches it through P along the line, in
-// either direction: doubling scans per chunk, carries between chunks (forward pass, then
-// backward). Same fixed point as the one-thread-per-line sweep, with a wave per line
-// instead of a thread, so the launch fills the GPU.
+// One sweep of the flood fill along `axis`, one wave per grid line (lines of at most
+// 64·kLineChunks nodes). A node joins the exterior if φ > 0 and a node reachable from it
+// through φ > 0 along the line is exterior or has an exterior neighbour across the line.
+// The lanes take 64 consecutive nodes of the line at a time; ballots give P (φ > 0), the
+// exterior nodes O and the seeds S (P-nodes exterior already or with an exterior neighbour
+// across the line); doubling scans per chunk, carries between chunks (forward pass, then
+// backward). Labels only go 0 → 1, so reads of neighbours being updated by other lines are
+// harmless; repeated sweeps over the three axes reach the unique fixed point, the
+// 6-connected component of {φ > 0} that touches the grid boundary.
 __global__ void __launch_bounds__(kBlock) k_cav_line(GridDev g, const double* __restrict__ phi, uint8_t* outside,
                                                      int axis, int* changed) {
   __shared__ uint64_t sP[kLineWaves][kLineChunks], sO[kLineWaves][kLineChunks], sF[kLineWaves][kLineChunks];
@@ -321,18 +288,27 @@ pb_status tvd_rk3(pb_ctx* ctx, const GridDev& g, double* phi, double* p1, double
 }  // namespace pb
 
 extern "C" pb_status pb_build_levelset(pb_ctx* ctx, const double* atoms, int n_atoms, const pb_params* prm,
-                                       const pb_grid* grid, double* phi) {
+                                       const pb_grid* grid, double* phi, size_t cap, size_t* needed) {
   using namespace pb;
   if (!ctx) return PB_EINVAL;
   PB_TRY(check_params(ctx, prm));
-  if (!atoms || n_atoms <= 0 || !grid || !phi) return ctx->fail(PB_EINVAL, "pb_build_levelset: NULL or empty input");
+  if (!grid) return ctx->fail(PB_EINVAL, "pb_build_levelset: NULL grid");
   if (grid->nx < 7 || grid->ny < 7 || grid->nz < 7)
     return ctx->fail(PB_EINVAL, "pb_build_levelset: grid must be at least 7 nodes per axis");
+  if (grid->nx > kMaxAxis || grid->ny > kMaxAxis || grid->nz > kMaxAxis)
+    return ctx->fail(PB_EINVAL, "pb_build_levelset: grid axes hold at most %d nodes", kMaxAxis);
+  if (!std::isfinite(grid->origin[0]) || !std::isfinite(grid->origin[1]) || !std::isfinite(grid->origin[2]))
+    return ctx->fail(PB_EINVAL, "pb_build_levelset: non-finite grid origin");
   if (std::fabs(grid->h - prm->h) > 1e-12 * prm->h)
     return ctx->fail(PB_EINVAL, "pb_build_levelset: grid spacing differs from params.h");
+  const size_t count = (size_t)grid->nx * (size_t)grid->ny * (size_t)grid->nz;
+  if (count >= ((size_t)1 << 31)) return ctx->fail(PB_EINVAL, "pb_build_levelset: grid of 2^31 nodes or more");
+  if (needed) *needed = count;
+  if (!phi) return PB_OK;  // size query
+  if (cap < count)
+    return ctx->fail(PB_ECAPACITY, "pb_build_levelset: phi holds %zu doubles, the grid needs %zu", cap, count);
+  if (!atoms || n_atoms <= 0) return ctx->fail(PB_EINVAL, "pb_build_levelset: NULL or empty atoms");
   PB_HIP(ctx, hipSetDevice(ctx->device));
-  if ((int64_t)grid->nx * grid->ny * grid->nz >= ((int64_t)1 << 31))
-    return ctx->fail(PB_EINVAL, "pb_build_levelset: grid of 2^31 nodes or more");
   GridDev g{grid->nx, grid->ny, grid->nz, grid->origin[0], grid->origin[1], grid->origin[2], grid->h};
   int64_t total = (int64_t)g.nx * g.ny * g.nz;
   unsigned nb = blocks_for(total);
@@ -373,11 +349,8 @@ extern "C" pb_status pb_build_levelset(pb_ctx* ctx, const double* atoms, int n_a
       int a1 = ax == 0 ? 1 : 0, a2 = ax == 2 ? 1 : 2;
       Scope t(ctx, "levelset");
       const int64_t lines = n3[a1] * n3[a2];
-      if (n3[ax] <= 64 * kLineChunks)
-        k_cav_line<<<(unsigned)((lines + kLineWaves - 1) / kLineWaves), kBlock, 0, ctx->stream>>>(g, phi, outside,
-                                                                                                 ax, flags);
-      else
-        k_cav_sweep<<<blocks_for(lines), kBlock, 0, ctx->stream>>>(g, phi, outside, ax, flags);
+      k_cav_line<<<(unsigned)((lines + kLineWaves - 1) / kLineWaves), kBlock, 0, ctx->stream>>>(g, phi, outside, ax,
+                                                                                               flags);
     }
     PB_TRY(launch_ok(ctx, "cavity sweep"));
     int changed = 0;

@@ -541,13 +541,19 @@ extern "C" pb_status pb_ibim_solve(pb_ctx* ctx, const pb_band* band, const doubl
     return PB_OK;
   };
   bool fallback = false;
-  PB_TRY(run(opts.precond == PB_PRECOND_LEARNED ? &opnn : nullptr, opts.max_iter));
-  if (opts.precond == PB_PRECOND_LEARNED && (!std::isfinite(relres) || relres > opts.tol)) {
-    // plain GMRES judges the learned path: restart without the network from the last
-    // iterate (or from Λ⁻¹g if that iterate is not finite)
+  // the preconditioned pass gets at most half of the iteration budget, so that plain GMRES
+  // keeps at least the other half should the network fail
+  const bool use_prec = opts.precond == PB_PRECOND_LEARNED;
+  PB_TRY(run(use_prec ? &opnn : nullptr, use_prec ? opts.max_iter - opts.max_iter / 2 : opts.max_iter));
+  if (learned && (!std::isfinite(relres) || relres > opts.tol)) {
+    // plain GMRES judges the learned path (x0 = M(g) and/or the preconditioner M): restart
+    // without the network from the last iterate, or from Λ⁻¹g if that iterate is not finite,
+    // with what is left of the iteration budget (with none left, the residual of that
+    // iterate is still formed and reported)
     fallback = true;
     if (!std::isfinite(relres)) k_diag_solve<<<vb, kBlock, 0, ctx->stream>>>(n, g, d.lam1, d.lam2, p);
-    PB_TRY(run(nullptr, opts.max_iter));
+    PB_TRY(launch_ok(ctx, "fallback x0"));
+    PB_TRY(run(nullptr, std::max(opts.max_iter - iters, 0)));
   }
   PB_TRY(sync(ctx, "pb_ibim_solve"));
   if (stats) {

@@ -95,7 +95,7 @@ def load(path: str = LIB_PATH):
     L.pb_default_solve_opts.argtypes = [P(pb_solve_opts)]
     L.pb_default_solve_opts.restype = None
     L.pb_grid_for_atoms.argtypes = [vp, C.c_int, P(pb_params), P(pb_grid)]
-    L.pb_build_levelset.argtypes = [vp, vp, C.c_int, P(pb_params), P(pb_grid), vp]
+    L.pb_build_levelset.argtypes = [vp, vp, C.c_int, P(pb_params), P(pb_grid), vp, C.c_size_t, P(C.c_size_t)]
     L.pb_narrowband_compact.argtypes = [vp, P(pb_grid), vp, P(pb_params), P(pb_band)]
     L.pb_ibim_rhs.argtypes = [vp, P(pb_band), vp, C.c_int, P(pb_params), vp]
     L.pb_ibim_matvec.argtypes = [vp, P(pb_band), P(pb_params), C.c_int, vp, vp]
@@ -248,9 +248,14 @@ def grid_shape(g: pb_grid):
 
 def pb_build_levelset(ctx: Context, atoms: torch.Tensor, prm: pb_params, grid: pb_grid,
                       phi: torch.Tensor | None = None) -> torch.Tensor:
+    """φ on the grid. Without phi, the size comes from the library's size query (phi = NULL)."""
     if phi is None:
-        phi = torch.empty(grid.nx * grid.ny * grid.nz, dtype=torch.float64, device=atoms.device)
-    ctx.check(lib.pb_build_levelset(ctx.handle, _ptr(atoms), atoms.shape[0], C.byref(prm), C.byref(grid), _ptr(phi)))
+        need = C.c_size_t()
+        ctx.check(lib.pb_build_levelset(ctx.handle, None, 0, C.byref(prm), C.byref(grid), None, 0, C.byref(need)))
+        phi = torch.empty(need.value, dtype=torch.float64, device=atoms.device)
+    assert phi.dtype == torch.float64 and phi.is_contiguous()
+    ctx.check(lib.pb_build_levelset(ctx.handle, _ptr(atoms), atoms.shape[0], C.byref(prm), C.byref(grid), _ptr(phi),
+                                    phi.numel(), None))
     return phi
 
 

@@ -46,7 +46,7 @@ def test_default_params_are_the_papers():
 
     p = pb.params()
     assert (p.eps_in, p.eps_out, p.kappa, p.band_k, p.tau_k, p.probe) == (1.0, 80.0, 0.1257, 2.0, 1.0, 1.4)
-    assert (p.grad_scheme, p.jacobian) == (pb.PB_GRAD_CENTRAL, pb.PB_JAC_ONE)
+    assert (p.grad_scheme, p.jacobian) == (pb.PB_GRAD_WENO, pb.PB_JAC_ONE)
     # the C struct is no larger than its ctypes mirror: bytes past it stay untouched
     import ctypes as C
 
@@ -55,7 +55,7 @@ def test_default_params_are_the_papers():
     pb.lib.pb_default_params(C.cast(buf, C.POINTER(pb.pb_params)))
     assert bytes(buf[size:]) == b"\xa5" * 64
     q = C.cast(buf, C.POINTER(pb.pb_params)).contents
-    assert (q.jacobian, q.grad_scheme, q.reinit_steps, q.h) == (0, 0, 0, 0.5)
+    assert (q.jacobian, q.grad_scheme, q.reinit_steps, q.h) == (0, 1, 0, 0.5)
     o = pb.solve_opts()
     assert o.x0 == pb.PB_X0_DIAG and o.precision == pb.PB_FP64
 

@@ -1,10 +1,11 @@
 """GPU: the learned preconditioner's BF16 MFMA kernels against the FP64 CPU reference
 (oracle/nn_ref.py), its training, and what it gains over the method without it.
 
-Bars: neighbour lists bit-exact; features 1e-6; M(v) and the parameter gradients within a
-few BF16 units (2e-2 relative) of the reference evaluated with the same BF16 roundings;
-training lowers the loss; the learned solve never ends worse than plain GMRES (plain GMRES
-is the fallback) and reaches the same energy.
+Bars: neighbour lists bit-exact; features 1e-6; M(v) and the parameter gradients within
+1e-2 relative of the reference evaluated with the same BF16 roundings (BF16 operands,
+FP32 accumulation in another order); training lowers the loss; the learned solve never ends
+worse than plain GMRES (plain GMRES is the fallback, for the learned x0 alone as for the
+preconditioner, within the one iteration budget) and reaches the same energy.
 """
 import sys
 
@@ -95,7 +96,7 @@ def test_apply_matches_reference(pbm, ctx, small):
     diag = np.concatenate([v[:n] / 40.5, v[n:] / 0.50625])
     err = np.linalg.norm(p - ref) / np.linalg.norm(ref - diag)
     say(f"apply: correction rel err {err:.3e}")
-    assert err < 2e-2
+    assert err < 1e-2
     # an untrained network is exactly the diagonal solve
     net0 = pbm.Net(ctx, seed=5)
     p0 = pbm.pb_nn_apply(ctx, net0, small["band"], small["prm"], torch.tensor(v, device="cuda")).cpu().numpy()
@@ -124,7 +125,7 @@ def test_gradients_match_reference(pbm, ctx, small):
             a, b = g[off:off + size], rg[off:off + size]
             err = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
             say(f"grad block {off}:{off + size} rel err {err:.3e}")
-            assert err < 3e-2
+            assert err < 1e-2
             off += size
 
 
@@ -212,29 +213,84 @@ def test_batched_learned_matches_single(pbm, ctx, trained):
         assert bst.graph_replays < bst0.graph_replays
 
 
+def _nan_net(pbm, ctx):
+    """A network whose output is not finite: finite parameters of magnitude 1e30 with random
+    signs (the library refuses non-finite parameters), so the second layer's activations
+    overflow FP32 and the sums of opposite infinities give NaN."""
+    net = pbm.Net(ctx, seed=9)
+    signs = np.where(np.random.default_rng(12).random(pbm.Net.param_count()) < 0.5, -1.0, 1.0)
+    net.set_params((1e30 * signs).astype(np.float32))
+    return net
+
+
 def test_batched_learned_fallback(pbm, ctx, small):
     """A useless network: the batched learned run misses the tolerance and every molecule is
-    finished by plain GMRES from its last iterate, reported as fallback."""
+    finished by plain GMRES from its last iterate, reported as fallback, within the batch's
+    iteration budget."""
     net = pbm.Net(ctx, seed=9)
     net.set_params(_random_params(pbm, 10, scale_last=1.0) * 40.0)
     say("case: batched learned fallback, globules 12/30 atoms seeds 21/22, useless network, tol 1e-8")
     m2 = _band(pbm, ctx, synth.globule(30, 22))
     bands, ats = [small["band"], m2[2]], [small["at"], m2[1]]
     ps, stats, bst = pbm.pb_ibim_solve_batched(ctx, bands, ats, small["prm"], pbm.solve_opts(
-        tol=1e-8, precision=pbm.PB_MIXED, precond=pbm.PB_PRECOND_LEARNED, nn=net.handle, max_iter=60))
+        tol=1e-8, precision=pbm.PB_MIXED, precond=pbm.PB_PRECOND_LEARNED, nn=net.handle, max_iter=300))
     for i, st in enumerate(stats):
         say(f"  mol {i}: fallback {st.fallback_used} iters {st.iters} relres {st.true_relres:.2e}")
+        assert st.fallback_used == 1
         assert st.converged and st.true_relres <= 1e-8
 
 
+def test_batched_learned_x0_nonfinite_fallback(pbm, ctx, small):
+    """x0 = M(g) alone with a network that returns NaN: every molecule restarts from Λ⁻¹g
+    without the network and converges, reported as fallback."""
+    net = _nan_net(pbm, ctx)
+    say("case: batched learned x0 only, NaN network, globules 12/30 atoms seeds 21/22, tol 1e-8")
+    m2 = _band(pbm, ctx, synth.globule(30, 22))
+    bands, ats = [small["band"], m2[2]], [small["at"], m2[1]]
+    ps, stats, bst = pbm.pb_ibim_solve_batched(ctx, bands, ats, small["prm"], pbm.solve_opts(
+        tol=1e-8, precision=pbm.PB_MIXED, x0=pbm.PB_X0_LEARNED, nn=net.handle, max_iter=300))
+    for i, st in enumerate(stats):
+        say(f"  mol {i}: fallback {st.fallback_used} iters {st.iters} relres {st.true_relres:.2e}")
+        assert st.fallback_used == 1
+        assert st.converged and st.true_relres <= 1e-8 and np.isfinite(ps[i].cpu().numpy()).all()
+
+
 def test_fallback_to_plain_gmres(pbm, ctx, small):
+    """A useless preconditioner: the solve is finished by plain GMRES from the last iterate,
+    reported as fallback, and the two passes together stay within max_iter."""
     net = pbm.Net(ctx, seed=9)
     w = _random_params(pbm, 10, scale_last=1.0) * 40.0  # a useless network
     net.set_params(w)
     q, st = pbm.pb_ibim_solve(ctx, small["band"], small["at"], small["prm"], pbm.solve_opts(
-        tol=1e-8, precision=pbm.PB_MIXED, precond=pbm.PB_PRECOND_LEARNED, nn=net.handle, max_iter=60))
+        tol=1e-8, precision=pbm.PB_MIXED, precond=pbm.PB_PRECOND_LEARNED, nn=net.handle, max_iter=300))
     say(f"fallback: used={st.fallback_used} iters={st.iters} relres={st.true_relres:.2e}")
-    assert st.converged and st.true_relres <= 1e-8
+    assert st.fallback_used == 1
+    assert st.converged and st.true_relres <= 1e-8 and st.iters <= 300
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_learned_x0_nonfinite_fallback(pbm, ctx, small, precision):
+    """x0 = M(g) alone (no preconditioner) with a network that returns NaN: the solve restarts
+    from Λ⁻¹g without the network and converges within the same budget, reported as
+    fallback; with a budget too small to converge it still returns a finite iterate."""
+    net = _nan_net(pbm, ctx)
+    prec = pbm.PB_FP64 if precision == "fp64" else pbm.PB_MIXED
+    say(f"case: learned x0 only, NaN network, {precision}, globule 12 atoms, tol 1e-8")
+    base, st0 = pbm.pb_ibim_solve(ctx, small["band"], small["at"], small["prm"],
+                                  pbm.solve_opts(tol=1e-8, precision=prec))
+    q, st = pbm.pb_ibim_solve(ctx, small["band"], small["at"], small["prm"], pbm.solve_opts(
+        tol=1e-8, precision=prec, x0=pbm.PB_X0_LEARNED, nn=net.handle, max_iter=200))
+    say(f"  plain iters {st0.iters}; learned-x0 fallback={st.fallback_used} iters={st.iters} "
+        f"relres={st.true_relres:.2e}")
+    assert st.fallback_used == 1 and st.converged and st.true_relres <= 1e-8 and st.iters <= 200
+    e0 = pbm.pb_solvation_energy(ctx, small["band"], small["at"], small["prm"], base).g_pol
+    e1 = pbm.pb_solvation_energy(ctx, small["band"], small["at"], small["prm"], q).g_pol
+    assert e1 == pytest.approx(e0, rel=1e-7)
+    q2, st2 = pbm.pb_ibim_solve(ctx, small["band"], small["at"], small["prm"], pbm.solve_opts(
+        tol=1e-12, precision=prec, x0=pbm.PB_X0_LEARNED, nn=net.handle, max_iter=3), allow_noconv=True)
+    say(f"  budget 3: fallback={st2.fallback_used} iters={st2.iters} relres={st2.true_relres:.2e}")
+    assert st2.fallback_used == 1 and not st2.converged and st2.iters <= 3
+    assert np.isfinite(st2.true_relres) and np.isfinite(q2.cpu().numpy()).all()
 
 
 def test_committed_network_on_heldout_globule(pbm, ctx):
