@@ -226,6 +226,20 @@ pb_status pb_ibim_solve(pb_ctx* ctx, const pb_band* band, const double* atoms, i
 pb_status pb_solvation_energy(pb_ctx* ctx, const pb_band* band, const double* atoms, int n_atoms,
                               const pb_params* prm, const double* p, pb_energy* out, double* psi_rxn);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+   serving loops, harnesses that forbid allocation): pb_solvation_energy that allocates
+   nothing and does not synchronize. It launches the same kernels on the context stream and
+   writes the fields of pb_energy, in order (g_pol, g_pol_kcal, area), to out: device, 3
+   doubles, caller-owned, valid once the stream has reached the call. psi_rxn: device,
+   n_atoms doubles, or NULL, in which case ψ_rxn goes to a scratch array of the library's
+   (131072 doubles per device, one per GPU for the life of the process; located at pb_create).
+   PB_EINVAL beyond 131072 atoms with psi_rxn == NULL. Every call on one GPU that passes
+   psi_rxn == NULL shares that GPU's scratch array: such calls must not overlap in time
+   (different streams or host threads race on it); each call overwrites the entries it
+   uses before reading them. Results equal pb_solvation_energy's bit for bit. */
+pb_status pb_solvation_energy_noalloc(pb_ctx* ctx, const pb_band* band, const double* atoms, int n_atoms,
+                                      const pb_params* prm, const double* p, double* out, double* psi_rxn);
+
 /* Batched solve statistics (host). */
 typedef struct {
   double t_total_s;    /* wall time of the call, set-up included */

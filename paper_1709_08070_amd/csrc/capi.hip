@@ -257,6 +257,10 @@ pb_status pb_create(pb_ctx** out, int device, void* hip_stream) {
   c->stream = (hipStream_t)hip_stream;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->n_cu = prop.multiProcessorCount;
+  if (pb::noalloc_init(c) != PB_OK) {
+    delete c;
+    return PB_EDEVICE;
+  }
   *out = c;
   return PB_OK;
 }

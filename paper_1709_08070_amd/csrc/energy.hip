@@ -6,14 +6,28 @@
 //   at y = y_j*, with ρ = |z − y|, s = (z − y)·n_j: ∂G0/∂n(y) = s/(4πρ³),
 //   ∂Gκ/∂n(y) = e^{−κρ}(1+κρ) s/(4πρ³). G_pol = ½ Σ_k q_k ψ_rxn(z_k); area = h³ Σ_j ω_j.
 // All FP64. Reductions are fixed-order block trees (bitwise reproducible).
+//
+// pb_solvation_energy_noalloc runs the same kernels with no device allocation: ψ_rxn goes to
+// the caller's array or to the file-scope `scratch` array below, and the three results to a
+// caller-owned device array.
 #include <cmath>
+#include <mutex>
 
 #include "pb_internal.hpp"
+
+// ψ_rxn per atom for pb_solvation_energy_noalloc when the caller passes no array: 1 MiB
+// per device, held until the process ends. Host code never names it in a launch or copy;
+// it uses the address from hipGetSymbolAddress (pb::scratch_dev below).
+constexpr int kNoallocMaxAtoms = 1 << 17;
+static __device__ __align__(256) double scratch[kNoallocMaxAtoms];
 
 namespace pb {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kMaxDevices = 64;
+double* scratch_dev[kMaxDevices];  // device address of `scratch` per device ordinal
+std::mutex scratch_mu;
 
 __global__ void __launch_bounds__(kBlock) k_rhs(int n, const double* __restrict__ px, const double* __restrict__ py,
                                                 const double* __restrict__ pz, const double* __restrict__ nx,
@@ -88,7 +102,8 @@ __global__ void __launch_bounds__(kBlock) k_psi_rxn(int n, const double* __restr
   if (threadIdx.x == 0) psi[k] = red[0];
 }
 
-// out[0] = ½ Σ_k q_k ψ_k, out[1] = h³ Σ_j ω_j (one block, fixed order).
+// The fields of pb_energy in order: out[0] = G_pol = ½ Σ_k q_k ψ_k, out[1] = G_pol in kcal/mol,
+// out[2] = area = h³ Σ_j ω_j (one block, fixed order).
 __global__ void __launch_bounds__(kBlock) k_finish(int n_atoms, const double* __restrict__ atoms,
                                                    const double* __restrict__ psi, int n, const double* __restrict__ w,
                                                    double h3, double* __restrict__ out) {
@@ -107,12 +122,37 @@ __global__ void __launch_bounds__(kBlock) k_finish(int n_atoms, const double* __
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    out[0] = 0.5 * r1[0];
-    out[1] = h3 * r2[0];
+    const double gpol = 0.5 * r1[0];
+    out[0] = gpol;
+    out[1] = gpol * 4.0 * kPi * 332.0637;
+    out[2] = h3 * r2[0];
   }
 }
 
+// ψ_rxn at every atom and the energy and area into out (3 doubles, device), on ctx->stream.
+void energy_launch(pb_ctx* ctx, const pb_band* band, const double* atoms, int n_atoms, const Derived& d,
+                   const double* p, double* psi, double* out) {
+  const int n = (int)band->n;
+  k_psi_rxn<<<n_atoms, kBlock, 0, ctx->stream>>>(n, band->px, band->py, band->pz, band->nx, band->ny, band->nz,
+                                                 band->w, p, atoms, d.th1, d.kappa, d.h3, psi);
+  k_finish<<<1, kBlock, 0, ctx->stream>>>(n_atoms, atoms, psi, n, band->w, d.h3, out);
+}
+
 }  // namespace
+
+pb_status noalloc_init(pb_ctx* ctx) {
+  if (ctx->device < 0 || ctx->device >= kMaxDevices)
+    return ctx->fail(PB_EDEVICE, "device ordinal %d beyond %d", ctx->device, kMaxDevices);
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (scratch_dev[ctx->device]) return PB_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return ctx->fail(PB_EDEVICE, "address of the energy scratch array on device %d: %s", ctx->device,
+                     hipGetErrorString(e));
+  scratch_dev[ctx->device] = (double*)ptr;
+  return PB_OK;
+}
 
 pb_status rhs(pb_ctx* ctx, const pb_band* band, const double* atoms, int n_atoms, const Derived& d, double* g) {
   const int n = (int)band->n;
@@ -146,22 +186,44 @@ extern "C" pb_status pb_solvation_energy(pb_ctx* ctx, const pb_band* band, const
   if (!atoms || n_atoms <= 0 || !p || !out) return ctx->fail(PB_EINVAL, "pb_solvation_energy: NULL or empty input");
   PB_HIP(ctx, hipSetDevice(ctx->device));
   Derived d = derive(*prm);
-  const int n = (int)band->n;
   double* psi = psi_rxn ? psi_rxn : (double*)workspace(ctx, "en_psi", sizeof(double) * n_atoms);
-  double* res = (double*)workspace(ctx, "en_out", 2 * sizeof(double));
+  double* res = (double*)workspace(ctx, "en_out", 3 * sizeof(double));
   if (!psi || !res) return PB_ENOMEM;
   {
     Scope t(ctx, "energy");
-    k_psi_rxn<<<n_atoms, kBlock, 0, ctx->stream>>>(n, band->px, band->py, band->pz, band->nx, band->ny, band->nz,
-                                                   band->w, p, atoms, d.th1, d.kappa, d.h3, psi);
-    k_finish<<<1, kBlock, 0, ctx->stream>>>(n_atoms, atoms, psi, n, band->w, d.h3, res);
+    energy_launch(ctx, band, atoms, n_atoms, d, p, psi, res);
   }
   PB_TRY(launch_ok(ctx, "energy"));
-  double h[2];
+  double h[3];
   PB_HIP(ctx, hipMemcpyAsync(h, res, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
   PB_TRY(sync(ctx, "pb_solvation_energy"));
   out->g_pol = h[0];
-  out->g_pol_kcal = h[0] * 4.0 * kPi * 332.0637;
-  out->area = h[1];
+  out->g_pol_kcal = h[1];
+  out->area = h[2];
   return PB_OK;
+}
+
+extern "C" pb_status pb_solvation_energy_noalloc(pb_ctx* ctx, const pb_band* band, const double* atoms, int n_atoms,
+                                                 const pb_params* prm, const double* p, double* out,
+                                                 double* psi_rxn) {
+  using namespace pb;
+  if (!ctx) return PB_EINVAL;
+  PB_TRY(check_params(ctx, prm));
+  PB_TRY(check_band(ctx, band));
+  if (!atoms || n_atoms <= 0 || !p || !out)
+    return ctx->fail(PB_EINVAL, "pb_solvation_energy_noalloc: NULL or empty input");
+  if (!psi_rxn && n_atoms > kNoallocMaxAtoms)
+    return ctx->fail(PB_EINVAL,
+                     "pb_solvation_energy_noalloc: %d atoms exceed the scratch array (%d); pass psi_rxn",
+                     n_atoms, kNoallocMaxAtoms);
+  double* psi = psi_rxn;
+  if (!psi) {
+    // set at pb_create for this device
+    psi = ctx->device >= 0 && ctx->device < kMaxDevices ? scratch_dev[ctx->device] : nullptr;
+    if (!psi) return ctx->fail(PB_EDEVICE, "pb_solvation_energy_noalloc: no scratch address for device %d",
+                               ctx->device);
+  }
+  PB_HIP(ctx, hipSetDevice(ctx->device));
+  energy_launch(ctx, band, atoms, n_atoms, derive(*prm), p, psi, out);
+  return launch_ok(ctx, "pb_solvation_energy_noalloc");
 }

@@ -156,6 +156,9 @@ void flush_timers(pb_ctx* ctx);  // after a stream synchronize
 void drop_timers(pb_ctx* ctx, size_t mark);
 
 pb_status check_params(pb_ctx* ctx, const pb_params* p);
+// Looks up, once per device (the context's device current), the address of the energy scratch
+// array that pb_solvation_energy_noalloc uses; called by pb_create.
+pb_status noalloc_init(pb_ctx* ctx);
 pb_status check_band(pb_ctx* ctx, const pb_band* b);
 // PB_AVG_CURVED needs the band's curvature array.
 pb_status check_curv(pb_ctx* ctx, const pb_band* b, const pb_params* p);

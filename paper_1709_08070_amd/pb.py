@@ -32,7 +32,7 @@ EXPORTS = [
     "pb_grid_for_atoms", "pb_build_levelset", "pb_narrowband_compact", "pb_ibim_rhs", "pb_ibim_matvec",
     "pb_ibim_solve", "pb_solvation_energy", "pb_set_timing", "pb_kernel_time", "pb_tree_info", "pb_ibim_solve_batched",
     "pb_nn_create", "pb_nn_destroy", "pb_nn_param_count", "pb_nn_get_params", "pb_nn_set_params", "pb_nn_prepare",
-    "pb_nn_apply", "pb_nn_train_step", "pb_nn_geometry", "pb_far_kernel",
+    "pb_nn_apply", "pb_nn_train_step", "pb_nn_geometry", "pb_far_kernel", "pb_solvation_energy_noalloc",
 ]
 
 
@@ -101,6 +101,7 @@ def load(path: str = LIB_PATH):
     L.pb_ibim_matvec.argtypes = [vp, P(pb_band), P(pb_params), C.c_int, vp, vp]
     L.pb_ibim_solve.argtypes = [vp, P(pb_band), vp, C.c_int, P(pb_params), P(pb_solve_opts), vp, P(pb_solve_stats)]
     L.pb_solvation_energy.argtypes = [vp, P(pb_band), vp, C.c_int, P(pb_params), vp, P(pb_energy), vp]
+    L.pb_solvation_energy_noalloc.argtypes = [vp, P(pb_band), vp, C.c_int, P(pb_params), vp, vp, vp]
     L.pb_ibim_solve_batched.argtypes = [vp, C.c_int, P(pb_band), P(vp), P(C.c_int), P(pb_params), P(pb_solve_opts),
                                         P(vp), P(pb_solve_stats), P(pb_batch_stats)]
     L.pb_nn_create.argtypes = [vp, C.c_uint64, P(vp)]
@@ -333,6 +334,17 @@ def pb_solvation_energy(ctx: Context, band: Band, atoms: torch.Tensor, prm: pb_p
     s = band.struct()
     ctx.check(lib.pb_solvation_energy(ctx.handle, C.byref(s), _ptr(atoms), atoms.shape[0], C.byref(prm), _ptr(p),
                                       C.byref(out), _ptr(psi_rxn) if psi_rxn is not None else None))
+    return out
+
+
+def pb_solvation_energy_noalloc(ctx: Context, band: Band, atoms: torch.Tensor, prm: pb_params, p: torch.Tensor,
+                                out: torch.Tensor, psi_rxn: torch.Tensor | None = None) -> torch.Tensor:
+    """out (device, 3 doubles) receives (g_pol, g_pol_kcal, area) on the context stream; no
+    allocation, no synchronization."""
+    assert out.dtype == torch.float64 and out.numel() >= 3
+    s = band.struct()
+    ctx.check(lib.pb_solvation_energy_noalloc(ctx.handle, C.byref(s), _ptr(atoms), atoms.shape[0], C.byref(prm),
+                                              _ptr(p), _ptr(out), _ptr(psi_rxn) if psi_rxn is not None else None))
     return out
 
 
