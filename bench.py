@@ -2,25 +2,29 @@
 
 One step = the whole path over one synthetic molecule, inputs resident in HBM:
 level set of the SES (pb_build_levelset) → band compaction (pb_narrowband_compact) →
-mixed-precision GMRES with FP64 iterative refinement to ‖g − Ap‖/‖g‖ ≤ 1e-6
-(pb_ibim_solve, which also forms the right-hand side) → area and polarization energy
-(pb_solvation_energy).
+GMRES to ‖g − Ap‖/‖g‖ ≤ 1e-6 (pb_ibim_solve, which also forms the right-hand side): by
+default mixed precision with FP64 iterative refinement and the learned x0 and right
+preconditioner (the committed network), --step-solve mixed without the network → area and
+polarization energy (pb_solvation_energy).
+
+The default workload is the largest single-GPU configuration: the 5000-atom synthetic
+globule at h = 0.25 Å (638,391 band nodes).
 
 value = pair-interactions evaluated by the operator during the K timed steps ÷ their wall
 time (one pair-interaction = one ordered (target, source) evaluation of the 2×2 kernel
-block, n² per operator application).
+block, n² per dense operator application).
 
-Extra fields: the dominant kernel's roofline (FP32 pair kernel, HIP-event timed over the
-timed region), GMRES time-to-1e-6 of the mixed path and of the learned-preconditioned mixed
-path against plain FP64 GMRES on the same GPU, and the FP64 CPU oracle timed on the host
-on a bounded sample.
+Extra fields: the dominant kernel's roofline (the FP32 far-field kernel, HIP-event timed
+over the timed region; algorithmic FLOPs of the dense definition, with the executed counts
+of the committed counter summary beside them); GMRES time-to-1e-6 of plain FP64, mixed,
+learned + mixed, treecode and learned + treecode solves on the same band; the same on one
+held-out 5000-atom molecule at h = 0.5 (the learned-preconditioner configuration); one
+batched solve of 64 molecules with its per-molecule p50/p99 times; and the FP64 CPU oracle
+timed on the host on a bounded sample.
 
-Other workloads: globule5000 (the same step at 5000 atoms, h = 0.25), batch64 (64
-molecules per step through the batched solve, plain and learned), heldout5000 (time to
-1e-6 on held-out 5000-atom molecules at h = 0.5: FP64, mixed, learned + mixed).
-
-The learned network is the committed weights file (trained by `python -m
-paper_1709_08070_amd.learn`), or one trained in-process with --learned-train N.
+Other workloads: globule500 (the same step at 500 atoms, h = 0.5), batch64 (64 molecules
+per step through the batched solve, plain and learned), heldout5000 (time to 1e-6 on up to
+8 held-out 5000-atom molecules at h = 0.5).
 """
 from __future__ import annotations
 
@@ -42,8 +46,8 @@ METRIC = "BIM pair-interactions/s; GMRES time-to-1e-6 (learned+mixed vs plain FP
 WORKLOADS = {
     # name: (atoms, seed, h); batch64 is 64 globules with atom counts log-uniform over 50-2000;
     # heldout5000 is 8 globules of 5000 atoms, seeds 200000+i (never used in training)
-    "globule500": (500, 500, 0.5),
     "globule5000": (5000, 5000, 0.25),
+    "globule500": (500, 500, 0.5),
     "batch64": (None, 64000, 0.5),
     "heldout5000": (5000, 200000, 0.5),
 }
@@ -141,15 +145,20 @@ def load_net(ctx, args):
     return net, rec
 
 
-def timed_solve(ctx, band, at, prm, opts, q, warm=True):
-    """Wall time of one solve from x0 (after one untimed solve that warms the caches and the
-    far-field autotuner); returns (seconds, stats)."""
+def timed_solve(ctx, band, at, prm, opts, q, warm=True, warm_tol=None):
+    """Wall time of one solve from x0; returns (seconds, stats). warm: one untimed solve
+    first (it warms the caches, the workspace and the far-field autotuner), to warm_tol if
+    given (a loose tolerance: the same set-up for a fraction of the iterations)."""
     import torch
 
     from paper_1709_08070_amd import pb
 
     if warm:
-        pb.pb_ibim_solve(ctx, band, at, prm, opts, q)
+        o = opts
+        if warm_tol is not None:
+            o = pb.pb_solve_opts.from_buffer_copy(opts)
+            o.tol = warm_tol
+        pb.pb_ibim_solve(ctx, band, at, prm, o, q, allow_noconv=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     _, st = pb.pb_ibim_solve(ctx, band, at, prm, opts, q)
@@ -157,13 +166,54 @@ def timed_solve(ctx, band, at, prm, opts, q, warm=True):
     return time.perf_counter() - t1, st
 
 
-def bench_heldout(args):
-    """Time to 1e-6 on held-out 5000-atom globules (h = 0.5): plain FP64 GMRES, mixed
-    GMRES-IR, and mixed with the learned x0 and right preconditioner, the latter also with the
-    treecode far field as the inner operator."""
+def heldout_rows(ctx, net, seeds, tol):
+    """Time to tol on held-out 5000-atom globules at h = 0.5 (never in training): plain FP64
+    GMRES, mixed GMRES-IR, and mixed with the learned x0 and right preconditioner, also with
+    the treecode far field as the inner operator. Each solve after a warm-up at 1e-2."""
     import torch
 
     from paper_1709_08070_amd import pb, synth
+
+    n_atoms, _, h = WORKLOADS["heldout5000"]
+    prm = pb.params(h, ls_mode=pb.PB_LS_SES)
+    rows = []
+    for seed in seeds:
+        atoms = synth.globule(n_atoms, seed)
+        grid = pb.pb_grid_for_atoms(atoms, prm)
+        at = torch.tensor(atoms, dtype=torch.float64, device="cuda")
+        phi = pb.pb_build_levelset(ctx, at, prm, grid)
+        band = pb.pb_narrowband_compact(ctx, grid, phi, prm)
+        q = torch.zeros(2 * band.n, dtype=torch.float64, device="cuda")
+        row = {"seed": seed, "atoms": n_atoms, "h": h, "band_nodes": band.n}
+        for name, o in (("fp64", pb.solve_opts(tol=tol, precision=pb.PB_FP64)),
+                        ("mixed", pb.solve_opts(tol=tol, precision=pb.PB_MIXED)),
+                        ("learned_mixed", pb.solve_opts(tol=tol, precision=pb.PB_MIXED, x0=pb.PB_X0_LEARNED,
+                                                        precond=pb.PB_PRECOND_LEARNED, nn=net.handle)),
+                        ("learned_tree", pb.solve_opts(tol=tol, precision=pb.PB_TREE, x0=pb.PB_X0_LEARNED,
+                                                       precond=pb.PB_PRECOND_LEARNED, nn=net.handle))):
+            t, st = timed_solve(ctx, band, at, prm, o, q, warm_tol=1e-2)
+            row[name + "_s"] = t
+            row[name + "_iters"] = st.iters
+            row[name + "_relres"] = st.true_relres
+            if name.startswith("learned"):
+                row[name + "_fallback"] = st.fallback_used
+            if name == "learned_mixed":
+                row["learned_mixed_pairs"] = st.pairs
+            row[name + "_g_pol_kcal"] = pb.pb_solvation_energy(ctx, band, at, prm, q).g_pol_kcal
+        for name in ("mixed", "learned_mixed", "learned_tree"):
+            row[f"speedup_{name}_vs_fp64"] = row["fp64_s"] / row[name + "_s"]
+            row[f"energy_rel_diff_{name}_vs_fp64"] = abs(row[name + "_g_pol_kcal"] / row["fp64_g_pol_kcal"] - 1)
+        log(f"held-out {seed}: n={band.n} fp64 {row['fp64_s']:.3f}s/{row['fp64_iters']} it, mixed "
+            f"{row['mixed_s']:.3f}s/{row['mixed_iters']} it, learned {row['learned_mixed_s']:.3f}s/"
+            f"{row['learned_mixed_iters']} it (fallback {row['learned_mixed_fallback']}), learned tree "
+            f"{row['learned_tree_s']:.3f}s/{row['learned_tree_iters']} it")
+        rows.append(row)
+    return rows
+
+
+def bench_heldout(args):
+    """Time to 1e-6 on up to 8 held-out 5000-atom globules (h = 0.5)."""
+    from paper_1709_08070_amd import pb
 
     n_atoms, seed0, h = WORKLOADS["heldout5000"]
     ctx = pb.Context(0)
@@ -171,56 +221,23 @@ def bench_heldout(args):
     if net is None:
         log("heldout5000 needs a network: the weights file or --learned-train N")
         sys.exit(2)
-    prm = pb.params(h, ls_mode=pb.PB_LS_SES)
     n_mol = max(1, min(args.steps, 8))
-    rows, pairs, t_learned = [], 0.0, 0.0
-    for i in range(n_mol):
-        atoms = synth.globule(n_atoms, seed0 + i)
-        grid = pb.pb_grid_for_atoms(atoms, prm)
-        at = torch.tensor(atoms, dtype=torch.float64, device="cuda")
-        phi = pb.pb_build_levelset(ctx, at, prm, grid)
-        band = pb.pb_narrowband_compact(ctx, grid, phi, prm)
-        q = torch.zeros(2 * band.n, dtype=torch.float64, device="cuda")
-        row = {"seed": seed0 + i, "band_nodes": band.n}
-        for name, o in (("fp64", pb.solve_opts(tol=args.tol, precision=pb.PB_FP64)),
-                        ("mixed", pb.solve_opts(tol=args.tol, precision=pb.PB_MIXED)),
-                        ("learned_mixed", pb.solve_opts(tol=args.tol, precision=pb.PB_MIXED, x0=pb.PB_X0_LEARNED,
-                                                        precond=pb.PB_PRECOND_LEARNED, nn=net.handle)),
-                        ("learned_tree", pb.solve_opts(tol=args.tol, precision=pb.PB_TREE, x0=pb.PB_X0_LEARNED,
-                                                       precond=pb.PB_PRECOND_LEARNED, nn=net.handle))):
-            t, st = timed_solve(ctx, band, at, prm, o, q)
-            row[name + "_s"] = t
-            row[name + "_iters"] = st.iters
-            row[name + "_relres"] = st.true_relres
-            if name == "learned_tree":
-                row["learned_tree_fallback"] = st.fallback_used
-            if name == "learned_mixed":
-                row["learned_fallback"] = st.fallback_used
-                pairs += st.pairs
-                t_learned += t
-            row[name + "_g_pol_kcal"] = pb.pb_solvation_energy(ctx, band, at, prm, q).g_pol_kcal
-        log(f"held-out {i}: n={band.n} fp64 {row['fp64_s']:.2f}s/{row['fp64_iters']} it, mixed "
-            f"{row['mixed_s']:.2f}s/{row['mixed_iters']} it, learned {row['learned_mixed_s']:.2f}s/"
-            f"{row['learned_mixed_iters']} it (fallback {row['learned_fallback']}), learned tree "
-            f"{row['learned_tree_s']:.2f}s/{row['learned_tree_iters']} it")
-        rows.append(row)
+    rows = heldout_rows(ctx, net, [seed0 + i for i in range(n_mol)], args.tol)
 
     def mean(k):
         return sum(r[k] for r in rows) / len(rows)
 
     ttsol = {k: mean(k) for k in ("fp64_s", "mixed_s", "learned_mixed_s", "learned_tree_s", "fp64_iters",
                                   "mixed_iters", "learned_mixed_iters", "learned_tree_iters")}
-    ttsol["speedup_learned_tree_vs_fp64"] = ttsol["fp64_s"] / ttsol["learned_tree_s"]
-    ttsol["max_energy_rel_diff_learned_tree_vs_fp64"] = max(
-        abs(r["learned_tree_g_pol_kcal"] / r["fp64_g_pol_kcal"] - 1) for r in rows)
-    ttsol["speedup_mixed_vs_fp64"] = ttsol["fp64_s"] / ttsol["mixed_s"]
-    ttsol["speedup_learned_mixed_vs_fp64"] = ttsol["fp64_s"] / ttsol["learned_mixed_s"]
+    for name in ("mixed", "learned_mixed", "learned_tree"):
+        ttsol[f"speedup_{name}_vs_fp64"] = ttsol["fp64_s"] / ttsol[name + "_s"]
+        ttsol[f"max_energy_rel_diff_{name}_vs_fp64"] = max(r[f"energy_rel_diff_{name}_vs_fp64"] for r in rows)
     ttsol["speedup_learned_mixed_vs_mixed"] = ttsol["mixed_s"] / ttsol["learned_mixed_s"]
-    ttsol["max_energy_rel_diff_learned_vs_fp64"] = max(
-        abs(r["learned_mixed_g_pol_kcal"] / r["fp64_g_pol_kcal"] - 1) for r in rows)
-    ttsol["fallbacks"] = sum(r["learned_fallback"] for r in rows) + sum(r["learned_tree_fallback"] for r in rows)
+    ttsol["fallbacks"] = sum(r["learned_mixed_fallback"] + r["learned_tree_fallback"] for r in rows)
     ttsol["per_molecule"] = rows
     ttsol["network"] = rec
+    pairs = sum(r["learned_mixed_pairs"] for r in rows)
+    t_learned = sum(r["learned_mixed_s"] for r in rows)
     out = {
         "metric": METRIC, "value": pairs / t_learned, "unit": "pair-interactions/s", "n_gpus": 1,
         "steps": n_mol, "warmup": 1, "ms_per_step": 1e3 * t_learned / n_mol, "higher_is_better": True,
@@ -236,25 +253,20 @@ def bench_heldout(args):
     ctx.close()
 
 
-def bench_batch(args):
-    """64 molecules of uneven size: per step, every level set and band, then one batched
-    mixed-precision solve (persistent far-field launch, captured Arnoldi-step graph) and
-    every energy."""
+def batch_setup(ctx, prm):
+    """The 64 molecules of the batched workload: atoms, grids, level sets and bands."""
     import torch
 
     from paper_1709_08070_amd import pb, synth
 
-    _, seed0, h = WORKLOADS["batch64"]
+    _, seed0, _ = WORKLOADS["batch64"]
     sizes = synth.batch_sizes(64, seed0)
     mols = [synth.globule(n, seed0 + m) for m, n in enumerate(sizes)]
-    ctx = pb.Context(0)
-    prm = pb.params(h, ls_mode=pb.PB_LS_SES)
     grids, ats, phis, bands = [], [], [], []
     for atoms in mols:
         g = pb.pb_grid_for_atoms(atoms, prm)
         at = torch.tensor(atoms, dtype=torch.float64, device="cuda")
-        phi = torch.empty(g.nx * g.ny * g.nz, dtype=torch.float64, device="cuda")
-        pb.pb_build_levelset(ctx, at, prm, g, phi)
+        phi = pb.pb_build_levelset(ctx, at, prm, g)
         grids.append(g)
         ats.append(at)
         phis.append(phi)
@@ -262,6 +274,86 @@ def bench_batch(args):
     ns = [b.n for b in bands]
     log(f"batch64: atoms {min(sizes)}-{max(sizes)}, band nodes {min(ns)}-{max(ns)}, total {sum(ns)}, "
         f"sum n^2 {sum(float(n) * n for n in ns):.3e}")
+    return sizes, grids, ats, phis, bands
+
+
+def batch_learned(ctx, net, rec, prm, bands, ats, ps, tol, t_plain):
+    """One batched solve with the learned x0 and preconditioner (after a warm-up at 1e-2)."""
+    import torch
+
+    from paper_1709_08070_amd import pb
+
+    lopts = pb.solve_opts(tol=tol, precision=pb.PB_MIXED, x0=pb.PB_X0_LEARNED, precond=pb.PB_PRECOND_LEARNED,
+                          nn=net.handle)
+    lps = [torch.zeros_like(p) for p in ps]
+    warm = pb.pb_solve_opts.from_buffer_copy(lopts)
+    warm.tol = 1e-2
+    pb.pb_ibim_solve_batched(ctx, bands, ats, prm, warm, lps, allow_noconv=True)
+    torch.cuda.synchronize()
+    _, lstats, lbst = pb.pb_ibim_solve_batched(ctx, bands, ats, prm, lopts, lps)
+    rel = max(abs(pb.pb_solvation_energy(ctx, b, at, prm, q).g_pol / pb.pb_solvation_energy(ctx, b, at, prm, p).g_pol
+                  - 1) for b, at, q, p in zip(bands, ats, lps, ps))
+    learned = {"solve_s": lbst.t_total_s, "p50_solve_s": lbst.t_p50_s, "p99_solve_s": lbst.t_p99_s,
+               "graph_replays": lbst.graph_replays, "outer": lbst.outer,
+               "fallbacks": sum(st.fallback_used for st in lstats),
+               "max_relres": max(st.true_relres for st in lstats),
+               "max_energy_rel_diff_vs_plain": rel,
+               "speedup_vs_plain_batched": t_plain / lbst.t_total_s, "network": rec}
+    log(f"learned batch: replays={lbst.graph_replays} solve={lbst.t_total_s:.3f}s p50={lbst.t_p50_s:.3f}s "
+        f"p99={lbst.t_p99_s:.3f}s fallbacks={learned['fallbacks']} energy diff {rel:.2e}")
+    return learned, lps
+
+
+def batch_leg(net, rec, tol):
+    """The batched workload as a leg of the default run: one plain and one learned batched
+    solve of the 64 molecules (each after a warm-up at 1e-2), on a context of its own."""
+    import torch
+
+    from paper_1709_08070_amd import pb
+
+    _, _, h = WORKLOADS["batch64"]
+    ctx = pb.Context(0)
+    prm = pb.params(h, ls_mode=pb.PB_LS_SES)
+    sizes, grids, ats, phis, bands = batch_setup(ctx, prm)
+    ns = [b.n for b in bands]
+    ps = [torch.zeros(2 * n, dtype=torch.float64, device="cuda") for n in ns]
+    opts = pb.solve_opts(tol=tol, precision=pb.PB_MIXED)
+    warm = pb.pb_solve_opts.from_buffer_copy(opts)
+    warm.tol = 1e-2
+    pb.pb_ibim_solve_batched(ctx, bands, ats, prm, warm, ps, allow_noconv=True)
+    torch.cuda.synchronize()
+    _, stats, bst = pb.pb_ibim_solve_batched(ctx, bands, ats, prm, opts, ps)
+    log(f"batch64 leg: replays={bst.graph_replays} solve={bst.t_total_s:.3f}s p50={bst.t_p50_s:.3f}s "
+        f"p99={bst.t_p99_s:.3f}s max relres={max(st.true_relres for st in stats):.2e}")
+    out = {"molecules": len(ns), "atoms_range": [min(sizes), max(sizes)], "h": h,
+           "band_nodes_total": sum(ns), "band_nodes_range": [min(ns), max(ns)],
+           "sum_n2": sum(float(n) * n for n in ns), "solve_s": bst.t_total_s, "p50_solve_s": bst.t_p50_s,
+           "p99_solve_s": bst.t_p99_s, "graph_replays": bst.graph_replays, "pairs": bst.pairs,
+           "pairs_per_s": bst.pairs / bst.t_total_s, "far_symmetric": bst.far_symmetric,
+           "work_items": bst.n_items, "max_relres": max(st.true_relres for st in stats), "learned": None}
+    if net is not None:
+        # the network belongs to another context: load the same weights into this one
+        lnet = pb.Net(ctx, seed=1)
+        lnet.set_params(net.params())
+        out["learned"], _ = batch_learned(ctx, lnet, rec, prm, bands, ats, ps, tol, bst.t_total_s)
+        lnet.close()
+    ctx.close()
+    return out
+
+
+def bench_batch(args):
+    """64 molecules of uneven size: per step, every level set and band, then one batched
+    mixed-precision solve (persistent far-field launch, captured Arnoldi-step graph) and
+    every energy."""
+    import torch
+
+    from paper_1709_08070_amd import pb
+
+    _, seed0, h = WORKLOADS["batch64"]
+    ctx = pb.Context(0)
+    prm = pb.params(h, ls_mode=pb.PB_LS_SES)
+    sizes, grids, ats, phis, bands = batch_setup(ctx, prm)
+    ns = [b.n for b in bands]
     ps = [torch.zeros(2 * n, dtype=torch.float64, device="cuda") for n in ns]
     opts = pb.solve_opts(tol=args.tol, precision=pb.PB_MIXED)
 
@@ -291,25 +383,10 @@ def bench_batch(args):
             f"max relres={max(st.true_relres for st in stats):.2e}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    learned = None
+    learned, lps = None, None
     net, rec = load_net(ctx, args)
     if net is not None:
-        lopts = pb.solve_opts(tol=args.tol, precision=pb.PB_MIXED, x0=pb.PB_X0_LEARNED,
-                              precond=pb.PB_PRECOND_LEARNED, nn=net.handle)
-        lps = [torch.zeros_like(p) for p in ps]
-        pb.pb_ibim_solve_batched(ctx, bands, ats, prm, lopts, lps)  # warm
-        torch.cuda.synchronize()
-        _, lstats, lbst = pb.pb_ibim_solve_batched(ctx, bands, ats, prm, lopts, lps)
-        rel = max(abs(pb.pb_solvation_energy(ctx, b, at, prm, q).g_pol / pb.pb_solvation_energy(ctx, b, at, prm, p).g_pol
-                      - 1) for b, at, q, p in zip(bands, ats, lps, ps))
-        learned = {"solve_s": lbst.t_total_s, "p50_solve_s": lbst.t_p50_s, "p99_solve_s": lbst.t_p99_s,
-                   "graph_replays": lbst.graph_replays, "outer": lbst.outer,
-                   "fallbacks": sum(st.fallback_used for st in lstats),
-                   "max_relres": max(st.true_relres for st in lstats),
-                   "max_energy_rel_diff_vs_plain": rel,
-                   "speedup_vs_plain_batched": (sum(tsolve) / len(tsolve)) / lbst.t_total_s, "network": rec}
-        log(f"learned batch: replays={lbst.graph_replays} solve={lbst.t_total_s:.3f}s p50={lbst.t_p50_s:.3f}s "
-            f"p99={lbst.t_p99_s:.3f}s fallbacks={learned['fallbacks']} energy diff {rel:.2e}")
+        learned, lps = batch_learned(ctx, net, rec, prm, bands, ats, ps, args.tol, sum(tsolve) / len(tsolve))
     fp64 = None
     if "fp64" in [x for x in args.legs.split(",") if x] and not args.no_compare:
         # plain FP64 GMRES on the same 64 molecules, one after the other (x0 = Λ⁻¹g)
@@ -353,16 +430,47 @@ def bench_batch(args):
     ctx.close()
 
 
+def executed_counts(kernel: str, workload: str, pairs_per_launch: float, launch_s: float):
+    """Executed VALU work of the kernel from the committed rocprofv3 counter summary (only while
+    the kernel's source is unchanged), against the measured launch time."""
+    path = os.path.join(ROOT, "profiles", f"{kernel.replace('k_', '')}_{workload}_valu.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.split("#")[0].strip()
+    try:
+        if kernel_source_hash(os.path.join(ROOT, kv["source"])) != kv.get("source_sha256_16"):
+            return None
+        valu = float(kv["SQ_INSTS_VALU"])
+        fma, mul, add = (float(kv[f"SQ_INSTS_VALU_{x}_F32"]) for x in ("FMA", "MUL", "ADD"))
+        trans = float(kv["SQ_INSTS_VALU_TRANS_F32"])
+    except (KeyError, OSError, ValueError):
+        return None
+    flops = 64.0 * (2.0 * fma + mul + add)  # wave instructions × 64 lanes, FMA = 2
+    return {"source": os.path.relpath(path, ROOT), "valu_insts_per_pair": valu * 64.0 / pairs_per_launch,
+            "executed_fp32_tflops": flops / launch_s / 1e12, "frac_of_peak": flops / launch_s / PEAK_FP32,
+            "frac_of_nonpacked_ceiling": flops / launch_s / (PEAK_FP32 / 2),
+            "transcendentals_per_s": 64.0 * trans / launch_s}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="globule500", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="globule5000", choices=sorted(WORKLOADS))
     ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--step-solve", default="learned", choices=("learned", "mixed"),
+                    help="solve of each timed step: mixed GMRES-IR with the learned x0 and preconditioner "
+                         "(default), or without the network")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-compare", action="store_true", help="skip the FP64 time-to-solution comparison")
+    ap.add_argument("--no-compare", action="store_true", help="skip every time-to-solution leg")
     ap.add_argument("--no-tree", action="store_true", help="skip the treecode time-to-solution legs")
+    ap.add_argument("--no-heldout", action="store_true", help="skip the held-out learned-preconditioner leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-molecule leg")
     ap.add_argument("--legs", default="fp64,mixed,learned,tree,learned_tree",
                     help="time-to-solution legs, comma separated: fp64, mixed, learned, tree, learned_tree")
     ap.add_argument("--learned-train", type=int, default=0, metavar="N",
@@ -405,13 +513,18 @@ def main():
     prm = pb.params(h, ls_mode=pb.PB_LS_SES)
     grid = pb.pb_grid_for_atoms(atoms, prm)
     at = torch.tensor(atoms, dtype=torch.float64, device=dev)
-    phi = torch.empty(grid.nx * grid.ny * grid.nz, dtype=torch.float64, device=dev)
-    pb.pb_build_levelset(ctx, at, prm, grid, phi)
+    phi = pb.pb_build_levelset(ctx, at, prm, grid)
     band = pb.pb_narrowband_compact(ctx, grid, phi, prm)
     n = band.n
     p = torch.zeros(2 * n, dtype=torch.float64, device=dev)
-    opts = pb.solve_opts(tol=args.tol, precision=pb.PB_MIXED)
-    log(f"workload {args.workload}: atoms={n_atoms} grid={grid.nx}x{grid.ny}x{grid.nz} band nodes={n}")
+    net, rec = load_net(ctx, args)
+    if args.step_solve == "learned" and net is None:
+        log("--step-solve learned needs the network: the weights file or --learned-train N")
+        sys.exit(2)
+    learned_kw = dict(x0=pb.PB_X0_LEARNED, precond=pb.PB_PRECOND_LEARNED, nn=net.handle) if net else {}
+    opts = pb.solve_opts(tol=args.tol, precision=pb.PB_MIXED, **(learned_kw if args.step_solve == "learned" else {}))
+    log(f"workload {args.workload}: atoms={n_atoms} grid={grid.nx}x{grid.ny}x{grid.nz} band nodes={n}; "
+        f"step solve {args.step_solve}")
 
     def step():
         pb.pb_build_levelset(ctx, at, prm, grid, phi)
@@ -422,17 +535,18 @@ def main():
 
     for w in range(args.warmup):
         st, en = step()
-        log(f"warmup {w}: iters={st.iters} outer={st.outer} relres={st.true_relres:.2e}")
+        log(f"warmup {w}: iters={st.iters} outer={st.outer} relres={st.true_relres:.2e} fallback={st.fallback_used}")
     torch.cuda.synchronize()
     ctx.set_timing(2)  # events around the far-field launches only
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    pairs = 0.0
+    pairs, fallbacks = 0.0, 0
     for s in range(args.steps):
         st, en = step()
         pairs += st.pairs
+        fallbacks += st.fallback_used
         log(f"step {s}: iters={st.iters} outer={st.outer} fp64_mv={st.matvecs_fp64} mixed_mv={st.matvecs_mixed} "
-            f"relres={st.true_relres:.2e} G_pol={en.g_pol_kcal:.3f} kcal/mol")
+            f"relres={st.true_relres:.2e} fallback={st.fallback_used} G_pol={en.g_pol_kcal:.3f} kcal/mol")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     f32_ms, f32_n = ctx.kernel_time("p2p_f32")
@@ -443,16 +557,25 @@ def main():
     near_ms, near_n = ctx.kernel_time("near_f64")
     ctx.set_timing(0)
     value = pairs / elapsed
+    step_stats = {"iters": st.iters, "outer": st.outer, "matvecs_mixed": st.matvecs_mixed,
+                  "matvecs_fp64": st.matvecs_fp64, "true_relres": st.true_relres, "fallbacks": fallbacks,
+                  "g_pol_kcal": en.g_pol_kcal, "area": en.area, "pairs_per_step": pairs / max(args.steps, 1)}
 
     per_launch_s = f32_ms * 1e-3 / max(f32_n, 1)
-    achieved = FLOP_PER_PAIR * float(n) * float(n) / per_launch_s if f32_n else 0.0
+    pairs_launch = float(n) * float(n)
+    achieved = FLOP_PER_PAIR * pairs_launch / per_launch_s if f32_n else 0.0
     cfg = ctx.far_kernel(n)
     kname = "k_p2p_f32_sym" if cfg == 4 else "k_p2p_f32<%d, %d>" % ((256, 1), (512, 1), (256, 2), (512, 2))[cfg]
+    kfile = "k_p2p_f32_sym" if cfg == 4 else "k_p2p_f32"
     roofline = {"kernel": kname, "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP32,
-                "traffic": measured_traffic("k_p2p_f32_sym" if cfg == 4 else "k_p2p_f32", args.workload),
+                "traffic": measured_traffic(kfile, args.workload),
+                "basis": f"algorithmic: {FLOP_PER_PAIR} FP32 FLOP (FMA = 2) per ordered pair-interaction of the "
+                         "dense definition x n^2 per launch / HIP-event launch time; the kernel executes fewer "
+                         "(see executed)",
+                "executed": executed_counts(kfile, args.workload, pairs_launch, per_launch_s) if f32_n else None,
                 "avg_launch_ms": per_launch_s * 1e3, "launches": f32_n,
-                "pairs_per_s": float(n) * float(n) / per_launch_s if f32_n else 0.0,
+                "pairs_per_s": pairs_launch / per_launch_s if f32_n else 0.0,
                 "p2p_f64_avg_ms": f64_ms / max(f64_n, 1), "near_f64_avg_ms": near_ms / max(near_n, 1)}
 
     ttsol = None
@@ -461,10 +584,10 @@ def main():
         legs = [x for x in legs if "tree" not in x]
     if legs:
         ttsol = {}
-        net, rec = load_net(ctx, args) if any(x.startswith("learned") for x in legs) else (None, None)
-        learned_kw = dict(x0=pb.PB_X0_LEARNED, precond=pb.PB_PRECOND_LEARNED, nn=net.handle) if net else None
         # (name in the record, precision, learned?): FP64 GMRES, mixed GMRES-IR, and the treecode
-        # far field as the inner operator of the refinement (the exact FP64 residual stays outside)
+        # far field as the inner operator of the refinement (the exact FP64 residual stays outside).
+        # The FP64, mixed and learned solves run warm from the timed steps (same operator kernels
+        # and workspace); the treecode legs first build their plan in a solve to 1e-2.
         table = {"fp64": ("fp64", pb.PB_FP64, False), "mixed": ("mixed", pb.PB_MIXED, False),
                  "learned": ("learned_mixed", pb.PB_MIXED, True), "tree": ("tree", pb.PB_TREE, False),
                  "learned_tree": ("learned_tree", pb.PB_TREE, True)}
@@ -475,8 +598,9 @@ def main():
                 continue
             o = pb.solve_opts(tol=args.tol, precision=prec, **(learned_kw if learned else {}))
             q = torch.zeros_like(p)
-            log(f"time to {args.tol:g}: {name} solve (one warm-up, one timed)")
-            t, st = timed_solve(ctx, band, at, prm, o, q)
+            warm = prec == pb.PB_TREE
+            log(f"time to {args.tol:g}: {name} solve" + (" (after a warm-up to 1e-2)" if warm else ""))
+            t, st = timed_solve(ctx, band, at, prm, o, q, warm=warm, warm_tol=1e-2)
             ttsol[name + "_s"] = t
             ttsol[name + "_iters"] = st.iters
             ttsol[name + "_outer"] = st.outer
@@ -517,6 +641,18 @@ def main():
                 dense_equivalent_pairs_per_s=float(n) * n / (far_ms * 1e-3) if far_ms > 0 else None,
                 mean_batch=n / max(info["batches"], 1), **info)
 
+    heldout = None
+    if not args.no_compare and not args.no_heldout and net is not None:
+        # the learned-preconditioner configuration: a held-out 5000-atom molecule at h = 0.5
+        log("held-out 5000-atom globule (h = 0.5): fp64, mixed, learned mixed, learned treecode")
+        heldout = heldout_rows(ctx, net, [WORKLOADS["heldout5000"][1]], args.tol)[0]
+        heldout["network"] = rec
+
+    batch = None
+    if not args.no_compare and not args.no_batch:
+        log("batch of 64 molecules (h = 0.5): one plain and one learned batched solve")
+        batch = batch_leg(net, rec, args.tol)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -549,15 +685,18 @@ def main():
                "kind": "oracle", "sample": sample,
                "cpu_model": cpu_model(), "one_thread": one_thread_rate(oracle, nodes, oprm, x, cores)}
 
+    solve_desc = ("mixed GMRES-IR with the learned x0 and right preconditioner" if args.step_solve == "learned"
+                  else "mixed GMRES-IR")
     out = {
         "metric": METRIC, "value": value, "unit": "pair-interactions/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed * 1e3 / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "accumulate": "f64", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {n_atoms}-atom synthetic globule (seed {seed}), SES probe 1.4 A, "
-                               f"h={h} A, eps=2h, tau=h; level set + band + mixed GMRES-IR to {args.tol:g} + energy",
+                               f"h={h} A, eps=2h, tau=h; level set + band + {solve_desc} to {args.tol:g} + energy",
                    "band_nodes": n, "grid": [grid.nx, grid.ny, grid.nz], "parallelism": "single GPU"},
-        "roofline": roofline, "time_to_tol": ttsol, "cpu_baseline": cpu,
+        "roofline": roofline, "step": step_stats, "time_to_tol": ttsol, "heldout_c5": heldout, "batch_c4": batch,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     ctx.close()
