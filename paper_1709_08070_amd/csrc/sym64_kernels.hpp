@@ -13,9 +13,19 @@
 // regularized direction gets K11 = K21 = K22 = 0, K12 = K̄12. A pair at r = 0 is regularized in
 // both directions under every metric, so the shared radial terms are only used for r > 0.
 //
+// Far sub-block pairs. Under the guarded tangent metric no pair with r ≥ 2τ is regularized,
+// under the Euclidean one none with r ≥ τ. Sub-block pairs whose exact FP64 bounding boxes
+// (block reductions over the staged nodes) are farther apart than that radius, with a
+// relative margin of 1e-9 on its square that covers the rounding of the box gap and of r²,
+// skip the predicate: none of their pairs can take the regularized branch, so the geometry
+// may use fused multiply-adds and the selects drop out. The literal tangent metric can
+// regularize pairs at any distance and always runs the predicate.
+//
 // Work items and partial-sum ownership are those of the symmetric FP32 kernel (chunk pairs,
-// one owner per slot, fixed-order FP64 accumulation). The reverse sums travel with their
-// source across the lanes of a wave (ds_bpermute on the two halves of each double).
+// one owner per slot, fixed-order FP64 accumulation; forward sums held in registers over a
+// target sub-block's sources and stored once, reverse sums stored or added per sub-block
+// pair). The reverse sums travel with their source across the lanes of a wave (ds_bpermute
+// on the two halves of each double).
 #pragma once
 
 #include "sym_kernels.hpp"
@@ -25,7 +35,45 @@ namespace pb {
 struct Sym64Shared {
   double2 s0[kSymSub], s1[kSymSub], s2[kSymSub], s3[kSymSub];  // (x, y), (z, nx), (ny, nz), (wψ, wψn)
   double racc[kSymWaves][2][kSymSub];
+  double box[kSymWaves][6];  // per-wave bounding boxes (lo xyz, hi xyz) of a block reduction
 };
+
+// Bounding box over the block: each thread passes the box of its own points (empty: +∞/−∞);
+// every thread gets the block's. Every thread of the block calls it (it synchronizes).
+__device__ __forceinline__ void block_box(double (&lo)[3], double (&hi)[3], Sym64Shared& sh) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int off = 32; off > 0; off >>= 1)
+    for (int c = 0; c < 3; ++c) {
+      lo[c] = fmin(lo[c], __shfl_xor(lo[c], off));
+      hi[c] = fmax(hi[c], __shfl_xor(hi[c], off));
+    }
+  if (lane == 0)
+    for (int c = 0; c < 3; ++c) {
+      sh.box[w][c] = lo[c];
+      sh.box[w][3 + c] = hi[c];
+    }
+  __syncthreads();
+  for (int c = 0; c < 3; ++c) {
+    lo[c] = sh.box[0][c];
+    hi[c] = sh.box[0][3 + c];
+    for (int v = 1; v < kSymWaves; ++v) {
+      lo[c] = fmin(lo[c], sh.box[v][c]);
+      hi[c] = fmax(hi[c], sh.box[v][3 + c]);
+    }
+  }
+  __syncthreads();
+}
+
+// Squared gap between two boxes (0 if they overlap), FP64.
+__device__ __forceinline__ double box_gap2_f64(const double (&alo)[3], const double (&ahi)[3],
+                                               const double (&blo)[3], const double (&bhi)[3]) {
+  double g2 = 0.0;
+  for (int c = 0; c < 3; ++c) {
+    const double g = fmax(0.0, fmax(blo[c] - ahi[c], alo[c] - bhi[c]));
+    g2 += g * g;
+  }
+  return g2;
+}
 
 // Regularization decision for the direction whose target has tangential coordinate dn, for
 // a metric fixed at compile time.
@@ -39,25 +87,25 @@ __device__ __forceinline__ bool reg_f64(double r2, double dn, const KParams& kp)
 
 // e^{−z} for z ≥ 0 in FP64 without branches (Cody–Waite reduction): k = rint(−z·log2 e),
 // t = −z − k·ln2 with ln 2 = L_hi + L_lo (L_hi its nearest double, L_lo the remainder; the
-// products are exact inside the FMAs), |t| ≤ ln2/2, e^t by its Taylor series to degree 13
-// (truncation error below 1e-17 relative), then scaled by 2^k. z is clamped to 745, beyond which
-// e^{−z} is 0 in FP64.
+// products are exact inside the FMAs), |t| ≤ ln2/2, e^t by the degree-11 interpolant of e^t at
+// the 12 Chebyshev nodes of [−ln2/2, ln2/2] (near-minimax; relative error 1.7e-17 before
+// rounding, against 5.2e-18 for the Taylor series to degree 13, two terms longer; the
+// coefficients come from exp_coeffs.py beside this file), then scaled by 2^k. z is clamped to
+// 745, beyond which e^{−z} is 0 in FP64.
 __device__ __forceinline__ double exp_neg_f64(double z) {
   z = fmin(z, 745.0);
   const double k = __builtin_rint(-z * 1.4426950408889634);
   const double t = fma(-k, 2.3190468138462996e-17, fma(-k, 0.6931471805599453, -z));
-  double p = 1.0 / 6227020800.0;  // 1/13!
-  p = fma(p, t, 1.0 / 479001600.0);
-  p = fma(p, t, 1.0 / 39916800.0);
-  p = fma(p, t, 1.0 / 3628800.0);
-  p = fma(p, t, 1.0 / 362880.0);
-  p = fma(p, t, 1.0 / 40320.0);
-  p = fma(p, t, 1.0 / 5040.0);
-  p = fma(p, t, 1.0 / 720.0);
-  p = fma(p, t, 1.0 / 120.0);
-  p = fma(p, t, 1.0 / 24.0);
-  p = fma(p, t, 1.0 / 6.0);
-  p = fma(p, t, 0.5);
+  double p = 2.5110037605963777e-08;
+  p = fma(p, t, 2.763263963904103e-07);
+  p = fma(p, t, 2.755724091857897e-06);
+  p = fma(p, t, 2.4801485482328494e-05);
+  p = fma(p, t, 0.00019841269890047113);
+  p = fma(p, t, 0.0013888888952314775);
+  p = fma(p, t, 0.008333333333319601);
+  p = fma(p, t, 0.0416666666664881);
+  p = fma(p, t, 0.1666666666666668);
+  p = fma(p, t, 0.5000000000000019);
   p = fma(p, t, 1.0);
   p = fma(p, t, 1.0);
   return ldexp(p, (int)k);
@@ -105,27 +153,95 @@ __device__ __forceinline__ void pair_sym_f64(double xi, double yi, double zi, do
   g2 += rr ? 0.0 : g2r;
 }
 
+// Both directions of a pair that cannot be regularized (far sub-block pairs): the same
+// kernels as pair_sym_f64's regular branch, the products free to fuse.
+__device__ __forceinline__ void pair_sym_f64_far(double xi, double yi, double zi, double nxi, double nyi, double nzi,
+                                                 double wpi, double wni, const double2& s0, const double2& s1,
+                                                 const double2& s2, const double2& s3, const KParams& kp, double& f1,
+                                                 double& f2, double& g1, double& g2) {
+  const double xj = s0.x, yj = s0.y, zj = s1.x, nxj = s1.y, nyj = s2.x, nzj = s2.y, wpj = s3.x, wnj = s3.y;
+  const double dx = xi - xj, dy = yi - yj, dz = zi - zj;
+  const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+  const double dnx = fma(dz, nzi, fma(dy, nyi, dx * nxi));
+  const double dny = fma(dz, nzj, fma(dy, nyj, dx * nxj));
+  const double nn = fma(nzi, nzj, fma(nyi, nyj, nxi * nxj));
+  // 1/r: the hardware estimate and two Newton steps y ← y + y(½ − ½r²y²)
+  const double hr2 = 0.5 * r2;
+  double rinv = __builtin_amdgcn_rsq(r2);
+  rinv = fma(rinv, fma(-hr2 * rinv, rinv, 0.5), rinv);
+  rinv = fma(rinv, fma(-hr2 * rinv, rinv, 0.5), rinv);
+  const double ri2 = rinv * rinv;
+  const double r3 = ri2 * rinv;
+  const double z = kp.kappa * (r2 * rinv);
+  const double E = exp_neg_f64(z);
+  const double a = fma(E, z, E);                    // E(1 + z)
+  const double b = E * fma(z, z + 3.0, 3.0);        // E(3 + 3z + z²)
+  const double k12 = fma(-E, rinv, rinv);           // (1 − E)/r
+  const double k21 = r3 * fma(-(dnx * dny) * (3.0 - b), ri2, nn * (1.0 - a));
+  const double c1 = fma(-kp.th1, a, 1.0) * r3, c2 = fma(-kp.th2, a, 1.0) * r3;
+  f1 = fma(dny * c1, wpj, fma(-k12, wnj, f1));
+  f2 = fma(k21, wpj, fma(dnx * c2, wnj, f2));
+  g1 = fma(-(dnx * c1), wpi, fma(-k12, wni, g1));
+  g2 = fma(k21, wpi, fma(-(dny * c2), wni, g2));
+}
+
 __device__ __forceinline__ double shfl_next(double v, int addr) {
   const int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(v));
   const int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(v));
   return __hiloint2double(hi, lo);
 }
 
-// Targets [t0, t0 + 512) (full) against sources [s0, s0 + 512), s0 ≠ t0, both directions;
-// adds into fwd (index i − t0) and rev (index j − s0). wpsi/wpsn: h³ωψ/4π, h³ωψn/4π.
+// The pair loop of sym64_block: both directions of every pair between the thread's two
+// targets and the 512 staged sources; forward sums into f, reverse sums into sh.racc.
+template <int kMetric, bool kFar>
+__device__ __forceinline__ void sym64_loop(double xa, double ya, double za, double nxa, double nya, double nza,
+                                           double wpa, double wna, double xb, double yb, double zb, double nxb,
+                                           double nyb, double nzb, double wpb, double wnb, const KParams& kp,
+                                           Sym64Shared& sh, double (&f)[4]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int next = ((lane + 1) & 63) << 2;
+  for (int g = 0; g < kSymSub; g += 64) {
+    double ra1 = 0.0, ra2 = 0.0;  // at step s: the reverse sums of source g + ((lane + s) mod 64)
+    for (int s = 0; s < 64; ++s) {
+      const int q = g + ((lane + s) & 63);
+      const double2 c0 = sh.s0[q], c1 = sh.s1[q], c2 = sh.s2[q], c3 = sh.s3[q];
+      if (kFar) {
+        pair_sym_f64_far(xa, ya, za, nxa, nya, nza, wpa, wna, c0, c1, c2, c3, kp, f[0], f[1], ra1, ra2);
+        pair_sym_f64_far(xb, yb, zb, nxb, nyb, nzb, wpb, wnb, c0, c1, c2, c3, kp, f[2], f[3], ra1, ra2);
+      } else {
+        pair_sym_f64<kMetric>(xa, ya, za, nxa, nya, nza, wpa, wna, c0, c1, c2, c3, kp, f[0], f[1], ra1, ra2);
+        pair_sym_f64<kMetric>(xb, yb, zb, nxb, nyb, nzb, wpb, wnb, c0, c1, c2, c3, kp, f[2], f[3], ra1, ra2);
+      }
+      ra1 = shfl_next(ra1, next);
+      ra2 = shfl_next(ra2, next);
+    }
+    sh.racc[w][0][g + lane] = ra1;
+    sh.racc[w][1][g + lane] = ra2;
+  }
+}
+
+// Targets [t0, t0 + 512) (full; two per thread, t0 + 128w + l and 64 further, with bounding
+// box tlo/thi) against sources [s0, s0 + 512), s0 ≠ t0, both directions; adds the forward sums
+// into f and stores the reverse sums into rev (index j − s0), or adds them when rev_acc.
+// wpsi/wpsn: h³ωψ/4π, h³ωψn/4π.
 template <int kMetric>
 __device__ __forceinline__ void sym64_block(const BandDev& b, const double* __restrict__ wpsi,
                                             const double* __restrict__ wpsn, int n, int t0, int s0,
-                                            const KParams& kp, Sym64Shared& sh, double* fwd1, double* fwd2,
-                                            double* rev1, double* rev2, bool acc) {
+                                            const KParams& kp, Sym64Shared& sh, double (&f)[4],
+                                            const double (&tlo)[3], const double (&thi)[3], double* rev1,
+                                            double* rev2, bool rev_acc) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  double slo[3] = {INFINITY, INFINITY, INFINITY}, shi[3] = {-INFINITY, -INFINITY, -INFINITY};
   for (int q = tid; q < kSymSub; q += kBlock) {
     const int j = s0 + q;
     if (j < n) {
-      sh.s0[q] = make_double2(b.px[j], b.py[j]);
-      sh.s1[q] = make_double2(b.pz[j], b.nx[j]);
+      const double x = b.px[j], y = b.py[j], z = b.pz[j];
+      sh.s0[q] = make_double2(x, y);
+      sh.s1[q] = make_double2(z, b.nx[j]);
       sh.s2[q] = make_double2(b.ny[j], b.nz[j]);
       sh.s3[q] = make_double2(wpsi[j], wpsn[j]);
+      slo[0] = fmin(slo[0], x), slo[1] = fmin(slo[1], y), slo[2] = fmin(slo[2], z);
+      shi[0] = fmax(shi[0], x), shi[1] = fmax(shi[1], y), shi[2] = fmax(shi[2], z);
     } else {  // padding far away with zero weights: contributes exactly zero both ways
       sh.s0[q] = make_double2(1e30, 1e30);
       sh.s1[q] = make_double2(1e30, 0.0);
@@ -133,31 +249,19 @@ __device__ __forceinline__ void sym64_block(const BandDev& b, const double* __re
       sh.s3[q] = make_double2(0.0, 0.0);
     }
   }
+  block_box(slo, shi, sh);  // synchronizes: the staged sources are visible after it
+  const bool far = kMetric != PB_REG_TANGENT &&
+                   box_gap2_f64(tlo, thi, slo, shi) >=
+                       (kMetric == PB_REG_EUCLIDEAN ? kp.tau2 : kp.four_tau2) * (1.0 + 1e-9);
   const int ia = t0 + w * 128 + lane, ib = ia + 64;
   const double xa = b.px[ia], ya = b.py[ia], za = b.pz[ia], nxa = b.nx[ia], nya = b.ny[ia], nza = b.nz[ia];
   const double xb = b.px[ib], yb = b.py[ib], zb = b.pz[ib], nxb = b.nx[ib], nyb = b.ny[ib], nzb = b.nz[ib];
   const double wpa = wpsi[ia], wna = wpsn[ia], wpb = wpsi[ib], wnb = wpsn[ib];
+  if (far)
+    sym64_loop<kMetric, true>(xa, ya, za, nxa, nya, nza, wpa, wna, xb, yb, zb, nxb, nyb, nzb, wpb, wnb, kp, sh, f);
+  else
+    sym64_loop<kMetric, false>(xa, ya, za, nxa, nya, nza, wpa, wna, xb, yb, zb, nxb, nyb, nzb, wpb, wnb, kp, sh, f);
   __syncthreads();
-  double fa1 = 0.0, fa2 = 0.0, fb1 = 0.0, fb2 = 0.0;
-  const int next = ((lane + 1) & 63) << 2;
-  for (int g = 0; g < kSymSub; g += 64) {
-    double ra1 = 0.0, ra2 = 0.0;  // at step s: the reverse sums of source g + ((lane + s) mod 64)
-    for (int s = 0; s < 64; ++s) {
-      const int q = g + ((lane + s) & 63);
-      const double2 c0 = sh.s0[q], c1 = sh.s1[q], c2 = sh.s2[q], c3 = sh.s3[q];
-      pair_sym_f64<kMetric>(xa, ya, za, nxa, nya, nza, wpa, wna, c0, c1, c2, c3, kp, fa1, fa2, ra1, ra2);
-      pair_sym_f64<kMetric>(xb, yb, zb, nxb, nyb, nzb, wpb, wnb, c0, c1, c2, c3, kp, fb1, fb2, ra1, ra2);
-      ra1 = shfl_next(ra1, next);
-      ra2 = shfl_next(ra2, next);
-    }
-    sh.racc[w][0][g + lane] = ra1;
-    sh.racc[w][1][g + lane] = ra2;
-  }
-  __syncthreads();
-  fwd1[ia - t0] = fa1 + (acc ? fwd1[ia - t0] : 0.0);
-  fwd2[ia - t0] = fa2 + (acc ? fwd2[ia - t0] : 0.0);
-  fwd1[ib - t0] = fb1 + (acc ? fwd1[ib - t0] : 0.0);
-  fwd2[ib - t0] = fb2 + (acc ? fwd2[ib - t0] : 0.0);
   for (int q = tid; q < kSymSub; q += kBlock) {
     if (s0 + q < n) {
       double x1 = 0.0, x2 = 0.0;
@@ -165,18 +269,19 @@ __device__ __forceinline__ void sym64_block(const BandDev& b, const double* __re
         x1 += sh.racc[v][0][q];
         x2 += sh.racc[v][1][q];
       }
-      rev1[q] = x1 + (acc ? rev1[q] : 0.0);
-      rev2[q] = x2 + (acc ? rev2[q] : 0.0);
+      rev1[q] = x1 + (rev_acc ? rev1[q] : 0.0);
+      rev2[q] = x2 + (rev_acc ? rev2[q] : 0.0);
     }
   }
   __syncthreads();
 }
 
-// Targets [t0, t0 + 512) against the sources of the same sub-block (self pair included), one
-// direction with the per-pair kernel of the one-directional operator; adds into fwd.
+// Targets [t0, t0 + 512) (the same two per thread as sym64_block) against the sources of the
+// same sub-block (self pair included), one direction with the per-pair kernel of the
+// one-directional operator; adds into f.
 __device__ __forceinline__ void diag64_block(const BandDev& b, const double* __restrict__ wpsi,
                                              const double* __restrict__ wpsn, int n, int t0, const KParams& kp,
-                                             Sym64Shared& sh, double* fwd1, double* fwd2, bool acc) {
+                                             Sym64Shared& sh, double (&f)[4]) {
   const int tid = threadIdx.x;
   for (int q = tid; q < kSymSub; q += kBlock) {
     const int j = t0 + q;
@@ -190,7 +295,7 @@ __device__ __forceinline__ void diag64_block(const BandDev& b, const double* __r
   __syncthreads();
   const int m = min(kSymSub, n - t0);
   for (int h = 0; h < 2; ++h) {
-    const int i = t0 + tid + h * kBlock;
+    const int i = t0 + (tid >> 6) * 128 + (tid & 63) + 64 * h;
     if (i < n) {
       const double xi = b.px[i], yi = b.py[i], zi = b.pz[i], nxi = b.nx[i], nyi = b.ny[i], nzi = b.nz[i];
       double s1 = 0.0, s2 = 0.0;
@@ -198,8 +303,8 @@ __device__ __forceinline__ void diag64_block(const BandDev& b, const double* __r
         const double2 c0 = sh.s0[q], c1 = sh.s1[q], c2 = sh.s2[q], c3 = sh.s3[q];
         pair_f64(xi, yi, zi, nxi, nyi, nzi, c0.x, c0.y, c1.x, c1.y, c2.x, c2.y, c3.x, c3.y, kp, 0.0, s1, s2);
       }
-      fwd1[i - t0] = s1 + (acc ? fwd1[i - t0] : 0.0);
-      fwd2[i - t0] = s2 + (acc ? fwd2[i - t0] : 0.0);
+      f[2 * h] += s1;
+      f[2 * h + 1] += s2;
     }
   }
   __syncthreads();
@@ -213,33 +318,47 @@ __device__ __forceinline__ void sym64_item(const BandDev& b, const double* __res
   const int i0 = Ic * C, i1 = min(n, i0 + C), j0 = Jc * C, j1 = min(n, j0 + C);
   double* rowF = partial + (int64_t)Jc * 2 * n;
   double* rowR = partial + (int64_t)Ic * 2 * n;
-  const bool acc = nsub > 1;  // one sub-block per chunk: every owned slot is written once
-  if (acc) {
-    for (int e = threadIdx.x; e < i1 - i0; e += kBlock) {
-      rowF[i0 + e] = 0.0;
-      rowF[n + i0 + e] = 0.0;
-    }
-    if (Ic != Jc)
-      for (int e = threadIdx.x; e < j1 - j0; e += kBlock) {
-        rowR[j0 + e] = 0.0;
-        rowR[n + j0 + e] = 0.0;
+  const bool diag = Ic == Jc;
+  const int tid = threadIdx.x;
+  for (int T = i0; T < i1; T += kSymSub) {
+    const int ia = T + (tid >> 6) * 128 + (tid & 63), ib = ia + 64;
+    // bounding box of the target sub-block (exact FP64)
+    double tlo[3] = {INFINITY, INFINITY, INFINITY}, thi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int i : {ia, ib})
+      if (i < n) {
+        const double p3[3] = {b.px[i], b.py[i], b.pz[i]};
+        for (int c = 0; c < 3; ++c) {
+          tlo[c] = fmin(tlo[c], p3[c]);
+          thi[c] = fmax(thi[c], p3[c]);
+        }
       }
+    block_box(tlo, thi, sh);
+    double f[4] = {0.0, 0.0, 0.0, 0.0};
+    const bool rev_acc = T != i0;  // the first target sub-block stores the reverse slots
+    for (int S = (diag ? T : j0); S < j1; S += kSymSub) {
+      if (S == T)
+        diag64_block(b, wpsi, wpsn, n, T, kp, sh, f);
+      else if (kp.metric == PB_REG_EUCLIDEAN)
+        sym64_block<PB_REG_EUCLIDEAN>(b, wpsi, wpsn, n, T, S, kp, sh, f, tlo, thi, rowR + S, rowR + n + S, rev_acc);
+      else if (kp.metric == PB_REG_TANGENT)
+        sym64_block<PB_REG_TANGENT>(b, wpsi, wpsn, n, T, S, kp, sh, f, tlo, thi, rowR + S, rowR + n + S, rev_acc);
+      else
+        sym64_block<PB_REG_TANGENT_GUARDED>(b, wpsi, wpsn, n, T, S, kp, sh, f, tlo, thi, rowR + S, rowR + n + S,
+                                            rev_acc);
+    }
+    // forward sums, once per target sub-block (in a diagonal item the earlier target
+    // sub-blocks' reverse sums are already in these slots)
+    const bool fwd_acc = diag && T != i0;
+    if (ia < n) {
+      rowF[ia] = f[0] + (fwd_acc ? rowF[ia] : 0.0);
+      rowF[n + ia] = f[1] + (fwd_acc ? rowF[n + ia] : 0.0);
+    }
+    if (ib < n) {
+      rowF[ib] = f[2] + (fwd_acc ? rowF[ib] : 0.0);
+      rowF[n + ib] = f[3] + (fwd_acc ? rowF[n + ib] : 0.0);
+    }
     __syncthreads();
   }
-  for (int T = i0; T < i1; T += kSymSub)
-    for (int S = (Ic == Jc ? T : j0); S < j1; S += kSymSub) {
-      if (S == T)
-        diag64_block(b, wpsi, wpsn, n, T, kp, sh, rowF + T, rowF + n + T, acc);
-      else if (kp.metric == PB_REG_EUCLIDEAN)
-        sym64_block<PB_REG_EUCLIDEAN>(b, wpsi, wpsn, n, T, S, kp, sh, rowF + T, rowF + n + T, rowR + S, rowR + n + S,
-                                      acc);
-      else if (kp.metric == PB_REG_TANGENT)
-        sym64_block<PB_REG_TANGENT>(b, wpsi, wpsn, n, T, S, kp, sh, rowF + T, rowF + n + T, rowR + S, rowR + n + S,
-                                    acc);
-      else
-        sym64_block<PB_REG_TANGENT_GUARDED>(b, wpsi, wpsn, n, T, S, kp, sh, rowF + T, rowF + n + T, rowR + S,
-                                            rowR + n + S, acc);
-    }
 }
 
 // Symmetric FP64 operator of one band: one block per work item.

@@ -20,9 +20,11 @@
 // of the one-directional kernel, partial[c][e] = contributions to vector entry e from the
 // sources of chunk c. Item (Ic, Jc), Ic < Jc, owns the slots (Jc, i ∈ Ic) (forward) and
 // (Ic, j ∈ Jc) (reverse); the diagonal item (Ic, Ic) owns (Ic, i ∈ Ic). Every slot belongs to
-// exactly one item, which writes it (one sub-block per chunk) or zeroes it and then
-// accumulates into it in FP64 in a fixed order (several), so the result is bitwise
-// reproducible and needs no atomics in global memory.
+// exactly one item, which accumulates into it in FP64 in a fixed order, so the result is
+// bitwise reproducible and needs no atomics in global memory. The forward sums of a target
+// sub-block stay in registers over all the item's source sub-blocks and are stored once; the
+// reverse sums of a source sub-block are stored after its first target sub-block and added
+// to after each later one (a slot's first writer stores, the later ones add: no zeroing pass).
 //
 // Inside an item the block (256 threads, 4 waves) walks sub-blocks of 512 nodes: targets T
 // (2 per thread), sources S staged in LDS. For T ≠ S, lane l of a wave pairs its targets with
@@ -112,13 +114,15 @@ __device__ __forceinline__ void pair_fwd(const float4& ta, const float4& tn, con
   if (kScreened) fa1 = __fmaf_rn(-t.f0r, sa.w, fa1);
 }
 
-// Targets [t0, t0 + 512) (full, 2 per thread) against sources [s0, s0 + 512) of the same
-// records, s0 ≠ t0, both directions. Adds σ·S1, σ²·S2 into fwd (index i − t0) and rev (index
-// j − s0). Every thread of the block calls it (it synchronizes).
+// Targets [t0, t0 + 512) (full, 2 per thread: t0 + 128w + l and 64 further) against sources
+// [s0, s0 + 512) of the same records, s0 ≠ t0, both directions. Adds the unscaled forward sums
+// S1, S2 of the thread's two targets into f (a1, a2 of the first, then of the second); stores
+// σ·S1, σ²·S2 of the sources into rev (index j − s0), or adds them when rev_acc. Every thread
+// of the block calls it (it synchronizes).
 template <bool kScreened, bool kCheck>
-__device__ __forceinline__ void sym_block(const float4* __restrict__ A, const float4* __restrict__ N, int n, int t0, int s0, const F32Params& fp,
-                                          double sig1, double sig2, SymShared& sh, double* fwd1, double* fwd2,
-                                          double* rev1, double* rev2, bool acc) {
+__device__ __forceinline__ void sym_block(const float4* __restrict__ A, const float4* __restrict__ N, int n, int t0,
+                                          int s0, const F32Params& fp, double sig1, double sig2, SymShared& sh,
+                                          double (&f)[4], double* rev1, double* rev2, bool rev_acc) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   for (int q = tid; q < kSymSub; q += kBlock) {
     const int j = s0 + q;
@@ -134,7 +138,6 @@ __device__ __forceinline__ void sym_block(const float4* __restrict__ A, const fl
   const float4 taa = A[ia], tna = N[ia];
   const float4 tab = A[ib], tnb = N[ib];
   __syncthreads();
-  double fa1d = 0.0, fa2d = 0.0, fb1d = 0.0, fb2d = 0.0;
   const int next = ((lane + 1) & 63) << 2;  // byte address of lane l + 1 for ds_bpermute
   for (int g = 0; g < kSymSub; g += 64) {
     float fa1 = 0.f, fa2 = 0.f, fb1 = 0.f, fb2 = 0.f;
@@ -150,16 +153,12 @@ __device__ __forceinline__ void sym_block(const float4* __restrict__ A, const fl
     }
     sh.racc[w][0][g + lane] = ra1;  // 64 rotations: lane l holds source g + l
     sh.racc[w][1][g + lane] = ra2;
-    fa1d += (double)fa1;
-    fa2d += (double)fa2;
-    fb1d += (double)fb1;
-    fb2d += (double)fb2;
+    f[0] += (double)fa1;
+    f[1] += (double)fa2;
+    f[2] += (double)fb1;
+    f[3] += (double)fb2;
   }
   __syncthreads();
-  fwd1[ia - t0] = sig1 * fa1d + (acc ? fwd1[ia - t0] : 0.0);
-  fwd2[ia - t0] = sig2 * fa2d + (acc ? fwd2[ia - t0] : 0.0);
-  fwd1[ib - t0] = sig1 * fb1d + (acc ? fwd1[ib - t0] : 0.0);
-  fwd2[ib - t0] = sig2 * fb2d + (acc ? fwd2[ib - t0] : 0.0);
   for (int q = tid; q < kSymSub; q += kBlock) {
     if (s0 + q < n) {
       double x1 = 0.0, x2 = 0.0;
@@ -167,19 +166,19 @@ __device__ __forceinline__ void sym_block(const float4* __restrict__ A, const fl
         x1 += (double)sh.racc[v][0][q];
         x2 += (double)sh.racc[v][1][q];
       }
-      rev1[q] = sig1 * x1 + (acc ? rev1[q] : 0.0);
-      rev2[q] = sig2 * x2 + (acc ? rev2[q] : 0.0);
+      rev1[q] = sig1 * x1 + (rev_acc ? rev1[q] : 0.0);
+      rev2[q] = sig2 * x2 + (rev_acc ? rev2[q] : 0.0);
     }
   }
   __syncthreads();
 }
 
-// Targets [t0, t0 + 512) against the sources of the same sub-block, one direction, with the
-// near-pair predicate (the self pair and the nearest pairs are here). Adds into fwd.
+// Targets [t0, t0 + 512) (the same two per thread as sym_block) against the sources of the
+// same sub-block, one direction, with the near-pair predicate (the self pair and the nearest
+// pairs are here). Adds the unscaled sums into f.
 template <bool kScreened>
-__device__ __forceinline__ void diag_block(const float4* __restrict__ A, const float4* __restrict__ N, int n, int t0, const F32Params& fp,
-                                           double sig1, double sig2, SymShared& sh, double* fwd1, double* fwd2,
-                                           bool acc) {
+__device__ __forceinline__ void diag_block(const float4* __restrict__ A, const float4* __restrict__ N, int n, int t0,
+                                           const F32Params& fp, SymShared& sh, double (&f)[4]) {
   const int tid = threadIdx.x;
   for (int q = tid; q < kSymSub; q += kBlock) {
     const int j = t0 + q;
@@ -191,13 +190,12 @@ __device__ __forceinline__ void diag_block(const float4* __restrict__ A, const f
       sh.sN[q] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
   }
-  const int ia = t0 + tid, ib = ia + kBlock;
+  const int ia = t0 + (tid >> 6) * 128 + (tid & 63), ib = ia + 64;
   const float4 taa = ia < n ? A[ia] : make_float4(0.f, 0.f, 0.f, 0.f);
   const float4 tna = ia < n ? N[ia] : make_float4(0.f, 0.f, 1.f, 0.f);  // dead targets: results unused
   const float4 tab = ib < n ? A[ib] : make_float4(0.f, 0.f, 0.f, 0.f);
   const float4 tnb = ib < n ? N[ib] : make_float4(0.f, 0.f, 1.f, 0.f);
   __syncthreads();
-  double fa1d = 0.0, fa2d = 0.0, fb1d = 0.0, fb2d = 0.0;
   for (int g = 0; g < kSymSub; g += 64) {
     float fa1 = 0.f, fa2 = 0.f, fb1 = 0.f, fb2 = 0.f;
 #pragma unroll 4
@@ -206,18 +204,10 @@ __device__ __forceinline__ void diag_block(const float4* __restrict__ A, const f
       pair_fwd<kScreened>(taa, tna, sa, sn, fp, fa1, fa2);
       pair_fwd<kScreened>(tab, tnb, sa, sn, fp, fb1, fb2);
     }
-    fa1d += (double)fa1;
-    fa2d += (double)fa2;
-    fb1d += (double)fb1;
-    fb2d += (double)fb2;
-  }
-  if (ia < n) {
-    fwd1[ia - t0] = sig1 * fa1d + (acc ? fwd1[ia - t0] : 0.0);
-    fwd2[ia - t0] = sig2 * fa2d + (acc ? fwd2[ia - t0] : 0.0);
-  }
-  if (ib < n) {
-    fwd1[ib - t0] = sig1 * fb1d + (acc ? fwd1[ib - t0] : 0.0);
-    fwd2[ib - t0] = sig2 * fb2d + (acc ? fwd2[ib - t0] : 0.0);
+    f[0] += (double)fa1;
+    f[1] += (double)fa2;
+    f[2] += (double)fb1;
+    f[3] += (double)fb2;
   }
   __syncthreads();
 }
@@ -225,34 +215,27 @@ __device__ __forceinline__ void diag_block(const float4* __restrict__ A, const f
 // One work item (Ic, Jc), Ic ≤ Jc, of a band of n records with chunks of nsub sub-blocks.
 // partial: the band's chunked partial sums (slot (c, e) at partial[c·2n + e]).
 template <bool kScreened>
-__device__ __forceinline__ void sym_item(const float4* __restrict__ A, const float4* __restrict__ N, const float4* __restrict__ box, int n,
-                                         int Ic, int Jc, int nsub, const F32Params& fp, double sig1, double sig2,
-                                         double* __restrict__ partial, SymShared& sh) {
+__device__ __forceinline__ void sym_item(const float4* __restrict__ A, const float4* __restrict__ N,
+                                         const float4* __restrict__ box, int n, int Ic, int Jc, int nsub,
+                                         const F32Params& fp, double sig1, double sig2, double* __restrict__ partial,
+                                         SymShared& sh) {
   const int C = nsub * kSymSub;
   const int i0 = Ic * C, i1 = min(n, i0 + C), j0 = Jc * C, j1 = min(n, j0 + C);
   double* rowF = partial + (int64_t)Jc * 2 * n;  // slots (Jc, i): contributions of chunk Jc
   double* rowR = partial + (int64_t)Ic * 2 * n;  // slots (Ic, j): contributions of chunk Ic
-  // With one sub-block per chunk every owned slot is written exactly once (no zeroing, no
-  // read-back); with several, the owned slots are zeroed and then accumulated into.
-  const bool acc = nsub > 1;
-  if (acc) {
-    for (int e = threadIdx.x; e < i1 - i0; e += kBlock) {
-      rowF[i0 + e] = 0.0;
-      rowF[n + i0 + e] = 0.0;
-    }
-    if (Ic != Jc)
-      for (int e = threadIdx.x; e < j1 - j0; e += kBlock) {
-        rowR[j0 + e] = 0.0;
-        rowR[n + j0 + e] = 0.0;
-      }
-    __syncthreads();
-  }
+  const bool diag = Ic == Jc;
+  const int tid = threadIdx.x;
   for (int T = i0; T < i1; T += kSymSub) {
     float4 tlo, thi;
     box_union(box, T / kGroup, min(T + kSymSub, n + kGroup - 1) / kGroup, tlo, thi);
-    for (int S = (Ic == Jc ? T : j0); S < j1; S += kSymSub) {
+    double f[4] = {0.0, 0.0, 0.0, 0.0};
+    // reverse slots of the item's source sub-blocks: stored at the first target sub-block,
+    // added to at the later ones (in a diagonal item a sub-block's slots then also take its
+    // own forward sums, after every reverse contribution, since targets go in increasing order)
+    const bool rev_acc = T != i0;
+    for (int S = (diag ? T : j0); S < j1; S += kSymSub) {
       if (S == T) {
-        diag_block<kScreened>(A, N, n, T, fp, sig1, sig2, sh, rowF + T, rowF + n + T, acc);
+        diag_block<kScreened>(A, N, n, T, fp, sh, f);
         continue;
       }
       int clear = 0;
@@ -263,12 +246,23 @@ __device__ __forceinline__ void sym_item(const float4* __restrict__ A, const flo
       }
       clear = __builtin_amdgcn_readfirstlane(clear);
       if (clear)
-        sym_block<kScreened, false>(A, N, n, T, S, fp, sig1, sig2, sh, rowF + T, rowF + n + T, rowR + S,
-                                    rowR + n + S, acc);
+        sym_block<kScreened, false>(A, N, n, T, S, fp, sig1, sig2, sh, f, rowR + S, rowR + n + S, rev_acc);
       else
-        sym_block<kScreened, true>(A, N, n, T, S, fp, sig1, sig2, sh, rowF + T, rowF + n + T, rowR + S,
-                                   rowR + n + S, acc);
+        sym_block<kScreened, true>(A, N, n, T, S, fp, sig1, sig2, sh, f, rowR + S, rowR + n + S, rev_acc);
     }
+    // forward sums of the two targets of this thread, once per target sub-block; in a
+    // diagonal item the earlier target sub-blocks' reverse sums are already in these slots
+    const bool fwd_acc = diag && T != i0;
+    const int ia = T + (tid >> 6) * 128 + (tid & 63), ib = ia + 64;
+    if (ia < n) {
+      rowF[ia] = sig1 * f[0] + (fwd_acc ? rowF[ia] : 0.0);
+      rowF[n + ia] = sig2 * f[1] + (fwd_acc ? rowF[n + ia] : 0.0);
+    }
+    if (ib < n) {
+      rowF[ib] = sig1 * f[2] + (fwd_acc ? rowF[ib] : 0.0);
+      rowF[n + ib] = sig2 * f[3] + (fwd_acc ? rowF[n + ib] : 0.0);
+    }
+    __syncthreads();
   }
 }
 

@@ -92,6 +92,40 @@ def test_symmetric_matches_oracle_and_tiled(pbm, case):
     ctx.close()
 
 
+def test_symmetric_multi_subblock_chunks(pbm):
+    """A band above 51,200 nodes, where a chunk of the symmetric kernels holds several 512-node
+    sub-blocks (target sub-blocks keep their forward sums in registers over the chunk's
+    sources, reverse slots are stored by the first target sub-block and added to by the
+    later ones) and the last chunk is ragged; most sub-block pairs take the FP64 kernel's far
+    path. FP32 symmetric vs one-directional on every row (1e-6), FP64 symmetric vs
+    one-directional on every row (1e-13), both against the oracle on 64 sampled rows."""
+    import torch
+
+    say("case: symmetric kernels with multi-sub-block chunks, globule 1200 atoms seed 1200 h=0.5")
+    ctx = pbm.Context(0)
+    prm, at, band = _pipeline(pbm, ctx, synth.globule(1200, 1200), 0.5, True)
+    n = band.n
+    nsub = -(-n // (100 * 512))
+    say(f"  n={n}, sub-blocks per chunk {nsub}")
+    assert nsub >= 2 and n % (512 * nsub) != 0
+    p = torch.tensor(np.random.default_rng(11).normal(size=2 * n), device="cuda")
+    ys, yt = _mixed(pbm, 4, band, prm, p), _mixed(pbm, 2, band, prm, p)
+    zs, zt = _fp64(pbm, 1, band, prm, p), _fp64(pbm, 0, band, prm, p)
+    rel32 = np.linalg.norm(ys - yt) / np.linalg.norm(yt)
+    rel64 = np.linalg.norm(zs - zt) / np.linalg.norm(zt)
+    rows = np.random.default_rng(12).choice(n, 64, replace=False)
+    y1, y2 = oracle.matvec_rows(band.table(), oracle.params(0.5), p.cpu().numpy(), rows)
+    ref = np.concatenate([y1, y2])
+    o32 = np.linalg.norm(np.concatenate([ys[rows], ys[n + rows]]) - ref) / np.linalg.norm(ref)
+    got64 = np.concatenate([zs[rows], zs[n + rows]])
+    o64 = np.max(np.abs(got64 - ref)) / np.max(np.abs(ref))
+    say(f"  FP32 sym vs tiled {rel32:.3e}, vs oracle rows {o32:.3e}; FP64 sym vs tiled {rel64:.3e}, "
+        f"vs oracle rows (max) {o64:.3e}")
+    assert rel32 < 1e-6 and o32 < 1e-5
+    assert rel64 < 1e-13 and o64 < 1e-10
+    ctx.close()
+
+
 def test_symmetric_in_batched_solve(pbm):
     say("case: batched solve with the symmetric FP32 far field and FP64 operator, 3 globules (25/60/110 atoms), "
         "h=0.5, tol 1e-8")
