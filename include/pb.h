@@ -204,13 +204,15 @@ pb_status pb_ibim_rhs(pb_ctx* ctx, const pb_band* band, const double* atoms, int
    p, y: device, 2n; they must not overlap.
    PB_MIXED: FP32 far field + FP64 near field (every pair closer than r_c, the regularized
    ones included). The far-field kernel is chosen once per band size (per batch shape in
-   pb_ibim_solve_batched) by timing the candidates; the environment variable PB_FAR_CFG=k
+   pb_ibim_solve_batched) by timing the candidates (bands of 262,144 nodes or more take the
+   symmetric kernel without timing); the environment variable PB_FAR_CFG=k
    fixes it instead: k = 0..3 the one-directional kernel with (sources per LDS tile, targets
    per lane) = (256, 1), (512, 1), (256, 2), (512, 2); k = 4 the symmetric kernel (each
    unordered pair evaluated once for both directions). All give the same operator up to
    FP32 rounding; each is bitwise reproducible from run to run.
    PB_FP64: the same choice between the one-directional kernel (PB_F64_CFG=0) and the
-   symmetric one (PB_F64_CFG=1), which evaluates the regularization test per direction. */
+   symmetric one (PB_F64_CFG=1), which evaluates the regularization test per direction and
+   skips it on sub-block pairs too far apart for any pair to be regularized. */
 pb_status pb_ibim_matvec(pb_ctx* ctx, const pb_band* band, const pb_params* prm, int precision, const double* p,
                          double* y);
 

@@ -117,6 +117,11 @@ int far_max_chunks(pb_ctx* ctx, int n) {
 
 }  // namespace
 
+// Bands from this size on take the symmetric kernels without timing: they were the faster
+// ones at every band size timed (3281 to 638,391 nodes; 1.7× for FP32 and 1.8× for FP64 at
+// the largest), and one timed one-directional launch costs seconds at millions of nodes.
+constexpr int kTuneMaxN = 1 << 18;
+
 // Picks the far-field tile shape for a band of n nodes by timing each candidate once on the
 // packed records (after one warm-up launch); the choice is cached per n on the context.
 // PB_FAR_CFG=<index> in the environment fixes the choice instead.
@@ -134,6 +139,11 @@ pb_status far_autotune(pb_ctx* ctx, int n, bool screened, const float4* A, const
       *cfg_out = c;
       return PB_OK;
     }
+  }
+  if (n >= kTuneMaxN) {
+    ctx->far_cfg[n] = kSymCfg;
+    *cfg_out = kSymCfg;
+    return PB_OK;
   }
   hipEvent_t e0, e1;
   PB_HIP(ctx, hipEventCreate(&e0));
@@ -200,6 +210,11 @@ pb_status f64_autotune(pb_ctx* ctx, const pb_band* band, const double* wpsi, con
       *cfg_out = c;
       return PB_OK;
     }
+  }
+  if (n >= kTuneMaxN) {
+    ctx->f64_cfg[n] = 1;
+    *cfg_out = 1;
+    return PB_OK;
   }
   hipEvent_t e0, e1;
   PB_HIP(ctx, hipEventCreate(&e0));

@@ -1,6 +1,6 @@
 """GPU parity at full size: the 5000-atom globule at h = 0.25 (638,391 band nodes), the
-largest single-molecule workload, and the 500-atom globule at h = 0.5 that bench.py times by
-default, each in the launch configuration bench.py uses.
+largest single-molecule workload and the one bench.py times by default, and the 500-atom
+globule at h = 0.5, each in the launch configuration bench.py uses.
 
 The oracle cannot rerun the level set of a 14M-node grid in test time, so parity at this
 size rests on outputs it computes one by one from the GPU's own inputs:
@@ -9,12 +9,14 @@ size rests on outputs it computes one by one from the GPU's own inputs:
   * 64 sampled operator rows (FP64 path: 1e-10 of max|y|; mixed path: 1e-5 relative, with
     the autotuner's far-field kernel and with the symmetric and one-directional ones forced;
     the treecode operator with its packed target batches: 3e-5 relative);
-  * the mixed solve to 1e-6: its residual on the sampled rows recomputed by the oracle
-    (1e-5 relative), and the energy of its solution recomputed by the oracle (1e-10);
+  * the mixed solve to 1e-6, and the benchmark's step solve (mixed with the committed
+    network as x0 and right preconditioner): residual on the sampled rows recomputed by the
+    oracle (1e-5 relative), and the energy of the solution recomputed by the oracle (1e-10);
   * at the benchmark's size the same band, residual and energy checks for the mixed solve
     and for the learned solve with the committed network.
-The level-set kernels are compared node by node with the oracle at the smaller sizes of
-test_gpu_parity.py.
+The level set itself is compared node by node with the oracle's Stage 1 on a held-out
+5000-atom globule at h = 0.5 (a 2.3M-node grid, the learned-preconditioner workload): φ to
+1e-10 absolute, and the band of each side's φ bit-exact in its nodes.
 """
 import os
 import sys
@@ -117,6 +119,58 @@ def test_globule5000_sampled(pbm):
     oE, _ = oracle.energy(nodes, atoms, oprm, s)
     say(f"energy gpu {e_gpu:.12e} oracle {oE:.12e}, {time.perf_counter() - t0:.1f}s")
     assert e_gpu == pytest.approx(oE, rel=1e-10)
+    # the benchmark's step solve: the committed network as x0 and right preconditioner
+    wpath = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1709_08070_amd",
+                         "weights", "learned_h0.5.npz")
+    if os.path.exists(wpath):
+        net = pbm.Net(ctx, seed=1)
+        net.load(wpath)
+        lsol, lst = pbm.pb_ibim_solve(ctx, band, at, prm, pbm.solve_opts(
+            tol=1e-6, precision=pbm.PB_MIXED, x0=pbm.PB_X0_LEARNED, precond=pbm.PB_PRECOND_LEARNED, nn=net.handle))
+        say(f"learned mixed solve: iters={lst.iters} (plain {st.iters}) fallback={lst.fallback_used} "
+            f"relres={lst.true_relres:.2e}")
+        assert lst.converged and lst.true_relres <= 1e-6 and not lst.fallback_used and lst.iters < st.iters
+        ls = lsol.cpu().numpy()
+        b1, b2 = oracle.matvec_rows(nodes, oprm, ls, rows)
+        lres = np.concatenate([b1 - g[rows], b2 - g[n + rows]])
+        assert np.linalg.norm(lres) / np.linalg.norm(np.concatenate([g[rows], g[n + rows]])) < 1e-5
+        le = pbm.pb_solvation_energy(ctx, band, at, prm, lsol).g_pol
+        loE, _ = oracle.energy(nodes, atoms, oprm, ls)
+        say(f"learned energy gpu {le:.12e} oracle {loE:.12e}, {time.perf_counter() - t0:.1f}s")
+        assert le == pytest.approx(loE, rel=1e-10)
+        assert le == pytest.approx(oE, rel=1e-6)
+        net.close()
+    ctx.close()
+
+
+def test_heldout5000_levelset_node_by_node(pbm):
+    """Stage 1 on the held-out 5000-atom globule (seed 200000, h = 0.5; grid 150x133x116):
+    the GPU φ against the oracle's φ at every grid node (1e-10 absolute, the bar of the
+    smaller level-set tests), and the band of the GPU φ against the oracle's band of its own
+    φ (same nodes in the same order)."""
+    import torch
+
+    t0 = time.perf_counter()
+    say("case: level set node by node, held-out globule 5000 atoms seed 200000 h=0.5 SES")
+    ctx = pbm.Context(0)
+    atoms = synth.globule(5000, 200000)
+    prm = pbm.params(0.5, ls_mode=pbm.PB_LS_SES)
+    grid = pbm.pb_grid_for_atoms(atoms, prm)
+    at = torch.tensor(atoms, dtype=torch.float64, device="cuda")
+    phi = pbm.pb_build_levelset(ctx, at, prm, grid).cpu().numpy()
+    band = pbm.pb_narrowband_compact(ctx, grid, torch.tensor(phi, device="cuda"), prm)
+    dims, origin = (grid.nx, grid.ny, grid.nz), tuple(grid.origin)
+    odims, oorigin = oracle.grid(atoms, 0.5, oracle.grid_margin(atoms, 0.5))
+    assert dims == odims and np.allclose(origin, oorigin, rtol=0, atol=1e-12)
+    ophi, _ = oracle.ses(dims, origin, atoms, oracle.params(0.5))
+    diff = np.max(np.abs(phi - ophi))
+    say(f"grid {dims} ({phi.size} nodes): max |phi_gpu - phi_oracle| = {diff:.3e}, {time.perf_counter() - t0:.1f}s")
+    assert diff <= 1e-10
+    onodes, ogidx = oracle.band(dims, origin, 0.5, ophi, 1.0)
+    assert band.n == len(onodes)
+    np.testing.assert_array_equal(band.gidx[: band.n].cpu().numpy(), ogidx)
+    np.testing.assert_allclose(band.table(), onodes, rtol=0, atol=1e-9)
+    say(f"band of {band.n} nodes matches, {time.perf_counter() - t0:.1f}s")
     ctx.close()
 
 
