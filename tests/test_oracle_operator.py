@@ -141,13 +141,16 @@ def test_kirkwood_first_order_convergence():
     assert 1.6 < errs[0] / errs[1] < 2.6 and 1.6 < errs[1] / errs[2] < 2.6
 
 
-def _table2_rows():
+def _table2_rows(grid=64):
+    """The printed rows of the single-ion table for one grid size."""
     import os
     path = os.path.join(os.path.dirname(__file__), "golden", "table2_single_ion.txt")
     rows = []
     for line in open(path):
         if line.strip() and not line.startswith("#"):
-            rows.append([float(v) for v in line.split()])
+            row = [float(v) for v in line.split()]
+            if int(row[0]) == grid:
+                rows.append(row)
     return rows
 
 
