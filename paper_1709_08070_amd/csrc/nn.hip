@@ -19,6 +19,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "pair_kernels.hpp"
@@ -84,6 +85,13 @@ __device__ __forceinline__ bf16x8_t pack8(const float* v) {
 __device__ __forceinline__ bf16x8_t load8_bf16(const uint16_t* p) {
   short8_t s = *reinterpret_cast<const short8_t*>(p);
   return __builtin_bit_cast(bf16x8_t, s);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) {
+  const uint32_t u = (uint32_t)b << 16;
+  float f;
+  memcpy(&f, &u, 4);
+  return f;
 }
 
 __device__ __forceinline__ float act(float z) { return z > 0.f ? z : kSlope * z; }
@@ -230,18 +238,23 @@ __global__ void __launch_bounds__(kBlock) k_build_g1(int n, BandDev b, const int
 // ---------------------------------------------------------------- forward
 
 // Z = A·W + b for 16-node wave tiles; A rows are G1 (dense, BF16, K = 256) or the gathered
-// FP32 activations of the 16 neighbour slots (converted to BF16 per load). kAct applies the
-// leaky ReLU. Block = 4 waves = 64 nodes. The BF16 weights are staged in LDS in chunks of
+// BF16 activations of the 16 neighbour slots (8 channels, one 16-byte load per lane and
+// step). kAct (hidden layers) applies the leaky ReLU and stores BF16, rounded to nearest even
+// once here (the rounding every consumer applies: the next layer's MFMA operand and the
+// weight gradient's); the output layer stores FP32. Block = 4 waves = 64 nodes. The BF16 weights are staged in LDS in chunks of
 // kWChunk columns and shared by the block's four waves (each wave would otherwise stream the
 // whole matrix from the caches); rows are padded by 8 elements so that the 16 rows a wave
 // reads at one column offset fall on different banks.
 constexpr int kWChunk = 256;
 constexpr int kWPad = 8;
+constexpr int kFwdWaves = 8;  // 128 nodes per block: each staged weight chunk serves twice as many nodes
+constexpr int kFwdNodes = 16 * kFwdWaves;
 
 template <bool kDense, int CIN, int COUT, bool kAct>
-__global__ void __launch_bounds__(256) k_layer_fwd(int n, const uint16_t* __restrict__ G1, const float* __restrict__ X,
-                                                   const int* __restrict__ nbr, const uint16_t* __restrict__ Wt,
-                                                   const float* __restrict__ bias, float* __restrict__ Y,
+__global__ void __launch_bounds__(64 * kFwdWaves) k_layer_fwd(int n, const uint16_t* __restrict__ G1,
+                                                   const uint16_t* __restrict__ X, const int* __restrict__ nbr,
+                                                   const uint16_t* __restrict__ Wt, const float* __restrict__ bias,
+                                                   std::conditional_t<kAct, uint16_t, float>* __restrict__ Y,
                                                    const int* __restrict__ skip) {
   if (skip && *skip) return;
   constexpr int K = kSlots * CIN;
@@ -250,45 +263,53 @@ __global__ void __launch_bounds__(256) k_layer_fwd(int n, const uint16_t* __rest
   static_assert(K % KC == 0 && KC % 32 == 0, "whole chunks of 32-column steps");
   __shared__ uint16_t sW[COUT][KC + kWPad];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int node0 = (blockIdx.x * 4 + wave) * 16;
+  const int node0 = (blockIdx.x * kFwdWaves + wave) * 16;
   const int node = node0 + (lane & 15);
   const bool live = node < n;
   const int kq = 8 * (lane >> 4);
   f32x4_t acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  // the node's neighbour rows, looked up once (the gathered layers read every slot)
+  int rows[kSlots];
+#pragma unroll
+  for (int q = 0; q < kSlots; ++q) rows[q] = 0;
+  if (!kDense && live) {
+#pragma unroll
+    for (int q = 0; q < kSlots; q += 4) {
+      const int4 v = *reinterpret_cast<const int4*>(nbr + (int64_t)node * kSlots + q);
+      rows[q] = v.x, rows[q + 1] = v.y, rows[q + 2] = v.z, rows[q + 3] = v.w;
+    }
+  }
   for (int k0 = 0; k0 < K; k0 += KC) {
+    // this chunk's A operands, loaded before the weights are staged so that the gathers'
+    // latency overlaps the staging
+    bf16x8_t a[KC / 32];
+#pragma unroll
+    for (int u = 0; u < KC / 32; ++u) {
+      const int kk = k0 + u * 32 + kq;
+      if (!live) {
+        a[u] = __builtin_bit_cast(bf16x8_t, short8_t{0, 0, 0, 0, 0, 0, 0, 0});
+      } else if (kDense) {
+        a[u] = load8_bf16(G1 + (int64_t)node * K + kk);
+      } else {
+        a[u] = load8_bf16(X + (int64_t)rows[kk / CIN] * CIN + kk % CIN);
+      }
+    }
     __syncthreads();  // the previous chunk is no longer read
-    for (int e = threadIdx.x; e < COUT * KC / 8; e += 256) {
+    for (int e = threadIdx.x; e < COUT * KC / 8; e += 64 * kFwdWaves) {
       const int row = e / (KC / 8), col = (e % (KC / 8)) * 8;
       *reinterpret_cast<short8_t*>(&sW[row][col]) =
           *reinterpret_cast<const short8_t*>(Wt + (int64_t)row * K + k0 + col);
     }
     __syncthreads();
-    for (int kb = 0; kb < KC; kb += 32) {
-      const int kk = k0 + kb + kq;
-      bf16x8_t a;
-      if (kDense) {
-        if (live) a = load8_bf16(G1 + (int64_t)node * K + kk);
-        else {
-          const float zero[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-          a = pack8(zero);
-        }
-      } else {
-        float vals[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (live) {
-          const int slot = kk / CIN, c = kk % CIN;
-          const float* src = X + (int64_t)nbr[(int64_t)node * kSlots + slot] * CIN + c;
 #pragma unroll
-          for (int r = 0; r < 8; ++r) vals[r] = src[r];
-        }
-        a = pack8(vals);
-      }
+    for (int u = 0; u < KC / 32; ++u) {
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         const bf16x8_t bw = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const short8_t*>(
-                                                             &sW[t * 16 + (lane & 15)][kb + kq]));
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw, acc[t], 0, 0, 0);
+                                                             &sW[t * 16 + (lane & 15)][u * 32 + kq]));
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u], bw, acc[t], 0, 0, 0);
       }
     }
   }
@@ -300,7 +321,10 @@ __global__ void __launch_bounds__(256) k_layer_fwd(int n, const uint16_t* __rest
       const int nd = node0 + 4 * (lane >> 4) + r;
       if (nd < n) {
         const float z = acc[t][r] + bias[j];
-        Y[(int64_t)nd * COUT + j] = kAct ? act(z) : z;
+        if constexpr (kAct)
+          Y[(int64_t)nd * COUT + j] = bf16_bits(act(z));
+        else
+          Y[(int64_t)nd * COUT + j] = z;
       }
     }
   }
@@ -372,12 +396,13 @@ __global__ void __launch_bounds__(kBlock) k_loss(int n, const float* __restrict_
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-// dZ = dY ⊙ act'(Y) (hidden layers) or dY (output layer), as an FP32 array.
+// dZ = dY ⊙ act'(Y) (hidden layers; Y the stored BF16 activation, whose sign is that of the
+// pre-activation) or dY (output layer), as an FP32 array.
 template <bool kAct>
-__global__ void __launch_bounds__(kBlock) k_dz(int64_t total, const float* __restrict__ dY, const float* __restrict__ Y,
-                                               float* __restrict__ dZ) {
+__global__ void __launch_bounds__(kBlock) k_dz(int64_t total, const float* __restrict__ dY,
+                                               const uint16_t* __restrict__ Y, float* __restrict__ dZ) {
   for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < total; e += (int64_t)gridDim.x * kBlock)
-    dZ[e] = kAct ? dY[e] * dact(Y[e]) : dY[e];
+    dZ[e] = kAct ? dY[e] * dact(bf16_to_f32(Y[e])) : dY[e];
 }
 
 // Weight gradient partials over a chunk of nodes: dW_part[blk][k][j] = Σ_nodes A[node][k]·dZ[node][j],
@@ -385,7 +410,7 @@ __global__ void __launch_bounds__(kBlock) k_dz(int64_t total, const float* __res
 // wave per 16×16 (k, j) tile, tiles strided over the block's waves.
 template <bool kDense, int CIN, int COUT>
 __global__ void __launch_bounds__(256) k_wgrad(int n, int chunk, const uint16_t* __restrict__ G1,
-                                               const float* __restrict__ X, const int* __restrict__ nbr,
+                                               const uint16_t* __restrict__ X, const int* __restrict__ nbr,
                                                const float* __restrict__ dZ, float* __restrict__ dWp,
                                                float* __restrict__ dbp) {
   constexpr int K = kSlots * CIN;
@@ -400,24 +425,20 @@ __global__ void __launch_bounds__(256) k_wgrad(int n, int chunk, const uint16_t*
     const int slot = krow / CIN, c = krow % CIN;
     f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
     for (int nb = n0; nb < n1; nb += 32) {
-      float av[8], bv[8];
+      short8_t as;
+      float bv[8];
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
         const int nd = nb + nq + r;
         if (nd < n1) {
-          if (kDense) {
-            const uint32_t bits = (uint32_t)G1[(int64_t)nd * K + krow] << 16;
-            memcpy(&av[r], &bits, 4);
-          } else {
-            av[r] = X[(int64_t)nbr[(int64_t)nd * kSlots + slot] * CIN + c];
-          }
+          as[r] = (short)(kDense ? G1[(int64_t)nd * K + krow] : X[(int64_t)nbr[(int64_t)nd * kSlots + slot] * CIN + c]);
           bv[r] = dZ[(int64_t)nd * COUT + jcol];
         } else {
-          av[r] = 0.f;
+          as[r] = 0;
           bv[r] = 0.f;
         }
       }
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pack8(av), pack8(bv), acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, as), pack8(bv), acc, 0, 0, 0);
     }
     // lane holds D[k = kt·16 + 4·(lane/16) + r][j = jt·16 + lane%16]
 #pragma unroll
@@ -581,7 +602,7 @@ struct NNBufs {
   double* s;
   double* spart;
   uint16_t* G1;
-  float* X[kLayers];  // X[0] unused (layer 0 reads G1); X[l] = input of layer l; X[4] = output O
+  uint16_t* X[kLayers];  // BF16; X[0] unused (layer 0 reads G1); X[l] = input of layer l
   float* T;
   float* dY;
   float* dZ;
@@ -603,9 +624,9 @@ pb_status bufs(pb_ctx* ctx, int n, NNBufs& B) {
   B.spart = (double*)ws("nn_spart", sizeof(double) * 2 * kRedBlocks);
   B.G1 = (uint16_t*)ws("nn_G1", sizeof(uint16_t) * (size_t)n * kdim(0));
   B.X[0] = nullptr;
-  B.X[1] = (float*)ws("nn_X1", sizeof(float) * (size_t)n * 64);
-  B.X[2] = (float*)ws("nn_X2", sizeof(float) * (size_t)n * 64);
-  B.X[3] = (float*)ws("nn_X3", sizeof(float) * (size_t)n * 64);
+  B.X[1] = (uint16_t*)ws("nn_X1", sizeof(uint16_t) * (size_t)n * 64);
+  B.X[2] = (uint16_t*)ws("nn_X2", sizeof(uint16_t) * (size_t)n * 64);
+  B.X[3] = (uint16_t*)ws("nn_X3", sizeof(uint16_t) * (size_t)n * 64);
   B.T = (float*)ws("nn_T", sizeof(float) * (size_t)n * 2);
   B.dY = (float*)ws("nn_dY", sizeof(float) * (size_t)n * 64);
   B.dZ = (float*)ws("nn_dZ", sizeof(float) * (size_t)n * 64);
@@ -670,7 +691,7 @@ pb_status nn_apply(pb_ctx* ctx, const pb_nn* net, const pb_band* band, const Der
   float* O = out_buf(ctx, n);
   if (!O) return PB_ENOMEM;
   const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
-  const unsigned nbl = (unsigned)((n + 63) / 64);
+  const unsigned nbf = (unsigned)((n + kFwdNodes - 1) / kFwdNodes);
   Scope t(ctx, "nn");
   k_rms_partial<<<kRedBlocks, kBlock, 0, ctx->stream>>>(n, v, B.spart);
   k_rms_finish<<<1, kBlock, 0, ctx->stream>>>(n, kRedBlocks, B.spart, B.s);
@@ -678,13 +699,13 @@ pb_status nn_apply(pb_ctx* ctx, const pb_nn* net, const pb_band* band, const Der
       n, band_dev(band), B.nbr, B.feat, v, B.s, d.eps, B.G1);
   const uint16_t* wt = net->wt;
   const float* prm = net->params;
-  k_layer_fwd<true, 16, 64, true><<<nbl, 256, 0, ctx->stream>>>(n, B.G1, nullptr, B.nbr, wt + wbf_off(0),
+  k_layer_fwd<true, 16, 64, true><<<nbf, 64 * kFwdWaves, 0, ctx->stream>>>(n, B.G1, nullptr, B.nbr, wt + wbf_off(0),
                                                                  prm + b_off(0), B.X[1], ctx->skip);
-  k_layer_fwd<false, 64, 64, true><<<nbl, 256, 0, ctx->stream>>>(n, nullptr, B.X[1], B.nbr, wt + wbf_off(1),
+  k_layer_fwd<false, 64, 64, true><<<nbf, 64 * kFwdWaves, 0, ctx->stream>>>(n, nullptr, B.X[1], B.nbr, wt + wbf_off(1),
                                                                   prm + b_off(1), B.X[2], ctx->skip);
-  k_layer_fwd<false, 64, 64, true><<<nbl, 256, 0, ctx->stream>>>(n, nullptr, B.X[2], B.nbr, wt + wbf_off(2),
+  k_layer_fwd<false, 64, 64, true><<<nbf, 64 * kFwdWaves, 0, ctx->stream>>>(n, nullptr, B.X[2], B.nbr, wt + wbf_off(2),
                                                                   prm + b_off(2), B.X[3], ctx->skip);
-  k_layer_fwd<false, 64, 16, false><<<nbl, 256, 0, ctx->stream>>>(n, nullptr, B.X[3], B.nbr, wt + wbf_off(3),
+  k_layer_fwd<false, 64, 16, false><<<nbf, 64 * kFwdWaves, 0, ctx->stream>>>(n, nullptr, B.X[3], B.nbr, wt + wbf_off(3),
                                                                    prm + b_off(3), O, ctx->skip);
   k_apply_out<<<nb, kBlock, 0, ctx->stream>>>(n, v, O, B.s, d.lam1, d.lam2, p);
   return launch_ok(ctx, "nn apply");
@@ -710,7 +731,7 @@ pb_status nn_grads(pb_ctx* ctx, pb_nn* net, const pb_band* band, const Derived& 
   float* g = net->grads;
   const int64_t n64 = n;
   // layer 3 (output): dZ = dO
-  k_dz<false><<<ew, kBlock, 0, ctx->stream>>>(n64 * 16, dO, O, B.dZ);
+  k_dz<false><<<ew, kBlock, 0, ctx->stream>>>(n64 * 16, dO, nullptr, B.dZ);
   k_wgrad<false, 64, 16><<<nblk, 256, 0, ctx->stream>>>(n, kWgradChunk, nullptr, B.X[3], B.nbr, B.dZ, B.dWp,
                                                         B.dWp + (int64_t)nblk * 1024 * 16);
   k_sum_parts<<<ew, kBlock, 0, ctx->stream>>>(1024 * 16, nblk, B.dWp, g + w_off(3));
@@ -882,9 +903,9 @@ pb_status nn_batch_prepare(pb_ctx* ctx, int n_mol, const pb_band* bands, const i
   nb.s = (double*)ws("nnb_s", sizeof(double) * 2 * n_mol);
   nb.G1 = (uint16_t*)ws("nnb_G1", sizeof(uint16_t) * (size_t)ntot * kdim(0));
   nb.X[0] = nullptr;
-  nb.X[1] = (float*)ws("nnb_X1", sizeof(float) * 64 * (size_t)ntot);
-  nb.X[2] = (float*)ws("nnb_X2", sizeof(float) * 64 * (size_t)ntot);
-  nb.X[3] = (float*)ws("nnb_X3", sizeof(float) * 64 * (size_t)ntot);
+  nb.X[1] = (uint16_t*)ws("nnb_X1", sizeof(uint16_t) * 64 * (size_t)ntot);
+  nb.X[2] = (uint16_t*)ws("nnb_X2", sizeof(uint16_t) * 64 * (size_t)ntot);
+  nb.X[3] = (uint16_t*)ws("nnb_X3", sizeof(uint16_t) * 64 * (size_t)ntot);
   nb.O = (float*)ws("nnb_O", sizeof(float) * 16 * (size_t)ntot);
   if (!nb.off || !nb.cnt || !nb.pos || !nb.nbr || !nb.feat || !nb.s || !nb.G1 || !nb.X[1] || !nb.X[2] || !nb.X[3] ||
       !nb.O)
@@ -914,16 +935,16 @@ void nn_batch_apply(hipStream_t stream, const pb_nn* net, const NNBatch& nb, con
   k_rms_batch<<<nb.n_mol, kBlock, 0, stream>>>(nb.n_mol, nb.off, nb.cnt, V, ldv, kptr, kmax, nb.s);
   k_build_g1_batch<<<(unsigned)(((int64_t)ntot * kSlots + kBlock - 1) / kBlock), kBlock, 0, stream>>>(
       ntot, nb.mol_of, nb.off, nb.cnt, nb.pos, nb.nbr, nb.feat, V, ldv, kptr, kmax, nb.s, nb.eps, nb.G1);
-  const unsigned nbl = (unsigned)((ntot + 63) / 64);
+  const unsigned nbf = (unsigned)((ntot + kFwdNodes - 1) / kFwdNodes);
   const uint16_t* wt = net->wt;
   const float* prm = net->params;
-  k_layer_fwd<true, 16, 64, true><<<nbl, 256, 0, stream>>>(ntot, nb.G1, nullptr, nb.nbr, wt + wbf_off(0),
+  k_layer_fwd<true, 16, 64, true><<<nbf, 64 * kFwdWaves, 0, stream>>>(ntot, nb.G1, nullptr, nb.nbr, wt + wbf_off(0),
                                                           prm + b_off(0), nb.X[1], nullptr);
-  k_layer_fwd<false, 64, 64, true><<<nbl, 256, 0, stream>>>(ntot, nullptr, nb.X[1], nb.nbr, wt + wbf_off(1),
+  k_layer_fwd<false, 64, 64, true><<<nbf, 64 * kFwdWaves, 0, stream>>>(ntot, nullptr, nb.X[1], nb.nbr, wt + wbf_off(1),
                                                            prm + b_off(1), nb.X[2], nullptr);
-  k_layer_fwd<false, 64, 64, true><<<nbl, 256, 0, stream>>>(ntot, nullptr, nb.X[2], nb.nbr, wt + wbf_off(2),
+  k_layer_fwd<false, 64, 64, true><<<nbf, 64 * kFwdWaves, 0, stream>>>(ntot, nullptr, nb.X[2], nb.nbr, wt + wbf_off(2),
                                                            prm + b_off(2), nb.X[3], nullptr);
-  k_layer_fwd<false, 64, 16, false><<<nbl, 256, 0, stream>>>(ntot, nullptr, nb.X[3], nb.nbr, wt + wbf_off(3),
+  k_layer_fwd<false, 64, 16, false><<<nbf, 64 * kFwdWaves, 0, stream>>>(ntot, nullptr, nb.X[3], nb.nbr, wt + wbf_off(3),
                                                             prm + b_off(3), nb.O, nullptr);
   k_apply_out_batch<<<(unsigned)((ntot + kBlock - 1) / kBlock), kBlock, 0, stream>>>(
       ntot, nb.mol_of, nb.off, nb.cnt, V, Z, ldv, kptr, kmax, nb.O, nb.s, lam1, lam2);

@@ -192,7 +192,7 @@ struct NNBatch {
   float* feat = nullptr;        // ntot × 5 node features
   double* s = nullptr;          // per molecule: RMS of the two halves of the input
   uint16_t* G1 = nullptr;
-  float* X[4] = {};
+  uint16_t* X[4] = {};  // hidden activations, BF16
   float* O = nullptr;
 };
 pb_status nn_batch_prepare(pb_ctx* ctx, int n_mol, const pb_band* bands, const int* off_host, const int* mol_of,
