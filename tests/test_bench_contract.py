@@ -27,18 +27,31 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_traffic_only_for_the_profiled_source():
-    for kernel, src in (("k_p2p_f32_sym", "sym_kernels.hpp"), ("k_p2p_f32", "pair_kernels.hpp")):
-        path = os.path.join(ROOT, "profiles", f"{kernel.replace('k_', '')}_globule500_hbm.txt")
+    for kernel, src, workload in (("k_p2p_f32_sym", "sym_kernels.hpp", "globule5000"),
+                                  ("k_p2p_f32", "pair_kernels.hpp", "globule500")):
+        path = os.path.join(ROOT, "profiles", f"{kernel.replace('k_', '')}_{workload}_hbm.txt")
         kv = dict(line.split(" = ", 1) for line in open(path) if " = " in line and not line.startswith("#"))
         srcpath = os.path.join(ROOT, "paper_1709_08070_amd", "csrc", src)
         assert kv["source"].strip().endswith(src)
         assert bench.kernel_source_hash(srcpath) == kv["source_sha256_16"].split()[0]
-        assert bench.measured_traffic(kernel, "globule500") == float(kv["traffic_bytes"].split()[0])
+        assert bench.measured_traffic(kernel, workload) == float(kv["traffic_bytes"].split()[0])
         # traffic = fetch·scale + write·scale, in bytes (KiB counters)
         t = (float(kv["fetch_size_kib"].split()[0]) * float(kv["fetch_scale"].split()[0])
              + float(kv["write_size_kib"].split()[0]) * float(kv["write_scale"].split()[0])) * 1024
         assert abs(t - float(kv["traffic_bytes"].split()[0])) <= 1e-6 * t + 1.0
-    assert bench.measured_traffic("k_p2p_f32_sym", "globule5000") is None
+    # no summary for this kernel at this workload: no traffic figure
+    assert bench.measured_traffic("k_p2p_f32_sym", "globule500") is None
+
+
+def test_executed_counts_from_the_profiled_source():
+    """The executed VALU work of the dominant kernel comes from the committed counter summary,
+    only while its source is unchanged."""
+    n = 638391
+    ex = bench.executed_counts("k_p2p_f32_sym", "globule5000", float(n) * n, 193.32e-3)
+    assert ex is not None
+    assert 23.0 < ex["valu_insts_per_pair"] < 24.0
+    assert 0.0 < ex["frac_of_peak"] < ex["frac_of_nonpacked_ceiling"] <= 1.0
+    assert bench.executed_counts("k_p2p_f32_sym", "globule500", 1.0, 1.0) is None
 
 
 def test_one_thread_rate():
