@@ -19,7 +19,8 @@
 //
 // Mixed precision as in the single solve: each outer step forms the FP64 residual with the
 // persistent FP64 operator and solves the correction with the mixed operator, to
-// max(½·tol·‖g‖, η·‖r‖) or until a restart cycle stalls at the FP32 rounding level.
+// max(½·tol·‖g‖, η·‖r‖). A molecule whose cycle ends on its residual estimate leaves the
+// inner solve without a further mixed application: its FP64 residual follows.
 //
 // Learned path: the network runs over all molecules at once (their nodes concatenated,
 // neighbour lists offset to global indices). As right preconditioner it is applied inside
@@ -416,17 +417,14 @@ static __global__ void k_trisolve_batch(int n_mol, int m, const int* __restrict_
   }
 }
 
-// Start of a cycle: s = [β, 0, …], active, tolerance; one thread per molecule. After the
-// first cycle of an inner solve, a molecule whose last cycle ended on its residual estimate
-// but did not halve the true residual has stalled at the FP32 rounding level and stops.
-static __global__ void k_cycle_init(int n_mol, int m, int first, const double* __restrict__ beta,
+// Start of a cycle: s = [β, 0, …], active, tolerance; one thread per molecule.
+static __global__ void k_cycle_init(int n_mol, int m, const double* __restrict__ beta,
                                     const double* __restrict__ tol_abs, const int* __restrict__ want,
                                     double* __restrict__ s, KState* __restrict__ st, int* __restrict__ active,
                                     int* __restrict__ n_active, int* __restrict__ kptr) {
   const int mol = blockIdx.x * blockDim.x + threadIdx.x;
   if (mol == 0) *kptr = 0;
   if (mol >= n_mol) return;
-  const bool stalled = !first && st[mol].early && beta[mol] > 0.5 * st[mol].beta;
   double* sm = s + (int64_t)mol * (m + 1);
   for (int i = 0; i <= m; ++i) sm[i] = 0.0;
   sm[0] = beta[mol];
@@ -434,9 +432,17 @@ static __global__ void k_cycle_init(int n_mol, int m, int first, const double* _
   st[mol].tol_abs = tol_abs[mol];
   st[mol].k_used = 0;
   st[mol].early = 0;
-  const int a = want[mol] && beta[mol] > tol_abs[mol] && !stalled;
+  const int a = want[mol] && beta[mol] > tol_abs[mol];
   active[mol] = a;
   if (a) atomicAdd(n_active, 1);
+}
+
+// End of a cycle: a molecule whose cycle ended on its residual estimate leaves the inner
+// solve (the refinement forms its FP64 residual next); the others restart. One thread per
+// molecule.
+static __global__ void k_drop_early(int n_mol, const KState* __restrict__ st, int* __restrict__ cycle) {
+  const int mol = blockIdx.x * blockDim.x + threadIdx.x;
+  if (mol < n_mol && st[mol].early) cycle[mol] = 0;
 }
 
 static __global__ void __launch_bounds__(kBlock) k_fill_mol(int* mol_of, int off, int n, int m) {
@@ -1075,9 +1081,9 @@ extern "C" pb_status pb_ibim_solve_batched(pb_ctx* ctx, int n_mol, const pb_band
     // sol = 0, so the first residual is the right-hand side itself
     k_copy<<<vb, kBlock, 0, B.st>>>(B.M, rhs_vec, rr);
     norms(B, rr, want, rn);
-    for (int first = 1;; first = 0) {
+    for (;;) {
       PB_HIP(ctx, hipMemsetAsync(B.n_active, 0, sizeof(int), B.st));
-      k_cycle_init<<<(n_mol + 63) / 64, 64, 0, B.st>>>(n_mol, m, first, rn, tolabs, want, B.s, B.kst, B.active,
+      k_cycle_init<<<(n_mol + 63) / 64, 64, 0, B.st>>>(n_mol, m, rn, tolabs, want, B.s, B.kst, B.active,
                                                       B.n_active, B.kptr);
       PB_HIP(ctx, hipMemcpyAsync(B.cycle, B.active, sizeof(int) * n_mol, hipMemcpyDeviceToDevice, B.st));
       int nact = 0;
@@ -1111,11 +1117,18 @@ extern "C" pb_status pb_ibim_solve_batched(pb_ctx* ctx, int n_mol, const pb_band
           maxk = std::max(maxk, ks[i].k_used);
         }
       iters_total += maxk;
-      // true residual of the correction equation with the mixed operator: r = rhs − A sol
+      // molecules that restart: the true residual of the correction equation with the mixed
+      // operator, r = rhs − A sol
+      int nrestart = 0;
+      for (int i = 0; i < n_mol; ++i)
+        if (cyc_h[i] && !ks[i].early) {
+          mvmx[i] += 1;
+          ++nrestart;
+        }
+      if (nrestart == 0) break;
+      k_drop_early<<<(n_mol + 63) / 64, 64, 0, B.st>>>(n_mol, B.kst, B.cycle);
       op_mixed(B, sol, rr, nullptr, 0, B.cycle);
       k_resid_keep<<<nbn, kBlock, 0, B.st>>>(B.ntot, B.mol_of, B.mols, B.cycle, rhs_vec, rr);
-      for (int i = 0; i < n_mol; ++i)
-        if (cyc_h[i]) mvmx[i] += 1;
       norms(B, rr, B.cycle, rn);
       PB_TRY(launch_ok(ctx, "batch cycle"));
       want = B.cycle;

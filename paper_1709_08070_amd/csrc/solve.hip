@@ -9,8 +9,8 @@
 // Mixed precision: GMRES on A_mixed x = g from the initial guess, then iterative refinement:
 // form the true FP64 residual r = g − A₆₄x and, while it misses tol, solve A_mixed d = r and
 // set x ← x + d. Each inner solve stops at max(½·tol·‖g‖, η·‖r₀‖), r₀ its initial residual
-// and η = kInnerEta, or when a restart cycle that ended on its residual estimate did not halve
-// the true residual (the estimate has reached the FP32 rounding level).
+// and η = kInnerEta. Its last cycle ends on the Arnoldi residual estimate: the inner operator
+// is not applied to the result again, since the refinement forms the better residual next.
 #include <chrono>
 #include <cmath>
 #include <functional>
@@ -277,8 +277,9 @@ struct SkipGuard {
 
 // Restarted GMRES(m) for A x = b from the given x until ‖b − Ax‖ ≤ max(tol_abs, rel·‖b − Ax₀‖)
 // (estimate, then confirmed with the operator at each restart) or max_iter operator
-// applications. With rel > 0 (an inexact operator) the solve also ends when a cycle that
-// stopped on its estimate did not halve the true residual.
+// applications. With rel > 0 the solve is the inner solve of a refinement whose caller forms
+// a more accurate residual of the result next: a cycle that stops on its estimate ends the
+// solve without the confirming application, and *res_out is that estimate.
 // With prec (flexible GMRES, right preconditioning): z_k = prec(v_k), w = A z_k, and the
 // update is x += Z y; the preconditioner may change from step to step (it may be nonlinear).
 //
@@ -310,12 +311,8 @@ pb_status gmres(pb_ctx* ctx, Krylov& K, const OpFn& op, const OpFn* prec, const 
   PB_TRY(norm2(ctx, K, r, &beta));
   tol_abs = std::fmax(tol_abs, rel * beta);
   int it = 0;
-  bool early = false;  // the last cycle ended on its residual estimate
-  double beta_prev = 0.0;
   for (;;) {
     if (!(beta > tol_abs) || it >= max_iter) break;
-    if (rel > 0.0 && early && beta > 0.5 * beta_prev) break;  // stalled at the operator's rounding level
-    beta_prev = beta;
     {
       Scope t(ctx, "gmres");
       k_cycle_start<<<1, 64, 0, ctx->stream>>>(state, sd, beta);
@@ -361,13 +358,13 @@ pb_status gmres(pb_ctx* ctx, Krylov& K, const OpFn& op, const OpFn* prec, const 
     }
     PB_HIP(ctx, hipStreamSynchronize(ctx->stream));
     const int kd = hs[2 * (enq - 1) + 1];  // steps taken
-    early = hs[2 * (enq - 1)] != 0;
+    const bool early = hs[2 * (enq - 1)] != 0;  // the cycle ended on its residual estimate
     if (kd < 1 || kd > enq) return ctx->fail(PB_EDEVICE, "GMRES: inconsistent step count %d of %d", kd, enq);
     if (enq > kd) drop_timers(ctx, mark);  // the last step was skipped
     *skipped += enq - kd;
     it += kd;
     PB_HIP(ctx, hipMemcpyAsync(H.data(), Hd, sizeof(double) * (size_t)kd * m, hipMemcpyDeviceToHost, ctx->stream));
-    PB_HIP(ctx, hipMemcpyAsync(s.data(), sd, sizeof(double) * (size_t)kd, hipMemcpyDeviceToHost, ctx->stream));
+    PB_HIP(ctx, hipMemcpyAsync(s.data(), sd, sizeof(double) * (size_t)(kd + 1), hipMemcpyDeviceToHost, ctx->stream));
     PB_TRY(sync(ctx, "arnoldi"));
     for (int i = kd - 1; i >= 0; --i) {
       double acc = s[i];
@@ -377,6 +374,10 @@ pb_status gmres(pb_ctx* ctx, Krylov& K, const OpFn& op, const OpFn* prec, const 
     PB_HIP(ctx, hipMemcpyAsync(ydev, y.data(), sizeof(double) * kd, hipMemcpyHostToDevice, ctx->stream));
     k_axpy_multi<<<vb, kBlock, 0, ctx->stream>>>(M, prec ? Z : V, M, kd, ydev, 1.0, x);
     PB_TRY(launch_ok(ctx, "update"));
+    if (rel > 0.0 && early) {
+      beta = std::fabs(s[kd]);
+      break;
+    }
     PB_TRY(op(x, r));
     k_residual<<<vb, kBlock, 0, ctx->stream>>>(M, b, r);
     PB_TRY(norm2(ctx, K, r, &beta));
