@@ -85,11 +85,15 @@ struct TreePlan {
   int2* dir_rng = nullptr;
   int* app_ptr = nullptr;            // per batch: proxy clusters
   int* app_cl = nullptr;
-  float4* box = nullptr;             // per cluster: centre, half-widths (scaled coordinates)
+  float4* half = nullptr;            // per cluster: half-widths of its box (scaled coordinates)
+  double* ccen = nullptr;            // per cluster: FP64 centre of its box (3 doubles)
   int4* items = nullptr;             // proxy work items (cluster, begin, end, ·)
   int* item_ptr = nullptr;           // per cluster: its items
-  float4 *At = nullptr, *Mt = nullptr, *Nt = nullptr;  // records in tree order
-  float4* PX = nullptr;              // proxies: position and Q (scaled coordinates)
+  float4 *At = nullptr, *Mt = nullptr, *Nt = nullptr;  // records in tree order (At: group-local offsets)
+  float4* Gt = nullptr;              // FP32 global coordinates in tree order (the near predicate's)
+  double* St = nullptr;              // exact scaled coordinates in tree order (3 per node)
+  double* anc = nullptr;             // per aligned group of tree-order nodes: FP64 local origin
+  float4* PX = nullptr;              // proxies: offset from the cluster centre, and Q
   float* PM = nullptr;               // proxies: M
   double2* part = nullptr;           // per item partial proxy weights
   double* far = nullptr;             // far field, band order, 2n

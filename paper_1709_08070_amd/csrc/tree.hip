@@ -29,6 +29,20 @@
 // field supplies them). Lists, ranges and boxes are built once per band; each application
 // packs the records, computes the proxy weights and runs one fused far-field kernel. Fixed
 // orders throughout: the operator is bitwise reproducible.
+//
+// Local coordinates. The FP32 records hold σ(x − c) relative to the band's centre; their
+// rounding, about 6e-8·|σ(x − c)|, is a relative error of |x − c|/r in the difference d of a
+// pair at distance r, and the double-layer kernel amplifies it into the residual (at 2.57M
+// band nodes it puts the FP32 operator about 1.2e-6·‖g‖ from the FP64 one, nearly all of it
+// from pairs closer than 1 Å). The treecode therefore forms every difference from FP32
+// coordinates local to an FP64 origin near the pair: a source of a direct range is stored
+// as its offset from the centre of its aligned group of kAnchor tree-order nodes (a compact
+// patch in Morton order) and the target is converted to the same origin, once per group, from
+// its FP64 position; a proxy is stored as its offset from its cluster's FP64 centre, and the
+// target converted to that centre once per cluster. The error in d is then about 6e-8 times
+// the pair's own scale. Which pairs are near stays the shared FP32 predicate on the global
+// records, evaluated on the direct ranges that can hold a near pair (the host marks them);
+// the other ranges skip it.
 #include <algorithm>
 #include <memory>
 #include <cmath>
@@ -51,6 +65,7 @@ static_assert(kLeaf <= kBatch, "a leaf fits one target batch");
 constexpr int kProxyChunk = 2048; // sources per proxy work item
 constexpr int kProxyBlock = 256;
 constexpr int kProxyTile = 64;
+constexpr int kAnchor = 16;       // tree-order nodes per local-coordinate group of direct sources
 
 // 1D Chebyshev points of the second kind on [−1, 1], u_a = cos(πa/p), for degree p.
 struct ChebNodes {
@@ -76,27 +91,62 @@ __device__ __forceinline__ void lagrange(float x, const ChebNodes& cn, float* L,
   }
 }
 
-// Tree-order records gathered from the band-order ones (the same FP32 bits the near-field
-// predicate was evaluated on).
+// Tree-order records gathered from the band-order ones: At = (offset from the node's group
+// anchor, w̃n ψn), Mt and Nt as in band order, and Gt = the FP32 global coordinates (the same
+// bits the near-field predicate was evaluated on).
 __global__ void __launch_bounds__(kBlock) k_tree_gather(int n, const int* __restrict__ perm,
                                                         const float4* __restrict__ A, const float4* __restrict__ M,
-                                                        const float4* __restrict__ N, float4* __restrict__ At,
-                                                        float4* __restrict__ Mt, float4* __restrict__ Nt) {
+                                                        const float4* __restrict__ N, const double* __restrict__ St,
+                                                        const double* __restrict__ anc, float4* __restrict__ At,
+                                                        float4* __restrict__ Mt, float4* __restrict__ Nt,
+                                                        float4* __restrict__ Gt) {
   const int t = blockIdx.x * kBlock + threadIdx.x;
   if (t >= n) return;
   const int j = perm[t];
-  At[t] = A[j];
+  const float4 a = A[j];
+  const double* o = anc + 3 * (size_t)(t / kAnchor);
+  const double* x = St + 3 * (size_t)t;
+  At[t] = make_float4((float)(x[0] - o[0]), (float)(x[1] - o[1]), (float)(x[2] - o[2]), a.w);
   Mt[t] = M[j];
   Nt[t] = N[j];
+  Gt[t] = make_float4(a.x, a.y, a.z, 0.f);
+}
+
+// Exact scaled coordinates in tree order, St[t] = σ(x − c) of band node perm[t] in FP64.
+__global__ void __launch_bounds__(kBlock) k_tree_coords(int n, const int* __restrict__ perm, BandDev b, double cx,
+                                                        double cy, double cz, double sigma, double* __restrict__ St) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= n) return;
+  const int j = perm[t];
+  St[3 * (size_t)t] = sigma * (b.px[j] - cx);
+  St[3 * (size_t)t + 1] = sigma * (b.py[j] - cy);
+  St[3 * (size_t)t + 2] = sigma * (b.pz[j] - cz);
+}
+
+// Anchor of each aligned group of kAnchor tree-order nodes: the centre of its bounding box.
+__global__ void __launch_bounds__(kBlock) k_tree_anchor(int n, const double* __restrict__ St,
+                                                        double* __restrict__ anc) {
+  const int g = blockIdx.x * kBlock + threadIdx.x;
+  if ((int64_t)g * kAnchor >= n) return;
+  const int e = min(n, (g + 1) * kAnchor);
+  for (int a = 0; a < 3; ++a) {
+    double lo = INFINITY, hi = -INFINITY;
+    for (int t = g * kAnchor; t < e; ++t) {
+      lo = fmin(lo, St[3 * (size_t)t + a]);
+      hi = fmax(hi, St[3 * (size_t)t + a]);
+    }
+    anc[3 * (size_t)g + a] = 0.5 * (lo + hi);
+  }
 }
 
 // Partial proxy weights of one work item (cluster c, sources [b, e)): part[item][k] =
-// (Q_k, M_k) summed over the item's sources in FP64. Cluster box: centre box[2c], half-widths
-// box[2c + 1]; the basis variable is u = (y − centre)/half per axis. Block of kProxyBlock
-// threads; a tile of kProxyTile sources has its 1D bases evaluated once (three axes) and
-// shared through LDS.
+// (Q_k, M_k) summed over the item's sources in FP64. Cluster box: FP64 centre ccen[c],
+// half-widths half[c]; the basis variable is u = (y − centre)/half per axis, formed in FP64
+// from the exact coordinates St. Block of kProxyBlock threads; a tile of kProxyTile sources
+// has its 1D bases evaluated once (three axes) and shared through LDS.
 template <int P1>
-__global__ void __launch_bounds__(kProxyBlock) k_proxy(const int4* __restrict__ items, const float4* __restrict__ box,
+__global__ void __launch_bounds__(kProxyBlock) k_proxy(const int4* __restrict__ items, const double* __restrict__ ccen,
+                                                       const float4* __restrict__ half, const double* __restrict__ St,
                                                        const float4* __restrict__ At, const float4* __restrict__ Nt,
                                                        ChebNodes cn, double2* __restrict__ part,
                                                        const int* __restrict__ skip) {
@@ -107,8 +157,8 @@ __global__ void __launch_bounds__(kProxyBlock) k_proxy(const int4* __restrict__ 
   __shared__ float4 sN[kProxyTile];
   __shared__ float sW[kProxyTile];
   const int4 it = items[blockIdx.x];  // (cluster, begin, end, unused)
-  const float4 mid = box[2 * it.x], hw = box[2 * it.x + 1];
-  const float4 ih = make_float4(1.f / hw.x, 1.f / hw.y, 1.f / hw.z, 0.f);
+  const float4 hw = half[it.x];
+  const double* mid = ccen + 3 * (size_t)it.x;
   int ka[kPer], kb[kPer], kc[kPer];
   double q[kPer], m[kPer];
 #pragma unroll
@@ -125,11 +175,9 @@ __global__ void __launch_bounds__(kProxyBlock) k_proxy(const int4* __restrict__ 
       const int j = threadIdx.x / 3, ax = threadIdx.x % 3;
       float L[P1], dL[P1];
       if (j < cnt) {
-        const float4 a = At[base + j];
-        const float c = ax == 0 ? a.x : (ax == 1 ? a.y : a.z);
-        const float o = ax == 0 ? mid.x : (ax == 1 ? mid.y : mid.z);
-        const float s = ax == 0 ? ih.x : (ax == 1 ? ih.y : ih.z);
-        lagrange<P1>((c - o) * s, cn, L, dL);
+        const double ihd = 1.0 / (double)(ax == 0 ? hw.x : (ax == 1 ? hw.y : hw.z));
+        const float s = (float)ihd;
+        lagrange<P1>((float)((St[3 * (size_t)(base + j) + ax] - mid[ax]) * ihd), cn, L, dL);
 #pragma unroll
         for (int b = 0; b < P1; ++b) dL[b] *= s;
       } else {
@@ -174,9 +222,10 @@ __global__ void __launch_bounds__(kProxyBlock) k_proxy(const int4* __restrict__ 
 }
 
 // Proxies of cluster c: position ŷ_k = centre + half·(u_a, u_b, u_c) and the weights Q_k, M_k,
-// the sum of the cluster's item partials in item order. PX[k] = (ŷ_k, Q_k), PM[k] = M_k.
+// the sum of the cluster's item partials in item order. PX[k] = (ŷ_k − centre, Q_k) (the
+// offset from the FP64 centre), PM[k] = M_k.
 __global__ void __launch_bounds__(kBlock) k_proxy_sum(int n_cl, int P1, const int* __restrict__ item_ptr,
-                                                      const double2* __restrict__ part, const float4* __restrict__ box,
+                                                      const double2* __restrict__ part, const float4* __restrict__ half,
                                                       ChebNodes cn, float4* __restrict__ PX, float* __restrict__ PM) {
   const int P3 = P1 * P1 * P1;
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -188,10 +237,9 @@ __global__ void __launch_bounds__(kBlock) k_proxy_sum(int n_cl, int P1, const in
     q += v.x;
     m += v.y;
   }
-  const float4 mid = box[2 * c], hw = box[2 * c + 1];
+  const float4 hw = half[c];
   const int a = k / (P1 * P1), b = (k / P1) % P1, cc = k % P1;
-  PX[g] = make_float4(__fmaf_rn(hw.x, cn.u[a], mid.x), __fmaf_rn(hw.y, cn.u[b], mid.y), __fmaf_rn(hw.z, cn.u[cc], mid.z),
-                      (float)q);
+  PX[g] = make_float4(hw.x * cn.u[a], hw.y * cn.u[b], hw.z * cn.u[cc], (float)q);
   PM[g] = (float)m;
 }
 
@@ -216,51 +264,84 @@ __device__ __forceinline__ void proxy_f32(const float4& ta, const float4& tn, co
   a2 = __fmaf_rn(-dn * t2, rinv * rinv * rinv, a2);
 }
 
+// A direct pair in local coordinates (tl − sl = d) on a range that may hold near pairs: the
+// shared FP32 predicate on the global coordinates tg, sg decides, and a near pair is replaced
+// by a far stand-in with zero weights, which contributes exactly zero.
+template <bool kScreened>
+__device__ __forceinline__ void pair_local_checked(const float4& tl, const float4& tn, const float4& sl,
+                                                   const float4& sm, const float4& tg, const float4& sg,
+                                                   const F32Params& fp, float& a1, float& a2) {
+  const bool near = r2_f32(tg.x, tg.y, tg.z, sg.x, sg.y, sg.z) < fp.rc2;
+  const float4 s = near ? make_float4(tl.x + 1.f, tl.y, tl.z, 0.f) : sl;
+  const float4 m = near ? make_float4(0.f, 0.f, 0.f, 0.f) : sm;
+  pair_f32<kScreened, false>(tl, tn, s, m, fp, a1, a2);
+}
+
 // Far field of one target batch per wave: its direct source ranges with the dense pair
 // function, then its proxy clusters. Every lane reads the same source or proxy at the same
-// time (wave-uniform addresses, no LDS staging and no barriers). FP32 sums per range and per
-// cluster, flushed into FP64. Output in band order (through perm), scaled by σ and σ².
+// time (wave-uniform addresses, no LDS staging and no barriers). Differences are formed in
+// local coordinates: per anchor group of a direct range and per proxy cluster, each lane
+// converts its target's FP64 position to that origin. A range whose end carries the sign bit
+// may hold near pairs and runs the predicate. FP32 sums per range and per cluster, flushed
+// into FP64. Output in band order (through perm), scaled by σ and σ².
 template <bool kScreened>
 __global__ void __launch_bounds__(kBatch) k_tree_far(const int2* __restrict__ batch, const int* __restrict__ dir_ptr,
                                                      const int2* __restrict__ dir_rng, const int* __restrict__ app_ptr,
                                                      const int* __restrict__ app_cl, int P3,
                                                      const float4* __restrict__ PX, const float* __restrict__ PM,
-                                                     const float4* __restrict__ At, const float4* __restrict__ Mt,
-                                                     const float4* __restrict__ Nt, const int* __restrict__ perm,
+                                                     const double* __restrict__ ccen, const float4* __restrict__ At,
+                                                     const float4* __restrict__ Mt, const float4* __restrict__ Nt,
+                                                     const float4* __restrict__ Gt, const double* __restrict__ St,
+                                                     const double* __restrict__ anc, const int* __restrict__ perm,
                                                      F32Params fp, int n, double sig1, double sig2,
                                                      double* __restrict__ out, const int* __restrict__ skip) {
   if (skip && *skip) return;
   const int2 bt = batch[blockIdx.x];
   const int t = bt.x + (int)threadIdx.x;
   const bool live = t < bt.y;
-  const float4 ta = live ? At[t] : make_float4(0.f, 0.f, 0.f, 0.f);
-  const float4 tn = live ? Nt[t] : make_float4(0.f, 0.f, 1.f, 0.f);
+  const int tt = live ? t : bt.x;  // idle lanes shadow the batch's first target (results unused)
+  const double tx = St[3 * (size_t)tt], ty = St[3 * (size_t)tt + 1], tz = St[3 * (size_t)tt + 2];
+  const float4 tn = Nt[tt];
   double acc1 = 0.0, acc2 = 0.0;
   const int r1 = dir_ptr[blockIdx.x + 1];
   for (int r = dir_ptr[blockIdx.x]; r < r1; ++r) {
     const int2 rg = dir_rng[r];
+    const bool check = rg.y < 0;
+    const int end = rg.y & 0x7fffffff;
     float f1 = 0.f, f2 = 0.f;
-    int j = rg.x;
-    for (; j + 4 <= rg.y; j += 4) {
+    for (int j = rg.x; j < end;) {
+      const int je = min(end, (j / kAnchor + 1) * kAnchor);
+      const double* o = anc + 3 * (size_t)(j / kAnchor);
+      const float4 tl = make_float4((float)(tx - o[0]), (float)(ty - o[1]), (float)(tz - o[2]), 0.f);
+      if (check) {
+        const float4 tg = Gt[tt];
+        for (; j < je; ++j) pair_local_checked<kScreened>(tl, tn, At[j], Mt[j], tg, Gt[j], fp, f1, f2);
+      } else {
+        for (; j + 4 <= je; j += 4) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) pair_f32<kScreened, true>(ta, tn, At[j + u], Mt[j + u], fp, f1, f2);
+          for (int u = 0; u < 4; ++u) pair_f32<kScreened, false>(tl, tn, At[j + u], Mt[j + u], fp, f1, f2);
+        }
+        for (; j < je; ++j) pair_f32<kScreened, false>(tl, tn, At[j], Mt[j], fp, f1, f2);
+      }
     }
-    for (; j < rg.y; ++j) pair_f32<kScreened, true>(ta, tn, At[j], Mt[j], fp, f1, f2);
     acc1 += (double)f1;
     acc2 += (double)f2;
   }
   const int c1 = app_ptr[blockIdx.x + 1];
   for (int r = app_ptr[blockIdx.x]; r < c1; ++r) {
-    const size_t base = (size_t)app_cl[r] * P3;
+    const int cl = app_cl[r];
+    const size_t base = (size_t)cl * P3;
     const float4* __restrict__ px = PX + base;
     const float* __restrict__ pm = PM + base;
+    const double* o = ccen + 3 * (size_t)cl;
+    const float4 tl = make_float4((float)(tx - o[0]), (float)(ty - o[1]), (float)(tz - o[2]), 0.f);
     float f1 = 0.f, f2 = 0.f;
     int k = 0;
     for (; k + 4 <= P3; k += 4) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) proxy_f32<kScreened>(ta, tn, px[k + u], pm[k + u], fp, f1, f2);
+      for (int u = 0; u < 4; ++u) proxy_f32<kScreened>(tl, tn, px[k + u], pm[k + u], fp, f1, f2);
     }
-    for (; k < P3; ++k) proxy_f32<kScreened>(ta, tn, px[k], pm[k], fp, f1, f2);
+    for (; k < P3; ++k) proxy_f32<kScreened>(tl, tn, px[k], pm[k], fp, f1, f2);
     acc1 += (double)f1;
     acc2 += (double)f2;
   }
@@ -534,6 +615,9 @@ pb_status tree_prepare(pb_ctx* ctx, const pb_band* band, const Derived& d, int d
   // interaction lists per batch, then batches ordered by decreasing work (the longest waves
   // start first)
   const double rcs = P.sigma * P.rc * 1.01;
+  // a direct leaf whose box is at least this far (squared) from the batch's box holds no pair
+  // that the FP32 predicate calls near (its rounding is far below the margin)
+  const double clear2 = (double)P.rc2f * (1.0 + 1e-3);
   std::vector<std::vector<int2>> dirs(n_batch);
   std::vector<std::vector<int>> apps(n_batch);
   std::vector<int64_t> work(n_batch, 0);
@@ -556,8 +640,17 @@ pb_status tree_prepare(pb_ctx* ctx, const pb_band* band, const Derived& d, int d
           apps[bi].push_back(k);
           work[bi] += P3;
         } else if (nd.n_kids == 0) {
-          if (!dl.empty() && dl.back().y == nd.b) dl.back().y = nd.e;
-          else dl.push_back(make_int2(nd.b, nd.e));
+          // ranges of consecutive leaves with the same predicate flag (sign bit of the end)
+          double gap2 = 0.0;
+          for (int a = 0; a < 3; ++a) {
+            const double g = std::max(0.0, std::max(nd.lo[a] - bhi[a], blo[a] - nd.hi[a]));
+            gap2 += g * g;
+          }
+          const int flag = gap2 >= clear2 ? 0 : (int)0x80000000u;
+          if (!dl.empty() && (dl.back().y & 0x7fffffff) == nd.b && (dl.back().y & (int)0x80000000u) == flag)
+            dl.back().y = nd.e | flag;
+          else
+            dl.push_back(make_int2(nd.b, nd.e | flag));
           work[bi] += 2 * (nd.e - nd.b);  // a direct pair costs about twice a proxy interaction
         } else {
           for (int q = nd.n_kids - 1; q >= 0; --q) stack.push_back(nd.first_kid + q);
@@ -577,7 +670,7 @@ pb_status tree_prepare(pb_ctx* ctx, const pb_band* band, const Derived& d, int d
   int64_t n_dir_pairs = 0, n_app_pairs = 0;
   for (int bi = 0; bi < n_batch; ++bi) {
     const int64_t cnt = batch[bi].y - batch[bi].x;
-    for (const int2& r : dirs[bi]) n_dir_pairs += cnt * (r.y - r.x);
+    for (const int2& r : dirs[bi]) n_dir_pairs += cnt * ((r.y & 0x7fffffff) - r.x);
     n_app_pairs += cnt * P3 * (int64_t)apps[bi].size();
   }
   std::vector<int> order(n_batch);
@@ -599,7 +692,8 @@ pb_status tree_prepare(pb_ctx* ctx, const pb_band* band, const Derived& d, int d
   // proxy clusters: the tree nodes that some list uses, numbered in tree-node order
   std::vector<char> used(nodes.size(), 0);
   for (int k : app_node) used[k] = 1;
-  std::vector<float4> box;
+  std::vector<float4> half;
+  std::vector<double> ccen;
   std::vector<int> item_ptr{0};
   std::vector<int4> items;
   int n_cl = 0;
@@ -608,11 +702,11 @@ pb_status tree_prepare(pb_ctx* ctx, const pb_band* band, const Derived& d, int d
     if (!used[k]) continue;
     const HNode& nd = nodes[k];
     const int cl = cl_of[k] = n_cl++;
-    double half[3], ext = 0.0;
+    double hw[3], ext = 0.0;
     for (int a = 0; a < 3; ++a) ext = std::max(ext, nd.hi[a] - nd.lo[a]);
-    for (int a = 0; a < 3; ++a) half[a] = std::max(0.5 * (nd.hi[a] - nd.lo[a]), std::max(1e-3 * ext, 1e-6));
-    box.push_back(make_float4((float)nd.c[0], (float)nd.c[1], (float)nd.c[2], 0.f));
-    box.push_back(make_float4((float)half[0], (float)half[1], (float)half[2], 0.f));
+    for (int a = 0; a < 3; ++a) hw[a] = std::max(0.5 * (nd.hi[a] - nd.lo[a]), std::max(1e-3 * ext, 1e-6));
+    half.push_back(make_float4((float)hw[0], (float)hw[1], (float)hw[2], 0.f));
+    ccen.insert(ccen.end(), nd.c, nd.c + 3);
     for (int t = nd.b; t < nd.e; t += kProxyChunk) items.push_back(make_int4(cl, t, std::min(nd.e, t + kProxyChunk), 0));
     item_ptr.push_back((int)items.size());
   }
@@ -631,7 +725,8 @@ pb_status tree_prepare(pb_ctx* ctx, const pb_band* band, const Derived& d, int d
   PB_TRY(up((px_ + "dir_rng").c_str(), dir_rng.data(), sizeof(int2) * dir_rng.size(), (void**)&T.dir_rng));
   PB_TRY(up((px_ + "app_ptr").c_str(), app_ptr.data(), sizeof(int) * (n_batch + 1), (void**)&T.app_ptr));
   PB_TRY(up((px_ + "app_cl").c_str(), app_cl.data(), sizeof(int) * app_cl.size(), (void**)&T.app_cl));
-  PB_TRY(up((px_ + "box").c_str(), box.data(), sizeof(float4) * box.size(), (void**)&T.box));
+  PB_TRY(up((px_ + "half").c_str(), half.data(), sizeof(float4) * half.size(), (void**)&T.half));
+  PB_TRY(up((px_ + "ccen").c_str(), ccen.data(), sizeof(double) * ccen.size(), (void**)&T.ccen));
   PB_TRY(up((px_ + "items").c_str(), items.data(), sizeof(int4) * items.size(), (void**)&T.items));
   PB_TRY(up((px_ + "item_ptr").c_str(), item_ptr.data(), sizeof(int) * item_ptr.size(), (void**)&T.item_ptr));
   T.At = (float4*)workspace(ctx, (px_ + "At").c_str(), sizeof(float4) * n);
@@ -641,7 +736,16 @@ pb_status tree_prepare(pb_ctx* ctx, const pb_band* band, const Derived& d, int d
   T.PM = (float*)workspace(ctx, (px_ + "PM").c_str(), sizeof(float) * std::max<size_t>((size_t)n_cl * P3, 1));
   T.part = (double2*)workspace(ctx, (px_ + "part").c_str(), sizeof(double2) * std::max<size_t>(items.size() * P3, 1));
   T.far = (double*)workspace(ctx, (px_ + "far").c_str(), sizeof(double) * 2 * (size_t)n);
-  if (!T.At || !T.Mt || !T.Nt || !T.PX || !T.PM || !T.part || !T.far) return PB_ENOMEM;
+  T.Gt = (float4*)workspace(ctx, (px_ + "Gt").c_str(), sizeof(float4) * n);
+  T.St = (double*)workspace(ctx, (px_ + "St").c_str(), sizeof(double) * 3 * (size_t)n);
+  const int n_anc = (n + kAnchor - 1) / kAnchor;
+  T.anc = (double*)workspace(ctx, (px_ + "anc").c_str(), sizeof(double) * 3 * (size_t)std::max(n_anc, 1));
+  if (!T.At || !T.Mt || !T.Nt || !T.PX || !T.PM || !T.part || !T.far || !T.Gt || !T.St || !T.anc) return PB_ENOMEM;
+  // exact scaled coordinates in tree order and the anchors of the direct sources' groups
+  k_tree_coords<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, ctx->stream>>>(n, T.perm, band_dev(band), P.cx,
+                                                                                    P.cy, P.cz, P.sigma, T.St);
+  k_tree_anchor<<<(unsigned)((n_anc + kBlock - 1) / kBlock), kBlock, 0, ctx->stream>>>(n, T.St, T.anc);
+  PB_TRY(launch_ok(ctx, "tree coordinates"));
   T.band_key = band->px;
   T.n = n;
   T.rc = d.rc;
@@ -660,8 +764,8 @@ namespace {
 
 template <int P1>
 void launch_proxy(pb_ctx* ctx, const TreePlan& T, const ChebNodes& cn) {
-  k_proxy<P1><<<(unsigned)T.n_items, kProxyBlock, 0, ctx->stream>>>(T.items, T.box, T.At, T.Nt, cn, T.part,
-                                                                        ctx->skip);
+  k_proxy<P1><<<(unsigned)T.n_items, kProxyBlock, 0, ctx->stream>>>(T.items, T.ccen, T.half, T.St, T.At, T.Nt, cn,
+                                                                        T.part, ctx->skip);
 }
 
 void launch_tree(pb_ctx* ctx, const TreePlan& T, bool screened, const F32Params& fp, double sig1, double sig2) {
@@ -679,12 +783,12 @@ void launch_tree(pb_ctx* ctx, const TreePlan& T, bool screened, const F32Params&
       default: launch_proxy<9>(ctx, T, cn); break;
     }
     k_proxy_sum<<<(unsigned)(((int64_t)T.n_cl * P3 + kBlock - 1) / kBlock), kBlock, 0, ctx->stream>>>(
-        T.n_cl, P1, T.item_ptr, T.part, T.box, cn, T.PX, T.PM);
+        T.n_cl, P1, T.item_ptr, T.part, T.half, cn, T.PX, T.PM);
   }
   auto far = screened ? k_tree_far<true> : k_tree_far<false>;
   far<<<(unsigned)T.n_batch, kBatch, 0, ctx->stream>>>(T.batch, T.dir_ptr, T.dir_rng, T.app_ptr, T.app_cl, P3, T.PX,
-                                                        T.PM, T.At, T.Mt, T.Nt, T.perm, fp, (int)T.n, sig1, sig2, T.far,
-                                                        ctx->skip);
+                                                        T.PM, T.ccen, T.At, T.Mt, T.Nt, T.Gt, T.St, T.anc, T.perm, fp,
+                                                        (int)T.n, sig1, sig2, T.far, ctx->skip);
 }
 
 }  // namespace
@@ -700,7 +804,7 @@ pb_status matvec_tree(pb_ctx* ctx, const pb_band* band, const Derived& d, const 
   const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
   k_pack_f32<<<nb, kBlock, 0, ctx->stream>>>(n, band_dev(band), band->w, p, d.h3 / (4.0 * kPi), P.cx, P.cy, P.cz,
                                              P.sigma, P.A, P.M, P.N);
-  k_tree_gather<<<nb, kBlock, 0, ctx->stream>>>(n, T.perm, P.A, P.M, P.N, T.At, T.Mt, T.Nt);
+  k_tree_gather<<<nb, kBlock, 0, ctx->stream>>>(n, T.perm, P.A, P.M, P.N, T.St, T.anc, T.At, T.Mt, T.Nt, T.Gt);
   const F32Params fp = f32params(d, P.sigma);
   const bool screened = d.kappa > 0.0;
   {
