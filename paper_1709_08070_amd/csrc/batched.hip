@@ -136,18 +136,19 @@ static __global__ void __launch_bounds__(kBlock) k_far32_sym_batch(const Item* _
 }
 
 // Symmetric FP64 operator of every selected molecule: items (molecule, Ic, Jc), persistent.
+// k2 = κ².
 static __global__ void __launch_bounds__(kBlock) k_far64_sym_batch(const Item* __restrict__ items, int n_items,
                                                                    const MolDev* __restrict__ mols,
                                                                    const int* __restrict__ active,
                                                                    const double* __restrict__ wpsi,
                                                                    const double* __restrict__ wpsn, KParams kp,
-                                                                   double* __restrict__ partial) {
+                                                                   double k2, double* __restrict__ partial) {
   __shared__ Sym64Shared sh;
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     const Item w = items[it];
     if (!active[w.mol]) continue;
     const MolDev& m = mols[w.mol];
-    sym64_item(m.band, wpsi + m.off, wpsn + m.off, m.n, w.tb, w.ch, m.nsub, kp, partial + m.poffsym, sh);
+    sym64_item(m.band, wpsi + m.off, wpsn + m.off, m.n, w.tb, w.ch, m.nsub, kp, k2, partial + m.poffsym, sh);
   }
 }
 
@@ -693,7 +694,7 @@ std::vector<Item> make_sym_items(const std::vector<MolDev>& mols) {
 void far64(Batch& B, int cfg, const int* sel) {
   if (cfg == 1)
     k_far64_sym_batch<<<B.grid64sym, kBlock, 0, B.st>>>(B.items32[kSymB], B.n_items32[kSymB], B.mols, sel, B.wpsi,
-                                                        B.wpsn, kparams(B.d), B.partial);
+                                                        B.wpsn, kparams(B.d), B.d.kappa * B.d.kappa, B.partial);
   else
     k_far64_batch<<<B.grid64, kBlock, 0, B.st>>>(B.items64, B.n_items64, B.mols, kChunk64, sel, B.wpsi, B.wpsn,
                                                  kparams(B.d), B.partial);

@@ -183,7 +183,7 @@ int launch_f64(pb_ctx* ctx, int cfg, const pb_band* band, const double* wpsi, co
     const int2* items = sym_items_dev(ctx, n, &n_items);
     if (!items) return -1;
     k_p2p_f64_sym<<<(unsigned)n_items, kBlock, 0, ctx->stream>>>(band_dev(band), wpsi, wpsn, n, sym_nsub(n), items,
-                                                                 n_items, kp, partial, skip);
+                                                                 n_items, kp, kp.kappa * kp.kappa, partial, skip);
     return sym_chunks(n);
   }
   int chunk = 0;

@@ -90,10 +90,10 @@ __device__ __forceinline__ bool reg_f64(double r2, double dn, const KParams& kp)
 // products are exact inside the FMAs), |t| ≤ ln2/2, e^t by the degree-11 interpolant of e^t at
 // the 12 Chebyshev nodes of [−ln2/2, ln2/2] (near-minimax; relative error 1.7e-17 before
 // rounding, against 5.2e-18 for the Taylor series to degree 13, two terms longer; the
-// coefficients come from exp_coeffs.py beside this file), then scaled by 2^k. z is clamped to
-// 745, beyond which e^{−z} is 0 in FP64.
+// coefficients come from exp_coeffs.py beside this file), then scaled by 2^k. For 0 ≤ z ≤ 1e9
+// (k fits an int; beyond z ≈ 745 the scaling underflows to 0, as e^{−z} does in FP64): the
+// kernels' distances stay far below that, padding records included (1e6 away).
 __device__ __forceinline__ double exp_neg_f64(double z) {
-  z = fmin(z, 745.0);
   const double k = __builtin_rint(-z * 1.4426950408889634);
   const double t = fma(-k, 2.3190468138462996e-17, fma(-k, 0.6931471805599453, -z));
   double p = 2.5110037605963777e-08;
@@ -154,11 +154,11 @@ __device__ __forceinline__ void pair_sym_f64(double xi, double yi, double zi, do
 }
 
 // Both directions of a pair that cannot be regularized (far sub-block pairs): the same
-// kernels as pair_sym_f64's regular branch, the products free to fuse.
+// kernels as pair_sym_f64's regular branch, the products free to fuse. k2 = κ².
 __device__ __forceinline__ void pair_sym_f64_far(double xi, double yi, double zi, double nxi, double nyi, double nzi,
                                                  double wpi, double wni, const double2& s0, const double2& s1,
-                                                 const double2& s2, const double2& s3, const KParams& kp, double& f1,
-                                                 double& f2, double& g1, double& g2) {
+                                                 const double2& s2, const double2& s3, const KParams& kp, double k2,
+                                                 double& f1, double& f2, double& g1, double& g2) {
   const double xj = s0.x, yj = s0.y, zj = s1.x, nxj = s1.y, nyj = s2.x, nzj = s2.y, wpj = s3.x, wnj = s3.y;
   const double dx = xi - xj, dy = yi - yj, dz = zi - zj;
   const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
@@ -175,10 +175,14 @@ __device__ __forceinline__ void pair_sym_f64_far(double xi, double yi, double zi
   const double z = kp.kappa * (r2 * rinv);
   const double E = exp_neg_f64(z);
   const double a = fma(E, z, E);                    // E(1 + z)
-  const double b = E * fma(z, z + 3.0, 3.0);        // E(3 + 3z + z²)
   const double k12 = fma(-E, rinv, rinv);           // (1 − E)/r
-  const double k21 = r3 * fma(-(dnx * dny) * (3.0 - b), ri2, nn * (1.0 - a));
-  const double c1 = fma(-kp.th1, a, 1.0) * r3, c2 = fma(-kp.th2, a, 1.0) * r3;
+  // with b = E(3 + 3z + z²) = 3a + Ez²: −(3 − b)/r² = 3(a − 1)/r² + Eκ² (3u as 4u − u keeps
+  // every constant inline)
+  const double am1 = a - 1.0;
+  const double gr = fma(fma(am1, 4.0, -am1), ri2, E * k2);
+  const double k21 = r3 * fma(dnx * dny, gr, -nn * am1);
+  const double ar3 = a * r3;
+  const double c1 = fma(-kp.th1, ar3, r3), c2 = fma(-kp.th2, ar3, r3);  // (1 − θa)/r³
   f1 = fma(dny * c1, wpj, fma(-k12, wnj, f1));
   f2 = fma(k21, wpj, fma(dnx * c2, wnj, f2));
   g1 = fma(-(dnx * c1), wpi, fma(-k12, wni, g1));
@@ -197,7 +201,7 @@ template <int kMetric, bool kFar>
 __device__ __forceinline__ void sym64_loop(double xa, double ya, double za, double nxa, double nya, double nza,
                                            double wpa, double wna, double xb, double yb, double zb, double nxb,
                                            double nyb, double nzb, double wpb, double wnb, const KParams& kp,
-                                           Sym64Shared& sh, double (&f)[4]) {
+                                           double k2, Sym64Shared& sh, double (&f)[4]) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int next = ((lane + 1) & 63) << 2;
   for (int g = 0; g < kSymSub; g += 64) {
@@ -206,8 +210,8 @@ __device__ __forceinline__ void sym64_loop(double xa, double ya, double za, doub
       const int q = g + ((lane + s) & 63);
       const double2 c0 = sh.s0[q], c1 = sh.s1[q], c2 = sh.s2[q], c3 = sh.s3[q];
       if (kFar) {
-        pair_sym_f64_far(xa, ya, za, nxa, nya, nza, wpa, wna, c0, c1, c2, c3, kp, f[0], f[1], ra1, ra2);
-        pair_sym_f64_far(xb, yb, zb, nxb, nyb, nzb, wpb, wnb, c0, c1, c2, c3, kp, f[2], f[3], ra1, ra2);
+        pair_sym_f64_far(xa, ya, za, nxa, nya, nza, wpa, wna, c0, c1, c2, c3, kp, k2, f[0], f[1], ra1, ra2);
+        pair_sym_f64_far(xb, yb, zb, nxb, nyb, nzb, wpb, wnb, c0, c1, c2, c3, kp, k2, f[2], f[3], ra1, ra2);
       } else {
         pair_sym_f64<kMetric>(xa, ya, za, nxa, nya, nza, wpa, wna, c0, c1, c2, c3, kp, f[0], f[1], ra1, ra2);
         pair_sym_f64<kMetric>(xb, yb, zb, nxb, nyb, nzb, wpb, wnb, c0, c1, c2, c3, kp, f[2], f[3], ra1, ra2);
@@ -227,7 +231,7 @@ __device__ __forceinline__ void sym64_loop(double xa, double ya, double za, doub
 template <int kMetric>
 __device__ __forceinline__ void sym64_block(const BandDev& b, const double* __restrict__ wpsi,
                                             const double* __restrict__ wpsn, int n, int t0, int s0,
-                                            const KParams& kp, Sym64Shared& sh, double (&f)[4],
+                                            const KParams& kp, double k2, Sym64Shared& sh, double (&f)[4],
                                             const double (&tlo)[3], const double (&thi)[3], double* rev1,
                                             double* rev2, bool rev_acc) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -243,8 +247,8 @@ __device__ __forceinline__ void sym64_block(const BandDev& b, const double* __re
       slo[0] = fmin(slo[0], x), slo[1] = fmin(slo[1], y), slo[2] = fmin(slo[2], z);
       shi[0] = fmax(shi[0], x), shi[1] = fmax(shi[1], y), shi[2] = fmax(shi[2], z);
     } else {  // padding far away with zero weights: contributes exactly zero both ways
-      sh.s0[q] = make_double2(1e30, 1e30);
-      sh.s1[q] = make_double2(1e30, 0.0);
+      sh.s0[q] = make_double2(1e6, 1e6);
+      sh.s1[q] = make_double2(1e6, 0.0);
       sh.s2[q] = make_double2(0.0, 1.0);
       sh.s3[q] = make_double2(0.0, 0.0);
     }
@@ -258,9 +262,11 @@ __device__ __forceinline__ void sym64_block(const BandDev& b, const double* __re
   const double xb = b.px[ib], yb = b.py[ib], zb = b.pz[ib], nxb = b.nx[ib], nyb = b.ny[ib], nzb = b.nz[ib];
   const double wpa = wpsi[ia], wna = wpsn[ia], wpb = wpsi[ib], wnb = wpsn[ib];
   if (far)
-    sym64_loop<kMetric, true>(xa, ya, za, nxa, nya, nza, wpa, wna, xb, yb, zb, nxb, nyb, nzb, wpb, wnb, kp, sh, f);
+    sym64_loop<kMetric, true>(xa, ya, za, nxa, nya, nza, wpa, wna, xb, yb, zb, nxb, nyb, nzb, wpb, wnb, kp, k2, sh,
+                              f);
   else
-    sym64_loop<kMetric, false>(xa, ya, za, nxa, nya, nza, wpa, wna, xb, yb, zb, nxb, nyb, nzb, wpb, wnb, kp, sh, f);
+    sym64_loop<kMetric, false>(xa, ya, za, nxa, nya, nza, wpa, wna, xb, yb, zb, nxb, nyb, nzb, wpb, wnb, kp, k2, sh,
+                               f);
   __syncthreads();
   for (int q = tid; q < kSymSub; q += kBlock) {
     if (s0 + q < n) {
@@ -310,10 +316,11 @@ __device__ __forceinline__ void diag64_block(const BandDev& b, const double* __r
   __syncthreads();
 }
 
-// One work item (Ic, Jc), Ic ≤ Jc; partial: the band's chunked partial sums.
+// One work item (Ic, Jc), Ic ≤ Jc; partial: the band's chunked partial sums; k2 = κ².
 __device__ __forceinline__ void sym64_item(const BandDev& b, const double* __restrict__ wpsi,
                                            const double* __restrict__ wpsn, int n, int Ic, int Jc, int nsub,
-                                           const KParams& kp, double* __restrict__ partial, Sym64Shared& sh) {
+                                           const KParams& kp, double k2, double* __restrict__ partial,
+                                           Sym64Shared& sh) {
   const int C = nsub * kSymSub;
   const int i0 = Ic * C, i1 = min(n, i0 + C), j0 = Jc * C, j1 = min(n, j0 + C);
   double* rowF = partial + (int64_t)Jc * 2 * n;
@@ -339,11 +346,12 @@ __device__ __forceinline__ void sym64_item(const BandDev& b, const double* __res
       if (S == T)
         diag64_block(b, wpsi, wpsn, n, T, kp, sh, f);
       else if (kp.metric == PB_REG_EUCLIDEAN)
-        sym64_block<PB_REG_EUCLIDEAN>(b, wpsi, wpsn, n, T, S, kp, sh, f, tlo, thi, rowR + S, rowR + n + S, rev_acc);
+        sym64_block<PB_REG_EUCLIDEAN>(b, wpsi, wpsn, n, T, S, kp, k2, sh, f, tlo, thi, rowR + S, rowR + n + S,
+                                      rev_acc);
       else if (kp.metric == PB_REG_TANGENT)
-        sym64_block<PB_REG_TANGENT>(b, wpsi, wpsn, n, T, S, kp, sh, f, tlo, thi, rowR + S, rowR + n + S, rev_acc);
+        sym64_block<PB_REG_TANGENT>(b, wpsi, wpsn, n, T, S, kp, k2, sh, f, tlo, thi, rowR + S, rowR + n + S, rev_acc);
       else
-        sym64_block<PB_REG_TANGENT_GUARDED>(b, wpsi, wpsn, n, T, S, kp, sh, f, tlo, thi, rowR + S, rowR + n + S,
+        sym64_block<PB_REG_TANGENT_GUARDED>(b, wpsi, wpsn, n, T, S, kp, k2, sh, f, tlo, thi, rowR + S, rowR + n + S,
                                             rev_acc);
     }
     // forward sums, once per target sub-block (in a diagonal item the earlier target
@@ -361,16 +369,17 @@ __device__ __forceinline__ void sym64_item(const BandDev& b, const double* __res
   }
 }
 
-// Symmetric FP64 operator of one band: one block per work item.
+// Symmetric FP64 operator of one band: one block per work item. k2 = κ² (a kernel argument,
+// so that it stays in scalar registers).
 static __global__ void __attribute__((unused)) __launch_bounds__(kBlock)
     k_p2p_f64_sym(BandDev b, const double* __restrict__ wpsi, const double* __restrict__ wpsn, int n, int nsub,
-                  const int2* __restrict__ items, int n_items, KParams kp, double* __restrict__ partial,
+                  const int2* __restrict__ items, int n_items, KParams kp, double k2, double* __restrict__ partial,
                   const int* __restrict__ skip) {
   if (skip && *skip) return;
   __shared__ Sym64Shared sh;
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     const int2 w = items[it];
-    sym64_item(b, wpsi, wpsn, n, w.x, w.y, nsub, kp, partial, sh);
+    sym64_item(b, wpsi, wpsn, n, w.x, w.y, nsub, kp, k2, partial, sh);
   }
 }
 
