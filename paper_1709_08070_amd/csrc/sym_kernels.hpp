@@ -12,8 +12,10 @@
 //          a2 += [W_i Q − c2 (d·n_j) V_i]/r'³,
 // with Q = (1 − a)(n_i·n_j) + (d·n_i)(d·n_j) g/r'² the weight-free K21 core, symmetric in
 // (i, j); it is evaluated with g/r'² = E − 3(1 − a)/r'² and a = E(1 + r') as one FMA each.
-// Everything but the last products is shared: 43 FP32 operations and 2 transcendentals per
-// unordered pair, 21.5 + 1 per ordered pair (34 + 2 for one direction at a time). Records: A = (σ(x − c), V) and N = (n, W), two float4 per node.
+// Everything but the last products is shared: 42 FP32 operations and 2 transcendentals per
+// unordered pair, 21 + 1 per ordered pair (34 + 2 for one direction at a time); the factor
+// 1/r'³ enters once through a/r'³, c2/r'³ and Q/r'³. Records: A = (σ(x − c), V) and
+// N = (n, W), two float4 per node.
 //
 // Work decomposition. The band is cut into chunks of C = 512·nsub nodes (nC chunks). One
 // work item is a chunk pair (Ic, Jc) with Ic ≤ Jc; the partial sums keep the chunked layout
@@ -50,10 +52,11 @@ struct SymShared {
   float racc[kSymWaves][2][kSymSub];
 };
 
-// Radial and pair terms shared by both directions (see the header): rinv = 1/r' (0 for a
-// near pair when kCheck), r3, P1 = c1/r'³, c2, f0r = (1 − E)/r', Q; dnx = d·n_i, dny = d·n_j.
+// Radial and pair terms shared by both directions (see the header), 1/r' being 0 for a near
+// pair when kCheck: P1 = c1/r'³, C2 = c2/r'³, f0r = (1 − E)/r', Qr = Q/r'³; dnx = d·n_i,
+// dny = d·n_j.
 struct PairTerms {
-  float r3, P1, c2, f0r, Q, dnx, dny;
+  float P1, C2, f0r, Qr, dnx, dny;
 };
 
 template <bool kScreened, bool kCheck>
@@ -70,20 +73,21 @@ __device__ __forceinline__ PairTerms pair_terms(const float4& ta, const float4& 
   }
   const float a = __fmaf_rn(E, z, E);  // E(1 + r')
   const float ri2 = rinv * rinv;
+  const float r3 = ri2 * rinv;
+  const float ar3 = a * r3;
   PairTerms t;
-  t.r3 = ri2 * rinv;
   t.dnx = __fmaf_rn(dz, tn.z, __fmaf_rn(dy, tn.y, dx * tn.x));
   t.dny = __fmaf_rn(dz, sn.z, __fmaf_rn(dy, sn.y, dx * sn.x));
-  t.P1 = __fmaf_rn(-fp.th1, a, 1.f) * t.r3;
-  t.c2 = __fmaf_rn(-fp.th2, a, 1.f);
+  t.P1 = __fmaf_rn(-fp.th1, ar3, r3);
+  t.C2 = __fmaf_rn(-fp.th2, ar3, r3);
   if (kScreened) {
     const float nn = __fmaf_rn(tn.z, sn.z, __fmaf_rn(tn.y, sn.y, tn.x * sn.x));
     const float gr = __fmaf_rn(__fmaf_rn(3.f, a, -3.f), ri2, E);  // g/r'² = E − 3(1 − a)/r'²
     t.f0r = __fmaf_rn(-E, rinv, rinv);
-    t.Q = __fmaf_rn(t.dnx * t.dny, gr, __fmaf_rn(-a, nn, nn));
+    t.Qr = __fmaf_rn(t.dnx * t.dny, gr, __fmaf_rn(-a, nn, nn)) * r3;
   } else {  // κ = 0: E = a = 1 and z = 0, so 1 − E = 0 and Q = 0
     t.f0r = 0.f;
-    t.Q = 0.f;
+    t.Qr = 0.f;
   }
   return t;
 }
@@ -96,8 +100,8 @@ __device__ __forceinline__ void pair_sym(const float4& ta, const float4& tn, con
   const PairTerms t = pair_terms<kScreened, kCheck>(ta, tn, sa, sn, fp);
   fa1 = __fmaf_rn(t.P1 * t.dny, sn.w, fa1);
   ra1 = __fmaf_rn(-(t.P1 * t.dnx), tn.w, ra1);
-  fa2 = __fmaf_rn(__fmaf_rn(t.c2 * t.dnx, sa.w, sn.w * t.Q), t.r3, fa2);
-  ra2 = __fmaf_rn(__fmaf_rn(-(t.c2 * t.dny), ta.w, tn.w * t.Q), t.r3, ra2);
+  fa2 = __fmaf_rn(t.C2 * t.dnx, sa.w, __fmaf_rn(t.Qr, sn.w, fa2));
+  ra2 = __fmaf_rn(-(t.C2 * t.dny), ta.w, __fmaf_rn(t.Qr, tn.w, ra2));
   if (kScreened) {
     fa1 = __fmaf_rn(-t.f0r, sa.w, fa1);
     ra1 = __fmaf_rn(-t.f0r, ta.w, ra1);
@@ -110,7 +114,7 @@ __device__ __forceinline__ void pair_fwd(const float4& ta, const float4& tn, con
                                          const F32Params& fp, float& fa1, float& fa2) {
   const PairTerms t = pair_terms<kScreened, true>(ta, tn, sa, sn, fp);
   fa1 = __fmaf_rn(t.P1 * t.dny, sn.w, fa1);
-  fa2 = __fmaf_rn(__fmaf_rn(t.c2 * t.dnx, sa.w, sn.w * t.Q), t.r3, fa2);
+  fa2 = __fmaf_rn(t.C2 * t.dnx, sa.w, __fmaf_rn(t.Qr, sn.w, fa2));
   if (kScreened) fa1 = __fmaf_rn(-t.f0r, sa.w, fa1);
 }
 

@@ -47,9 +47,9 @@ def test_executed_counts_from_the_profiled_source():
     """The executed VALU work of the dominant kernel comes from the committed counter summary,
     only while its source is unchanged."""
     n = 638391
-    ex = bench.executed_counts("k_p2p_f32_sym", "globule5000", float(n) * n, 193.32e-3)
+    ex = bench.executed_counts("k_p2p_f32_sym", "globule5000", float(n) * n, 192.46e-3)
     assert ex is not None
-    assert 23.0 < ex["valu_insts_per_pair"] < 24.0
+    assert 22.5 < ex["valu_insts_per_pair"] < 23.5
     assert 0.0 < ex["frac_of_peak"] < ex["frac_of_nonpacked_ceiling"] <= 1.0
     assert bench.executed_counts("k_p2p_f32_sym", "globule500", 1.0, 1.0) is None
 
