@@ -106,6 +106,7 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--tol", type=float, default=1e-7, help="tolerance of the solves that give the targets")
     ap.add_argument("--net-seed", type=int, default=1)
+    ap.add_argument("--n-random", type=int, default=1, help="random-field pairs per molecule besides (g, p*)")
     ap.add_argument("--out", required=True)
     args = ap.parse_args(argv)
 
@@ -115,9 +116,9 @@ def main(argv=None):
     ctx = pb.Context(0)
     net = pb.Net(ctx, seed=args.net_seed)
     info = train(ctx, net, n_mol=args.molecules, lo=args.lo, hi=args.hi, h=args.h, seed0=args.seed0,
-                 epochs=args.epochs, lr=args.lr, log=log, tol=args.tol)
+                 epochs=args.epochs, lr=args.lr, n_random=args.n_random, log=log, tol=args.tol)
     net.save(args.out)
-    info.update({k: getattr(args, k) for k in ("lo", "hi", "h", "seed0", "lr", "tol", "net_seed")})
+    info.update({k: getattr(args, k) for k in ("lo", "hi", "h", "seed0", "lr", "tol", "net_seed", "n_random")})
     with open(args.out.rsplit(".", 1)[0] + ".json", "w") as f:
         json.dump(info, f, indent=1)
     log(f"saved {args.out}: loss per epoch {info['loss']}, data {info['t_data_s']:.0f} s, "
