@@ -279,7 +279,8 @@ struct SkipGuard {
 // (estimate, then confirmed with the operator at each restart) or max_iter operator
 // applications. With rel > 0 the solve is the inner solve of a refinement whose caller forms
 // a more accurate residual of the result next: a cycle that stops on its estimate ends the
-// solve without the confirming application, and *res_out is that estimate.
+// solve without the confirming application, and *res_out is that estimate. With x_zero the
+// caller guarantees x = 0 on entry, and the first residual is b itself (no application).
 // With prec (flexible GMRES, right preconditioning): z_k = prec(v_k), w = A z_k, and the
 // update is x += Z y; the preconditioner may change from step to step (it may be nonlinear).
 //
@@ -289,7 +290,7 @@ struct SkipGuard {
 // was met finds the operator's skip flag set: its heavy kernels return at once and the step
 // is not counted (*skipped counts them).
 pb_status gmres(pb_ctx* ctx, Krylov& K, const OpFn& op, const OpFn* prec, const double* b, double* x, double tol_abs,
-                double rel, int max_iter, int* iters, double* res_out, int* skipped) {
+                double rel, int max_iter, int* iters, double* res_out, int* skipped, bool x_zero = false) {
   const int64_t M = K.M;
   const int m = K.m;
   double* V = (double*)workspace(ctx, "kr_V", sizeof(double) * (size_t)M * (m + 1));
@@ -305,7 +306,8 @@ pb_status gmres(pb_ctx* ctx, Krylov& K, const OpFn& op, const OpFn* prec, const 
   volatile int* hs = ctx->host_state;  // step slots, written by the device (k_dots_finish)
   const unsigned vb = vec_blocks(M), db = dot_blocks(M);
   std::vector<double> H((size_t)(m + 1) * m, 0.0), s(m + 1), y(m);
-  PB_TRY(op(x, r));
+  if (x_zero) k_zero<<<vb, kBlock, 0, ctx->stream>>>(M, r);  // A·0
+  else PB_TRY(op(x, r));
   k_residual<<<vb, kBlock, 0, ctx->stream>>>(M, b, r);
   double beta = 0.0;
   PB_TRY(norm2(ctx, K, r, &beta));
@@ -482,13 +484,16 @@ extern "C" pb_status pb_ibim_solve(pb_ctx* ctx, const pb_band* band, const doubl
   };
   int iters = 0, outer = 0;
   double relres = 0.0;
+  bool p_zero = opts.x0 == PB_X0_ZERO;  // p = 0 on entry to the first pass
   // one solve from the current p; prec = learned right preconditioner or none
   auto run = [&](const OpFn* prec, int iter_budget) -> pb_status {
+    const bool from_zero = p_zero;
+    p_zero = false;
     if (opts.precision == PB_FP64) {
       double res = 0.0;
       int it = 0;
       int sk = 0;
-      PB_TRY(gmres(ctx, K, op64, prec, g, p, opts.tol * gnorm, 0.0, iter_budget, &it, &res, &sk));
+      PB_TRY(gmres(ctx, K, op64, prec, g, p, opts.tol * gnorm, 0.0, iter_budget, &it, &res, &sk, from_zero));
       n64 -= sk;
       if (prec) nnn -= sk;
       iters += it;
@@ -503,7 +508,8 @@ extern "C" pb_status pb_ibim_solve(pb_ctx* ctx, const pb_band* band, const doubl
       int it = 0;
       double res = 0.0;
       int sk = 0;
-      PB_TRY(gmres(ctx, K, opmx, prec, g, p, 0.5 * opts.tol * gnorm, kInnerEta, iter_budget, &it, &res, &sk));
+      PB_TRY(gmres(ctx, K, opmx, prec, g, p, 0.5 * opts.tol * gnorm, kInnerEta, iter_budget, &it, &res, &sk,
+                   from_zero));
       nmx -= sk;
       if (prec) nnn -= sk;
       used += it;
@@ -529,7 +535,7 @@ extern "C" pb_status pb_ibim_solve(pb_ctx* ctx, const pb_band* band, const doubl
       double res = 0.0;
       int sk = 0;
       PB_TRY(gmres(ctx, K, opmx, prec, r, dx, 0.5 * opts.tol * gnorm, kInnerEta, iter_budget - used, &it, &res,
-                   &sk));
+                   &sk, true));
       nmx -= sk;
       if (prec) nnn -= sk;
       used += it;

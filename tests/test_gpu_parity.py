@@ -190,6 +190,23 @@ def test_born_solve_iteration_budget(pbm, ctx, born):
     assert st2.converged and st2.true_relres <= 1e-10
 
 
+@pytest.mark.parametrize("x0", ["zero", "diag"])
+def test_mixed_solve_application_count(pbm, ctx, born, x0):
+    """Refinement bookkeeping, with one restart cycle per inner solve: the inner solves spend
+    one mixed application per Arnoldi step; a solve that starts from zero (x0 = 0, and every
+    correction solve) forms its first residual without one, and a cycle that ends on its
+    residual estimate is not confirmed by another (the FP64 residual follows). The FP64
+    operator runs once per refinement step."""
+    say(f"case: Born solve mixed tol 1e-10 restart 400, x0 {x0}")
+    mode = pbm.PB_X0_ZERO if x0 == "zero" else pbm.PB_X0_DIAG
+    opts = pbm.solve_opts(tol=1e-10, precision=pbm.PB_MIXED, restart=400, max_iter=400, x0=mode)
+    p, st = pbm.pb_ibim_solve(ctx, born["band"], born["at"], born["prm"], opts)
+    say(f"  iterations {st.iters}, outer {st.outer}, mixed applications {st.matvecs_mixed}, FP64 {st.matvecs_fp64}")
+    assert st.converged and st.true_relres <= 1e-10 and st.outer >= 2
+    assert st.matvecs_fp64 == st.outer
+    assert st.matvecs_mixed == st.iters + (0 if x0 == "zero" else 1)
+
+
 @pytest.mark.parametrize("restart", [100, 5])
 def test_born_solve_mixed(pbm, ctx, born, restart):
     say(f"case: Born solve mixed tol 1e-8 restart {restart}")
