@@ -137,7 +137,11 @@ typedef struct {
   int converged;        /* 1 if the true residual met tol */
   int fallback_used;    /* 1 if the learned path was abandoned for plain GMRES */
   int matvecs_fp64;     /* FP64 operator applications */
-  int matvecs_mixed;    /* mixed-precision operator applications */
+  int matvecs_mixed;    /* mixed-precision (or treecode) operator applications: one per Arnoldi
+                           step, one per restart that ends on the restart length, one for a
+                           non-zero starting vector; a cycle that ends on its residual
+                           estimate takes none (the FP64 or fine residual of the refinement
+                           follows), nor does a solve from zero */
   double true_relres;   /* ‖g − Ap‖₂/‖g‖₂ with the FP64 operator, at exit */
   double t_total_s;     /* wall time of the call */
   double t_matvec_s;    /* device time inside the operator kernels */
