@@ -52,7 +52,7 @@ WORKLOADS = {
     "heldout5000": (5000, 200000, 0.5),
 }
 
-WEIGHTS = os.path.join(ROOT, "paper_1709_08070_amd", "weights", "learned_h0.5.npz")
+WEIGHTS = os.path.join(ROOT, "paper_1709_08070_amd", "weights", "learned_mixh.npz")
 
 
 def log(*a):

@@ -53,15 +53,16 @@ def make_example(ctx: pb.Context, n_atoms: int, seed: int, h: float, n_random: i
 
 def train(ctx: pb.Context, net: pb.Net, n_mol: int = 2000, lo: int = 200, hi: int = 1500, h: float = 0.5,
           seed0: int = 100000, epochs: int = 2, lr: float = 1e-3, n_random: int = 1, log=None,
-          tol: float = 1e-8) -> dict:
+          tol: float = 1e-8, h_choices=None) -> dict:
     """Builds the training set (n_mol molecules, atom counts uniform in [lo, hi], seeds
-    seed0 + i) and trains."""
+    seed0 + i, grid spacing h or, with h_choices, one of those drawn per molecule) and trains."""
     rng = np.random.default_rng(seed0)
     t0 = time.perf_counter()
     data = []
     for i in range(n_mol):
         na = int(rng.integers(lo, hi + 1))
-        data.append(make_example(ctx, na, seed0 + i, h, n_random, rng, tol))
+        hm = float(h_choices[int(rng.integers(len(h_choices)))]) if h_choices else h
+        data.append(make_example(ctx, na, seed0 + i, hm, n_random, rng, tol))
         if log and (i + 1) % max(1, n_mol // 10) == 0:
             log(f"training set: {i + 1}/{n_mol} molecules")
     t_data = time.perf_counter() - t0
@@ -107,6 +108,7 @@ def main(argv=None):
     ap.add_argument("--tol", type=float, default=1e-7, help="tolerance of the solves that give the targets")
     ap.add_argument("--net-seed", type=int, default=1)
     ap.add_argument("--n-random", type=int, default=1, help="random-field pairs per molecule besides (g, p*)")
+    ap.add_argument("--h-choices", default="", help="comma-separated grid spacings, one drawn per molecule")
     ap.add_argument("--out", required=True)
     args = ap.parse_args(argv)
 
@@ -116,9 +118,11 @@ def main(argv=None):
     ctx = pb.Context(0)
     net = pb.Net(ctx, seed=args.net_seed)
     info = train(ctx, net, n_mol=args.molecules, lo=args.lo, hi=args.hi, h=args.h, seed0=args.seed0,
-                 epochs=args.epochs, lr=args.lr, n_random=args.n_random, log=log, tol=args.tol)
+                 epochs=args.epochs, lr=args.lr, n_random=args.n_random, log=log, tol=args.tol,
+                 h_choices=[float(x) for x in args.h_choices.split(",") if x] or None)
     net.save(args.out)
-    info.update({k: getattr(args, k) for k in ("lo", "hi", "h", "seed0", "lr", "tol", "net_seed", "n_random")})
+    info.update({k: getattr(args, k) for k in ("lo", "hi", "h", "seed0", "lr", "tol", "net_seed", "n_random",
+                                                 "h_choices")})
     with open(args.out.rsplit(".", 1)[0] + ".json", "w") as f:
         json.dump(info, f, indent=1)
     log(f"saved {args.out}: loss per epoch {info['loss']}, data {info['t_data_s']:.0f} s, "

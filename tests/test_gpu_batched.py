@@ -117,7 +117,7 @@ def test_batch64_full_size_sampled(pbm):
     import os
 
     wpath = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1709_08070_amd",
-                         "weights", "learned_h0.5.npz")
+                         "weights", "learned_mixh.npz")
     if os.path.exists(wpath):
         net = pbm.Net(ctx, seed=1)
         net.load(wpath)

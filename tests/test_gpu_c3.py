@@ -121,7 +121,7 @@ def test_globule5000_sampled(pbm):
     assert e_gpu == pytest.approx(oE, rel=1e-10)
     # the benchmark's step solve: the committed network as x0 and right preconditioner
     wpath = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1709_08070_amd",
-                         "weights", "learned_h0.5.npz")
+                         "weights", "learned_mixh.npz")
     if os.path.exists(wpath):
         net = pbm.Net(ctx, seed=1)
         net.load(wpath)
@@ -203,7 +203,7 @@ def test_globule500_bench_step(pbm):
     rows = np.random.default_rng(13).choice(n, 64, replace=False)
     net = None
     wpath = _os.path.join(_os.path.dirname(_os.path.dirname(_os.path.abspath(__file__))), "paper_1709_08070_amd",
-                          "weights", "learned_h0.5.npz")
+                          "weights", "learned_mixh.npz")
     if _os.path.exists(wpath):
         net = pbm.Net(ctx, seed=1)
         net.load(wpath)

@@ -302,7 +302,7 @@ def test_committed_network_on_heldout_globule(pbm, ctx):
     import os
 
     wpath = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1709_08070_amd",
-                         "weights", "learned_h0.5.npz")
+                         "weights", "learned_mixh.npz")
     if not os.path.exists(wpath):
         pytest.skip("no committed network")
     say("case: committed network, held-out globule 5000 atoms seed 200000 h=0.5, tol 1e-6")

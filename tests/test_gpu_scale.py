@@ -86,7 +86,7 @@ def test_treecode_solves_at_2p5m_nodes(pbm):
     g = oracle.rhs(nodes, atoms, oprm)
     gs = np.concatenate([g[rows], g[n + rows]])
     wpath = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1709_08070_amd",
-                         "weights", "learned_h0.5.npz")
+                         "weights", "learned_mixh.npz")
     net = None
     kinds = [("tree", {})]
     if os.path.exists(wpath):

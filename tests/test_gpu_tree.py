@@ -154,7 +154,7 @@ def test_learned_tree_solve(pbm, ctx):
     say("case: learned + treecode solve, globule 120 atoms seed 31 h=0.5, tol 1e-8 (committed network)")
     prm, at, band = _pipeline(pbm, ctx, synth.globule(120, 31), 0.5, True)
     net = pbm.Net(ctx, seed=3)
-    net.load(os.path.join(os.path.dirname(pbm.__file__), "weights", "learned_h0.5.npz"))
+    net.load(os.path.join(os.path.dirname(pbm.__file__), "weights", "learned_mixh.npz"))
     opts = pbm.solve_opts(tol=1e-8, precision=pbm.PB_TREE, x0=pbm.PB_X0_LEARNED, precond=pbm.PB_PRECOND_LEARNED,
                           nn=net.handle)
     q, st = pbm.pb_ibim_solve(ctx, band, at, prm, opts)
