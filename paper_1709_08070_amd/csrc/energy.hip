@@ -13,6 +13,7 @@
 #include <cmath>
 #include <mutex>
 
+#include "fp64_math.hpp"
 #include "pb_internal.hpp"
 
 // ψ_rxn per atom for pb_solvation_energy_noalloc when the caller passes no array: 1 MiB
@@ -56,7 +57,7 @@ __global__ void __launch_bounds__(kBlock) k_rhs(int n, const double* __restrict_
         const double4 at = tile[q];
         double dx = x - at.x, dy = y - at.y, dz = z - at.z;
         double r2 = dx * dx + dy * dy + dz * dz;
-        double rinv = 1.0 / sqrt(r2);
+        double rinv = rsqrt_f64(r2);
         double dn = dx * a + dy * b + dz * c;
         double qe = at.w;
         s1 += qe * rinv;
@@ -70,36 +71,58 @@ __global__ void __launch_bounds__(kBlock) k_rhs(int n, const double* __restrict_
   }
 }
 
-// One block per atom: ψ_rxn(z_k) by a strided sum over the band and a fixed block tree.
-__global__ void __launch_bounds__(kBlock) k_psi_rxn(int n, const double* __restrict__ px, const double* __restrict__ py,
+constexpr int kPsiAtoms = 8;    // atoms per block of k_psi_rxn
+constexpr int kPsiBlock = 512;  // its threads: few blocks (n_atoms / 8), so wide ones
+
+// ψ_rxn of kPsiAtoms atoms per block: every thread reads the data of each of its nodes once
+// and adds that node's term to the sums of all the block's atoms, then one fixed-order block
+// reduction per atom. 1/ρ is rsqrt_f64 and e^{−κρ} exp_neg_f64 (fp64_math.hpp). Per pair, times
+// 4π: s(θ1 E(1 + κρ) − 1)/ρ³ · ψ̄_j + (1 − E)/ρ · ψ̄n_j, with the weight h³ω_j/4π.
+__global__ void __launch_bounds__(kPsiBlock) k_psi_rxn(int n, const double* __restrict__ px, const double* __restrict__ py,
                                                     const double* __restrict__ pz, const double* __restrict__ nx,
                                                     const double* __restrict__ ny, const double* __restrict__ nz,
                                                     const double* __restrict__ w, const double* __restrict__ p,
-                                                    const double* __restrict__ atoms, double th1, double kappa,
-                                                    double h3, double* __restrict__ psi) {
-  __shared__ double red[kBlock];
-  const int k = blockIdx.x;
-  const double zx = atoms[5 * k], zy = atoms[5 * k + 1], zz = atoms[5 * k + 2];
-  const double c4 = 1.0 / (4.0 * kPi);
-  double acc = 0.0;
-  for (int j = threadIdx.x; j < n; j += kBlock) {
-    double dx = zx - px[j], dy = zy - py[j], dz = zz - pz[j];
-    double rho = sqrt(dx * dx + dy * dy + dz * dz);
-    double s = dx * nx[j] + dy * ny[j] + dz * nz[j];
-    double E = exp(-kappa * rho);
-    double r3 = 1.0 / (rho * rho * rho);
-    double dG0 = c4 * s * r3;
-    double dGk = c4 * E * (1.0 + kappa * rho) * s * r3;
-    double G0mGk = c4 * (1.0 - E) / rho;
-    acc += h3 * w[j] * ((th1 * dGk - dG0) * p[j] + G0mGk * p[n + j]);
+                                                    const double* __restrict__ atoms, int n_atoms, double th1,
+                                                    double kappa, double h3, double* __restrict__ psi) {
+  __shared__ double red[kPsiBlock];
+  __shared__ double za[kPsiAtoms][3];
+  const int k0 = blockIdx.x * kPsiAtoms;
+  if (threadIdx.x < 3 * kPsiAtoms) {
+    const int a = threadIdx.x / 3, c = threadIdx.x % 3;
+    za[a][c] = k0 + a < n_atoms ? atoms[5 * (k0 + a) + c] : 0.0;  // a missing atom's sum is not stored
   }
-  red[threadIdx.x] = acc;
   __syncthreads();
-  for (int off = kBlock / 2; off > 0; off >>= 1) {
-    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+  const double c4 = h3 / (4.0 * kPi);
+  double acc[kPsiAtoms];
+#pragma unroll
+  for (int a = 0; a < kPsiAtoms; ++a) acc[a] = 0.0;
+  for (int j = threadIdx.x; j < n; j += kPsiBlock) {
+    const double yx = px[j], yy = py[j], yz = pz[j], nxj = nx[j], nyj = ny[j], nzj = nz[j];
+    const double ww = c4 * w[j];
+    const double w1 = ww * p[j], w2 = ww * p[n + j];
+#pragma unroll
+    for (int a = 0; a < kPsiAtoms; ++a) {
+      const double dx = za[a][0] - yx, dy = za[a][1] - yy, dz = za[a][2] - yz;
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      const double rinv = rsqrt_f64(r2);
+      const double z = kappa * (r2 * rinv);
+      const double E = exp_neg_f64(z);
+      const double s = dx * nxj + dy * nyj + dz * nzj;
+      const double r3 = rinv * rinv * rinv;
+      acc[a] += w1 * (s * r3 * (th1 * fma(E, z, E) - 1.0)) + w2 * ((1.0 - E) * rinv);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < kPsiAtoms; ++a) {
+    red[threadIdx.x] = acc[a];
+    __syncthreads();
+    for (int off = kPsiBlock / 2; off > 0; off >>= 1) {
+      if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0 && k0 + a < n_atoms) psi[k0 + a] = red[0];
     __syncthreads();
   }
-  if (threadIdx.x == 0) psi[k] = red[0];
 }
 
 // The fields of pb_energy in order: out[0] = G_pol = ½ Σ_k q_k ψ_k, out[1] = G_pol in kcal/mol,
@@ -133,8 +156,9 @@ __global__ void __launch_bounds__(kBlock) k_finish(int n_atoms, const double* __
 void energy_launch(pb_ctx* ctx, const pb_band* band, const double* atoms, int n_atoms, const Derived& d,
                    const double* p, double* psi, double* out) {
   const int n = (int)band->n;
-  k_psi_rxn<<<n_atoms, kBlock, 0, ctx->stream>>>(n, band->px, band->py, band->pz, band->nx, band->ny, band->nz,
-                                                 band->w, p, atoms, d.th1, d.kappa, d.h3, psi);
+  k_psi_rxn<<<(n_atoms + kPsiAtoms - 1) / kPsiAtoms, kPsiBlock, 0, ctx->stream>>>(
+      n, band->px, band->py, band->pz, band->nx, band->ny, band->nz, band->w, p, atoms, n_atoms, d.th1, d.kappa, d.h3,
+      psi);
   k_finish<<<1, kBlock, 0, ctx->stream>>>(n_atoms, atoms, psi, n, band->w, d.h3, out);
 }
 

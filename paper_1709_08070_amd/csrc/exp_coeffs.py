@@ -1,5 +1,5 @@
 """Coefficients of the degree-11 polynomial for e^t on |t| ≤ ln2/2 used by exp_neg_f64
-(sym64_kernels.hpp): the interpolant of e^t at the 12 Chebyshev nodes of the interval
+(fp64_math.hpp): the interpolant of e^t at the 12 Chebyshev nodes of the interval
 (near-minimax), solved in the monomial basis in 60-digit arithmetic and rounded to doubles.
 Prints the coefficients (t^0 first) and the largest relative error of their Horner
 evaluation on a 4001-point grid, measured in 60-digit arithmetic (1.7e-17; the Taylor
