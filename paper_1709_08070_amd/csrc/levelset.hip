@@ -33,34 +33,77 @@ __device__ __forceinline__ int64_t lin(const GridDev& g, int64_t i, int64_t j, i
 
 __device__ __forceinline__ double sq(double a) { return a * a; }
 
-// F(x) − shift over all atoms, atoms staged through LDS in tiles.
+// F(x) − shift, F = min over atoms of |x − z| − r, on tiles of kTI × kTJ × kTK nodes (one block
+// each, k fastest inside the tile). The tile's nodes lie within R of its centre c, so for every
+// node F ≤ U + R with U = min_k(|c − z_k| − r_k), and an atom can attain the minimum at a node of
+// the tile only if |c − z_k| ≤ U + 2R + r_k. The block keeps those atoms (with a margin far
+// above the rounding of both sides) in LDS and takes the minimum over them, with the same
+// per-atom arithmetic as a scan over all atoms, so F is the same to the last bit; a tile that
+// keeps more than kVdwList atoms scans them all.
+constexpr int kTI = 4, kTJ = 8, kTK = 8;  // kTI·kTJ·kTK = kBlock
+constexpr int kVdwList = 512;
+static_assert(kTI * kTJ * kTK == kBlock, "one node per thread");
+
+// One atom's candidate for F at x, with the skip of atoms that cannot lower best (their
+// distance exceeds best + r by a relative margin far above the rounding of both sides).
+__device__ __forceinline__ void vdw_update(double x, double y, double z, const double4& at, double& best) {
+  const double d2 = (sq(x - at.x) + sq(y - at.y)) + sq(z - at.z);
+  const double lim = best + at.w;
+  if (lim > 0.0 && d2 < lim * lim * (1.0 + 1e-12)) {
+    const double dist = sqrt(d2) - at.w;
+    best = dist < best ? dist : best;
+  }
+}
+
 __global__ void __launch_bounds__(kBlock) k_vdw(GridDev g, const double* __restrict__ atoms, int n_atoms,
                                                 double shift, double* __restrict__ phi) {
-  __shared__ double4 tile[kBlock];
-  int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  int64_t total = (int64_t)g.nx * g.ny * g.nz;
-  int64_t k = id % g.nz, j = (id / g.nz) % g.ny, i = id / ((int64_t)g.ny * g.nz);
-  double x = g.ox + g.h * (double)i, y = g.oy + g.h * (double)j, z = g.oz + g.h * (double)k;
-  double best = INFINITY;
-  for (int base = 0; base < n_atoms; base += kBlock) {
-    int a = base + threadIdx.x;
-    if (a < n_atoms) tile[threadIdx.x] = make_double4(atoms[5 * a], atoms[5 * a + 1], atoms[5 * a + 2], atoms[5 * a + 3]);
-    __syncthreads();
-    int m = min(kBlock, n_atoms - base);
-    for (int q = 0; q < m; ++q) {
-      double4 at = tile[q];
-      const double d2 = (sq(x - at.x) + sq(y - at.y)) + sq(z - at.z);
-      // |x − z| − r < best needs |x − z| < best + r: atoms that fail that (with a relative
-      // margin far above the rounding of both sides) cannot lower best, and skip the sqrt
-      const double lim = best + at.w;
-      if (lim > 0.0 && d2 < lim * lim * (1.0 + 1e-12)) {
-        const double dist = sqrt(d2) - at.w;
-        best = dist < best ? dist : best;
-      }
-    }
+  __shared__ double4 list[kVdwList];
+  __shared__ double red[kBlock];
+  __shared__ int count;
+  const int ntk = (g.nz + kTK - 1) / kTK, ntj = (g.ny + kTJ - 1) / kTJ;
+  const int tile = blockIdx.x;
+  const int bk = tile % ntk, bj = (tile / ntk) % ntj, bi = tile / (ntk * ntj);
+  const int t = threadIdx.x;
+  const int i = bi * kTI + t / (kTJ * kTK), j = bj * kTJ + (t / kTK) % kTJ, k = bk * kTK + t % kTK;
+  const bool live = i < g.nx && j < g.ny && k < g.nz;
+  const double x = g.ox + g.h * (double)i, y = g.oy + g.h * (double)j, z = g.oz + g.h * (double)k;
+  // centre and radius of the full tile
+  const double cx = g.ox + g.h * (bi * kTI + 0.5 * (kTI - 1)), cy = g.oy + g.h * (bj * kTJ + 0.5 * (kTJ - 1)),
+               cz = g.oz + g.h * (bk * kTK + 0.5 * (kTK - 1));
+  const double R = g.h * 0.5 * sqrt((double)((kTI - 1) * (kTI - 1) + (kTJ - 1) * (kTJ - 1) + (kTK - 1) * (kTK - 1)));
+  if (t == 0) count = 0;
+  // U = min over atoms of |c − z| − r
+  double u = INFINITY;
+  for (int a = t; a < n_atoms; a += kBlock) {
+    const double ax = atoms[5 * a], ay = atoms[5 * a + 1], az = atoms[5 * a + 2], ar = atoms[5 * a + 3];
+    const double dc = sqrt((sq(cx - ax) + sq(cy - ay)) + sq(cz - az)) - ar;
+    u = dc < u ? dc : u;
+  }
+  red[t] = u;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (t < off) red[t] = red[t + off] < red[t] ? red[t + off] : red[t];
     __syncthreads();
   }
-  if (id < total) phi[id] = best - shift;
+  const double reach = red[0] + 2.0 * R;  // an atom matters only within reach + r of c
+  for (int a = t; a < n_atoms; a += kBlock) {
+    const double ax = atoms[5 * a], ay = atoms[5 * a + 1], az = atoms[5 * a + 2], ar = atoms[5 * a + 3];
+    const double lim = (reach + ar) * (1.0 + 1e-9) + 1e-9 * (1.0 + g.h);
+    if (lim > 0.0 && (sq(cx - ax) + sq(cy - ay)) + sq(cz - az) <= lim * lim) {
+      const int q = atomicAdd(&count, 1);
+      if (q < kVdwList) list[q] = make_double4(ax, ay, az, ar);
+    }
+  }
+  __syncthreads();
+  const int m = count;
+  double best = INFINITY;
+  if (m <= kVdwList) {
+    for (int q = 0; q < m; ++q) vdw_update(x, y, z, list[q], best);
+  } else {
+    for (int a = 0; a < n_atoms; ++a)
+      vdw_update(x, y, z, make_double4(atoms[5 * a], atoms[5 * a + 1], atoms[5 * a + 2], atoms[5 * a + 3]), best);
+  }
+  if (live) phi[((int64_t)i * g.ny + j) * g.nz + k] = best - shift;
 }
 
 // Godunov |∇φ| for the Hamiltonian s·|∇φ| at node id = (i, j, k) (32-bit indexing; grids
@@ -316,7 +359,9 @@ extern "C" pb_status pb_build_levelset(pb_ctx* ctx, const double* atoms, int n_a
   const bool ses = prm->ls_mode == PB_LS_SES;
   {
     Scope t(ctx, "levelset");
-    k_vdw<<<nb, kBlock, 0, ctx->stream>>>(g, atoms, n_atoms, ses ? prm->probe : 0.0, phi);
+    const unsigned tiles = (unsigned)(((g.nx + kTI - 1) / kTI) * (int64_t)((g.ny + kTJ - 1) / kTJ) *
+                                      ((g.nz + kTK - 1) / kTK));
+    k_vdw<<<tiles, kBlock, 0, ctx->stream>>>(g, atoms, n_atoms, ses ? prm->probe : 0.0, phi);
   }
   PB_TRY(launch_ok(ctx, "vdw"));
   if (!ses) return sync(ctx, "pb_build_levelset");
