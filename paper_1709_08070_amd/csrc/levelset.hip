@@ -8,7 +8,9 @@
 // Layout: φ is one FP64 array, k fastest. Each stencil kernel maps one thread to one node;
 // consecutive threads are consecutive k, so the ±k neighbours are coalesced and the ±i/±j
 // neighbours are served from L2. Products and sums are rounded as written (no FMA
-// contraction), so the grid values are reproducible to the last bit from run to run.
+// contraction) except in the Godunov Hamiltonian of the stage kernel, where the compiler
+// fuses them into FMAs; either way the grid values are the same to the last bit from run
+// to run.
 #include <cmath>
 #include <utility>
 
@@ -106,59 +108,94 @@ __global__ void __launch_bounds__(kBlock) k_vdw(GridDev g, const double* __restr
   if (live) phi[((int64_t)i * g.ny + j) * g.nz + k] = best - shift;
 }
 
-// Godunov |∇φ| for the Hamiltonian s·|∇φ| at node id = (i, j, k) (32-bit indexing; grids
-// hold fewer than 2^31 nodes). ih = 1/h.
-__device__ double godunov(const GridDev& g, const double* __restrict__ phi, int id, int i, int j, int k, double ih,
-                          double s) {
-  double acc = 0.0;
-  const int n3[3] = {g.nx, g.ny, g.nz};
-  const int c[3] = {i, j, k};
-  const int stride[3] = {g.ny * g.nz, g.nz, 1};
-  for (int ax = 0; ax < 3; ++ax) {
-    double f[7];
-    for (int sft = -3; sft <= 3; ++sft) {
-      int q = c[ax] + sft;
-      // zero-Neumann ghosts: even reflection about the boundary node, −m ↦ m, n−1+m ↦ n−1−m
-      q = q < 0 ? -q : (q > n3[ax] - 1 ? 2 * (n3[ax] - 1) - q : q);
-      f[sft + 3] = phi[id + (q - c[ax]) * stride[ax]];
-    }
-    double D[6];
-    for (int m = 0; m < 6; ++m) D[m] = (f[m + 1] - f[m]) * ih;
-    double a = weno5(D[0], D[1], D[2], D[3], D[4]);
-    double b = weno5(D[5], D[4], D[3], D[2], D[1]);
-    if (s >= 0.0) acc += fmax(sq(fmax(a, 0.0)), sq(fmin(b, 0.0)));
-    else acc += fmax(sq(fmin(a, 0.0)), sq(fmax(b, 0.0)));
-  }
-  return sqrt(acc);
+// One axis of the Godunov Hamiltonian sg·|∇φ| (sg = ±1) from the seven values f[0..6] centred
+// on the node: the WENO5 one-sided derivatives a (differences d0..d4) and b (d5..d1), then
+// max((a⁺)², (b⁻)²) for sg > 0 and max((a⁻)², (b⁺)²) for sg < 0. It works on the differences
+// d = h·D instead of the divided differences D: the smoothness indicators are taken ×12h²
+// (so ε enters as e = 12h²ε, the same weights), the weights ×10 and the candidate stencils ×6h,
+// so the value returned is (6h)² times the axis's term; both one-sided derivatives share their
+// common second differences, and the larger of the two quotients is chosen by cross
+// multiplication (their denominators are positive), one division instead of two.
+struct Frac {
+  double n, d;
+};
+
+__device__ __forceinline__ Frac weno_frac(double b1, double b2, double b3, double e, double p1, double p2,
+                                          double p3) {
+#pragma clang fp contract(fast)
+  const double q1 = sq(b1 + e), q2 = sq(b2 + e), q3 = sq(b3 + e);
+  const double w1 = q2 * q3, w2 = 6.0 * (q1 * q3), w3 = 3.0 * (q1 * q2);
+  return {w1 * p1 + w2 * p2 + w3 * p3, (w1 + w2) + w3};
+}
+
+__device__ __forceinline__ double godunov_axis(const double f[7], double e, double sg) {
+#pragma clang fp contract(fast)
+  const double d0 = f[1] - f[0], d1 = f[2] - f[1], d2 = f[3] - f[2], d3 = f[4] - f[3], d4 = f[5] - f[4],
+               d5 = f[6] - f[5];
+  const double t0 = (d0 - 2.0 * d1) + d2, t1 = (d1 - 2.0 * d2) + d3, t2 = (d2 - 2.0 * d3) + d4,
+               t3 = (d3 - 2.0 * d4) + d5;
+  const double s1 = 13.0 * sq(t1), s2 = 13.0 * sq(t2);
+  const Frac a = weno_frac(13.0 * sq(t0) + 3.0 * sq((d0 - 4.0 * d1) + 3.0 * d2), s1 + 3.0 * sq(d1 - d3),
+                           s2 + 3.0 * sq((3.0 * d2 - 4.0 * d3) + d4), e, (2.0 * d0 - 7.0 * d1) + 11.0 * d2,
+                           (5.0 * d2 - d1) + 2.0 * d3, (2.0 * d2 + 5.0 * d3) - d4);
+  const Frac b = weno_frac(13.0 * sq(t3) + 3.0 * sq((d5 - 4.0 * d4) + 3.0 * d3), s2 + 3.0 * sq(d4 - d2),
+                           s1 + 3.0 * sq((3.0 * d3 - 4.0 * d2) + d1), e, (2.0 * d5 - 7.0 * d4) + 11.0 * d3,
+                           (5.0 * d3 - d4) + 2.0 * d2, (2.0 * d3 + 5.0 * d2) - d1);
+  const double A = fmax(sg * a.n, 0.0), B = fmax(-sg * b.n, 0.0);
+  const double x = A * b.d >= B * a.d ? A / a.d : B / b.d;
+  return x * x;
 }
 
 // One TVD-RK3 stage: L = L(φ_in), then
 //   stage 0: out = φ_in + dt·L
 //   stage 1: out = 0.75 φ_n + 0.25 (φ_in + dt·L)
 //   stage 2: out = φ_n / 3 + (2/3)(φ_in + dt·L)
-// mode 0: eikonal flow (L = |∇φ| with Hamiltonian −|∇φ|); mode 1: reinit (L = −S(|∇φ| − 1)).
+// MODE 0: eikonal flow (L = |∇φ| with Hamiltonian −|∇φ|); MODE 1: reinit (L = −S(|∇φ| − 1)).
+// |∇φ| is the Godunov Hamiltonian with zero-Neumann ghosts (even reflection about the boundary
+// node, −m ↦ m and n−1+m ↦ n−1−m), taken only by nodes within three of a face; e = 12h²ε and
+// c = 1/(6h) undo the scaling of godunov_axis. 32-bit node indexing (grids hold fewer than 2^31
+// nodes).
+template <int MODE>
 __global__ void __launch_bounds__(kBlock) k_rk_stage(GridDev g, const double* __restrict__ phi_in,
                                                      const double* __restrict__ phi_n, const double* __restrict__ S,
-                                                     double* __restrict__ out, int mode, int stage, double dt) {
+                                                     double* __restrict__ out, int stage, double dt, double e,
+                                                     double c) {
   const unsigned total = (unsigned)g.nx * (unsigned)g.ny * (unsigned)g.nz;
   const unsigned uid = blockIdx.x * kBlock + threadIdx.x;
   if (uid >= total) return;
   const unsigned t = uid / (unsigned)g.nz;
   const int k = (int)(uid - t * (unsigned)g.nz), j = (int)(t % (unsigned)g.ny), i = (int)(t / (unsigned)g.ny);
-  const int id = (int)uid;
-  const double ih = 1.0 / g.h;
-  double L;
-  if (mode == 0) {
-    L = godunov(g, phi_in, id, i, j, k, ih, -1.0);
-  } else {
-    double s = S[id];
-    L = -s * (godunov(g, phi_in, id, i, j, k, ih, s) - 1.0);
+  const double* __restrict__ p = phi_in + uid;
+  const int n3[3] = {g.nx, g.ny, g.nz};
+  const int c3[3] = {i, j, k};
+  const int stride[3] = {g.ny * g.nz, g.nz, 1};
+  double s = -1.0;
+  if (MODE == 1) s = S[uid];
+  const double sg = s >= 0.0 ? 1.0 : -1.0;
+  double acc = 0.0, f[7];
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    if ((unsigned)(c3[ax] - 3) <= (unsigned)(n3[ax] - 7)) {
+#pragma unroll
+      for (int m = 0; m < 7; ++m) f[m] = p[(m - 3) * stride[ax]];
+    } else {
+#pragma unroll
+      for (int m = 0; m < 7; ++m) {
+        int q = c3[ax] + m - 3;
+        q = q < 0 ? -q : (q > n3[ax] - 1 ? 2 * (n3[ax] - 1) - q : q);
+        f[m] = p[(q - c3[ax]) * stride[ax]];
+      }
+    }
+    acc += godunov_axis(f, e, sg);
   }
+  const double G = sqrt(acc) * c;
+  const double L = MODE == 0 ? G : -s * (G - 1.0);
+  const double v0 = p[0] + dt * L;
   double v;
-  if (stage == 0) v = phi_in[id] + dt * L;
-  else if (stage == 1) v = 0.75 * phi_n[id] + 0.25 * (phi_in[id] + dt * L);
-  else v = phi_n[id] * (1.0 / 3.0) + (2.0 / 3.0) * (phi_in[id] + dt * L);
-  out[id] = v;
+  if (stage == 0) v = v0;
+  else if (stage == 1) v = 0.75 * phi_n[uid] + 0.25 * v0;
+  else v = phi_n[uid] * (1.0 / 3.0) + (2.0 / 3.0) * v0;
+  out[uid] = v;
 }
 
 __global__ void __launch_bounds__(kBlock) k_sign(int64_t total, const double* __restrict__ phi, double h,
@@ -315,12 +352,14 @@ pb_status tvd_rk3(pb_ctx* ctx, const GridDev& g, double* phi, double* p1, double
                   int steps, double dt) {
   int64_t total = (int64_t)g.nx * g.ny * g.nz;
   unsigned nb = blocks_for(total);
+  const double e = 12.0 * g.h * g.h * kWenoEps, c = 1.0 / (6.0 * g.h);
   double *cur = phi, *spare = p1;
   for (int s = 0; s < steps; ++s) {
     Scope t(ctx, "levelset");
-    k_rk_stage<<<nb, kBlock, 0, ctx->stream>>>(g, cur, cur, S, spare, mode, 0, dt);
-    k_rk_stage<<<nb, kBlock, 0, ctx->stream>>>(g, spare, cur, S, p2, mode, 1, dt);
-    k_rk_stage<<<nb, kBlock, 0, ctx->stream>>>(g, p2, cur, S, spare, mode, 2, dt);
+    auto stage = mode == 0 ? k_rk_stage<0> : k_rk_stage<1>;
+    stage<<<nb, kBlock, 0, ctx->stream>>>(g, cur, cur, S, spare, 0, dt, e, c);
+    stage<<<nb, kBlock, 0, ctx->stream>>>(g, spare, cur, S, p2, 1, dt, e, c);
+    stage<<<nb, kBlock, 0, ctx->stream>>>(g, p2, cur, S, spare, 2, dt, e, c);
     std::swap(cur, spare);
   }
   if (cur != phi) PB_HIP(ctx, hipMemcpyAsync(phi, cur, sizeof(double) * total, hipMemcpyDeviceToDevice, ctx->stream));

@@ -7,6 +7,9 @@ namespace pb {
 
 __device__ __forceinline__ double stencil_sq(double a) { return a * a; }
 
+// ε of the WENO5 weights α_k = d_k/(ε + β_k)², with β_k in units of the divided differences.
+constexpr double kWenoEps = 1e-6;
+
 // Fifth-order WENO one-sided derivative from five consecutive differences. The weights
 // α_k = d_k/(ε + β_k)² are normalized as α_k/Σα = d_k q_l q_m / Σ d_k q_l q_m with
 // q = (ε + β)², the same quotient with one division instead of four; the constant
@@ -14,7 +17,7 @@ __device__ __forceinline__ double stencil_sq(double a) { return a * a; }
 // (no FMA contraction), like the stencil kernels that call it.
 __device__ __forceinline__ double weno5(double v1, double v2, double v3, double v4, double v5) {
 #pragma clang fp contract(off)
-  const double e = 1e-6;
+  const double e = kWenoEps;
   double s1 = 13.0 / 12.0 * stencil_sq(v1 - 2.0 * v2 + v3) + 0.25 * stencil_sq(v1 - 4.0 * v2 + 3.0 * v3);
   double s2 = 13.0 / 12.0 * stencil_sq(v2 - 2.0 * v3 + v4) + 0.25 * stencil_sq(v2 - v4);
   double s3 = 13.0 / 12.0 * stencil_sq(v3 - 2.0 * v4 + v5) + 0.25 * stencil_sq(3.0 * v3 - 4.0 * v4 + v5);
