@@ -32,14 +32,15 @@ __device__ __forceinline__ double exp_neg_f64(double z) {
   return ldexp(p, (int)k);
 }
 
-// 1/√x for x > 0: the hardware estimate (about 2^-24 relative) and two Newton steps
-// y ← y + y(½ − ½xy²), within an ulp or two of the correctly rounded value.
+// 1/√x for x > 0: the hardware estimate y (about 2^-24 relative) and one third-order step of
+// the series (1 − e)^{−1/2} = 1 + e/2 + 3e²/8 + … with e = 1 − xy², y ← y + ye(½ + 3e/8): the
+// truncation leaves about 2.5δ³ for an estimate off by δ, far below an ulp, so the result is
+// within an ulp of the correctly rounded value, like two Newton steps, in two fewer
+// instructions (checked on the CPU against long-double 1/√x with |δ| up to 2^-20).
 __device__ __forceinline__ double rsqrt_f64(double x) {
-  const double hx = 0.5 * x;
-  double y = __builtin_amdgcn_rsq(x);
-  y = fma(y, fma(-hx * y, y, 0.5), y);
-  y = fma(y, fma(-hx * y, y, 0.5), y);
-  return y;
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = fma(-(x * y), y, 1.0);
+  return fma(y * e, fma(e, 0.375, 0.5), y);
 }
 
 }  // namespace pb

@@ -22,7 +22,7 @@ namespace pb {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kDotBlocks = 512;
+constexpr int kDotBlocks = 1024;
 constexpr int kGroup = 8;
 constexpr int kMaxRestart = 2000;  // the largest restart length pb_ibim_solve accepts
 
@@ -80,22 +80,43 @@ __device__ void givens_step(const GivensArgs& g) {
   g.host_out[1] = k + 1;
 }
 
-// partial[q·nb + block] = Σ_{e in block's stride} w[e]·V[q][e], q < k, in groups of 8
-// vectors so that w is read once per group. The block's elements are e = block·kBlock + tid
-// + i·nb·kBlock.
+// Whether the vectors can be read as pairs of doubles: an even length and leading dimension
+// and 16-byte aligned bases (the solver's vectors always are: length 2N, workspace bases).
+__device__ __forceinline__ bool pairs_ok(int64_t M, int64_t ldv, const void* V, const void* w) {
+  return ((M | ldv) & 1) == 0 && (((uintptr_t)V | (uintptr_t)w) & 15) == 0;
+}
+
+// partial[q·nb + block] = Σ_{e in the block's share} w[e]·V[q][e], q < k, in groups of 8
+// vectors so that w is read once per group. The block's share is the pairs (2p, 2p + 1) with
+// p = block·kBlock + tid + i·nb·kBlock, read as 16-byte loads, or, when pairs_ok fails, the
+// single elements e at the same positions (pairs = false).
 __device__ __forceinline__ void block_dots(int64_t M, const double* __restrict__ V, int64_t ldv, int k,
-                                           const double* __restrict__ w, double* __restrict__ partial,
-                                           double (*red)[kBlock]) {
+                                           const double* __restrict__ w, bool pairs,
+                                           double* __restrict__ partial, double (*red)[kBlock]) {
+  const int64_t P = pairs ? M >> 1 : M, step = (int64_t)gridDim.x * kBlock;
   for (int q0 = 0; q0 < k; q0 += kGroup) {
     double acc[kGroup];
 #pragma unroll
     for (int g = 0; g < kGroup; ++g) acc[g] = 0.0;
     const int nq = min(kGroup, k - q0);
-    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < M; e += (int64_t)gridDim.x * kBlock) {
-      const double we = w[e];
+    if (pairs) {
+      const double2* __restrict__ w2 = reinterpret_cast<const double2*>(w);
+      for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < P; p += step) {
+        const double2 we = w2[p];
 #pragma unroll
-      for (int g = 0; g < kGroup; ++g)
-        if (g < nq) acc[g] += we * V[(int64_t)(q0 + g) * ldv + e];
+        for (int g = 0; g < kGroup; ++g)
+          if (g < nq) {
+            const double2 v = reinterpret_cast<const double2*>(V + (int64_t)(q0 + g) * ldv)[p];
+            acc[g] = fma(we.y, v.y, fma(we.x, v.x, acc[g]));
+          }
+      }
+    } else {
+      for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < P; e += step) {
+        const double we = w[e];
+#pragma unroll
+        for (int g = 0; g < kGroup; ++g)
+          if (g < nq) acc[g] = fma(we, V[(int64_t)(q0 + g) * ldv + e], acc[g]);
+      }
     }
 #pragma unroll
     for (int g = 0; g < kGroup; ++g) red[g][threadIdx.x] = acc[g];
@@ -114,24 +135,43 @@ __device__ __forceinline__ void block_dots(int64_t M, const double* __restrict__
 __global__ void __launch_bounds__(kBlock) k_dots(int64_t M, const double* __restrict__ V, int64_t ldv, int k,
                                                  const double* __restrict__ w, double* __restrict__ partial) {
   __shared__ double red[kGroup][kBlock];
-  block_dots(M, V, ldv, k, w, partial, red);
+  block_dots(M, V, ldv, k, w, pairs_ok(M, ldv, V, w), partial, red);
 }
 
 // One Gram–Schmidt update and the next reduction in one launch: w[e] −= Σ_q c[q]·V[q][e]
-// (q < k) over the block's elements, then the partial sums of w·V[q] (q < k; kd = k) or of w·w
-// (kd = 1, V = w, ldv = 0). Each block reads back only the elements it wrote itself, so no
-// grid-wide synchronization is needed between the two phases.
+// (q < k) over the block's share (as in block_dots), then the partial sums of w·V[q] (q < k;
+// kd = k) or of w·w (kd = 1, V = w, ldv = 0). Both phases split the elements the same way (pairs
+// or single elements, decided once), so each thread reads back only the elements it wrote
+// itself and no grid-wide synchronization is needed between them.
 __global__ void __launch_bounds__(kBlock) k_axpy_dots(int64_t M, const double* __restrict__ V, int64_t ldv, int k,
                                                       const double* __restrict__ c, double* __restrict__ w,
                                                       int norm_only, double* __restrict__ partial) {
   __shared__ double red[kGroup][kBlock];
-  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < M; e += (int64_t)gridDim.x * kBlock) {
-    double s = 0.0;
-    for (int q = 0; q < k; ++q) s += c[q] * V[(int64_t)q * ldv + e];
-    w[e] -= s;
+  const int64_t step = (int64_t)gridDim.x * kBlock;
+  const bool pairs = pairs_ok(M, ldv, V, w);
+  if (pairs) {
+    double2* __restrict__ w2 = reinterpret_cast<double2*>(w);
+    for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < (M >> 1); p += step) {
+      double sx = 0.0, sy = 0.0;
+      for (int q = 0; q < k; ++q) {
+        const double2 v = reinterpret_cast<const double2*>(V + (int64_t)q * ldv)[p];
+        sx = fma(c[q], v.x, sx);
+        sy = fma(c[q], v.y, sy);
+      }
+      double2 x = w2[p];
+      x.x -= sx;
+      x.y -= sy;
+      w2[p] = x;
+    }
+  } else {
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < M; e += step) {
+      double s = 0.0;
+      for (int q = 0; q < k; ++q) s = fma(c[q], V[(int64_t)q * ldv + e], s);
+      w[e] -= s;
+    }
   }
-  if (norm_only) block_dots(M, w, 0, 1, w, partial, red);
-  else block_dots(M, V, ldv, k, w, partial, red);
+  if (norm_only) block_dots(M, w, 0, 1, w, pairs, partial, red);
+  else block_dots(M, V, ldv, k, w, pairs, partial, red);
 }
 
 // out[q] = Σ_b partial[q·nb + b] (one block per q, fixed tree); if sqrt_out, out[q] =

@@ -6,8 +6,8 @@
 //   K11(i,j) = (d·n_j)(1 − θ1 a)/r³,  K12 = (1 − E)/r,
 //   K21 = (n_i·n_j)(1 − a)/r³ − (d·n_i)(d·n_j)(3 − b)/r⁵,  K22(i,j) = −(d·n_i)(1 − θ2 a)/r³,
 // so K12 and K21 are symmetric and, with d → −d, K11(j,i) = −(d·n_i)(1 − θ1 a)/r³ and
-// K22(j,i) = (d·n_j)(1 − θ2 a)/r³. r, E, a, b (one reciprocal square root with two Newton
-// steps and one exp) are shared. The regularization predicate of the section
+// K22(j,i) = (d·n_j)(1 − θ2 a)/r³. r, E, a, b (one reciprocal square root with a third-order
+// correction and one exp) are shared. The regularization predicate of the section
 // "Regularization of the singular kernels" measures the tangential distance in the target's
 // tangent plane (t² = r² − (d·n_target)²), so each direction takes its own decision; a
 // regularized direction gets K11 = K21 = K22 = 0, K12 = K̄12. A pair at r = 0 is regularized in
@@ -104,11 +104,7 @@ __device__ __forceinline__ void pair_sym_f64(double xi, double yi, double zi, do
   // r² = 1 here, whose (finite) radial terms are discarded.
   const double r2s = (rf && rr) ? 1.0 : r2;
   const double nn = nxi * nxj + nyi * nyj + nzi * nzj;
-  double rinv = __builtin_amdgcn_rsq(r2s);
-  double e = fma(-r2s * rinv, rinv, 1.0);
-  rinv = fma(0.5 * rinv, e, rinv);
-  e = fma(-r2s * rinv, rinv, 1.0);
-  rinv = fma(0.5 * rinv, e, rinv);
+  const double rinv = rsqrt_f64(r2s);
   const double r = r2s * rinv;
   const double r3 = rinv * rinv * rinv;
   const double r5 = r3 * rinv * rinv;
@@ -140,11 +136,7 @@ __device__ __forceinline__ void pair_sym_f64_far(double xi, double yi, double zi
   const double dnx = fma(dz, nzi, fma(dy, nyi, dx * nxi));
   const double dny = fma(dz, nzj, fma(dy, nyj, dx * nxj));
   const double nn = fma(nzi, nzj, fma(nyi, nyj, nxi * nxj));
-  // 1/r: the hardware estimate and two Newton steps y ← y + y(½ − ½r²y²)
-  const double hr2 = 0.5 * r2;
-  double rinv = __builtin_amdgcn_rsq(r2);
-  rinv = fma(rinv, fma(-hr2 * rinv, rinv, 0.5), rinv);
-  rinv = fma(rinv, fma(-hr2 * rinv, rinv, 0.5), rinv);
+  const double rinv = rsqrt_f64(r2);
   const double ri2 = rinv * rinv;
   const double r3 = ri2 * rinv;
   const double z = kp.kappa * (r2 * rinv);
