@@ -35,7 +35,7 @@ namespace pb {
 
 struct Sym64Shared {
   double2 s0[kSymSub], s1[kSymSub], s2[kSymSub], s3[kSymSub];  // (x, y), (z, nx), (ny, nz), (wψ, wψn)
-  double racc[kSymWaves][2][kSymSub];
+  double racc[kSymWaves][2][64];  // one 64-source group's reverse sums per wave
   double box[kSymWaves][6];  // per-wave bounding boxes (lo xyz, hi xyz) of a block reduction
 };
 
@@ -162,33 +162,32 @@ __device__ __forceinline__ double shfl_next(double v, int addr) {
   return __hiloint2double(hi, lo);
 }
 
-// The pair loop of sym64_block: both directions of every pair between the thread's two
-// targets and the 512 staged sources; forward sums into f, reverse sums into sh.racc.
+// One 64-source group g of sym64_block's pair loop: both directions of every pair between the
+// thread's two targets and sources g..g+63; forward sums into f, the wave's reverse sums of the
+// group into sh.racc[w][·][0..63].
 template <int kMetric, bool kFar>
-__device__ __forceinline__ void sym64_loop(double xa, double ya, double za, double nxa, double nya, double nza,
-                                           double wpa, double wna, double xb, double yb, double zb, double nxb,
-                                           double nyb, double nzb, double wpb, double wnb, const KParams& kp,
-                                           double k2, Sym64Shared& sh, double (&f)[4]) {
+__device__ __forceinline__ void sym64_group(int g, double xa, double ya, double za, double nxa, double nya,
+                                            double nza, double wpa, double wna, double xb, double yb, double zb,
+                                            double nxb, double nyb, double nzb, double wpb, double wnb,
+                                            const KParams& kp, double k2, Sym64Shared& sh, double (&f)[4]) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int next = ((lane + 1) & 63) << 2;
-  for (int g = 0; g < kSymSub; g += 64) {
-    double ra1 = 0.0, ra2 = 0.0;  // at step s: the reverse sums of source g + ((lane + s) mod 64)
-    for (int s = 0; s < 64; ++s) {
-      const int q = g + ((lane + s) & 63);
-      const double2 c0 = sh.s0[q], c1 = sh.s1[q], c2 = sh.s2[q], c3 = sh.s3[q];
-      if (kFar) {
-        pair_sym_f64_far(xa, ya, za, nxa, nya, nza, wpa, wna, c0, c1, c2, c3, kp, k2, f[0], f[1], ra1, ra2);
-        pair_sym_f64_far(xb, yb, zb, nxb, nyb, nzb, wpb, wnb, c0, c1, c2, c3, kp, k2, f[2], f[3], ra1, ra2);
-      } else {
-        pair_sym_f64<kMetric>(xa, ya, za, nxa, nya, nza, wpa, wna, c0, c1, c2, c3, kp, f[0], f[1], ra1, ra2);
-        pair_sym_f64<kMetric>(xb, yb, zb, nxb, nyb, nzb, wpb, wnb, c0, c1, c2, c3, kp, f[2], f[3], ra1, ra2);
-      }
-      ra1 = shfl_next(ra1, next);
-      ra2 = shfl_next(ra2, next);
+  double ra1 = 0.0, ra2 = 0.0;  // at step s: the reverse sums of source g + ((lane + s) mod 64)
+  for (int s = 0; s < 64; ++s) {
+    const int q = g + ((lane + s) & 63);
+    const double2 c0 = sh.s0[q], c1 = sh.s1[q], c2 = sh.s2[q], c3 = sh.s3[q];
+    if (kFar) {
+      pair_sym_f64_far(xa, ya, za, nxa, nya, nza, wpa, wna, c0, c1, c2, c3, kp, k2, f[0], f[1], ra1, ra2);
+      pair_sym_f64_far(xb, yb, zb, nxb, nyb, nzb, wpb, wnb, c0, c1, c2, c3, kp, k2, f[2], f[3], ra1, ra2);
+    } else {
+      pair_sym_f64<kMetric>(xa, ya, za, nxa, nya, nza, wpa, wna, c0, c1, c2, c3, kp, f[0], f[1], ra1, ra2);
+      pair_sym_f64<kMetric>(xb, yb, zb, nxb, nyb, nzb, wpb, wnb, c0, c1, c2, c3, kp, f[2], f[3], ra1, ra2);
     }
-    sh.racc[w][0][g + lane] = ra1;
-    sh.racc[w][1][g + lane] = ra2;
+    ra1 = shfl_next(ra1, next);
+    ra2 = shfl_next(ra2, next);
   }
+  sh.racc[w][0][lane] = ra1;
+  sh.racc[w][1][lane] = ra2;
 }
 
 // Targets [t0, t0 + 512) (full; two per thread, t0 + 128w + l and 64 further, with bounding
@@ -228,25 +227,27 @@ __device__ __forceinline__ void sym64_block(const BandDev& b, const double* __re
   const double xa = b.px[ia], ya = b.py[ia], za = b.pz[ia], nxa = b.nx[ia], nya = b.ny[ia], nza = b.nz[ia];
   const double xb = b.px[ib], yb = b.py[ib], zb = b.pz[ib], nxb = b.nx[ib], nyb = b.ny[ib], nzb = b.nz[ib];
   const double wpa = wpsi[ia], wna = wpsn[ia], wpb = wpsi[ib], wnb = wpsn[ib];
-  if (far)
-    sym64_loop<kMetric, true>(xa, ya, za, nxa, nya, nza, wpa, wna, xb, yb, zb, nxb, nyb, nzb, wpb, wnb, kp, k2, sh,
-                              f);
-  else
-    sym64_loop<kMetric, false>(xa, ya, za, nxa, nya, nza, wpa, wna, xb, yb, zb, nxb, nyb, nzb, wpb, wnb, kp, k2, sh,
-                               f);
-  __syncthreads();
-  for (int q = tid; q < kSymSub; q += kBlock) {
-    if (s0 + q < n) {
-      double x1 = 0.0, x2 = 0.0;
-      for (int v = 0; v < kSymWaves; ++v) {
-        x1 += sh.racc[v][0][q];
-        x2 += sh.racc[v][1][q];
+  for (int g = 0; g < kSymSub; g += 64) {
+    if (far)
+      sym64_group<kMetric, true>(g, xa, ya, za, nxa, nya, nza, wpa, wna, xb, yb, zb, nxb, nyb, nzb, wpb, wnb, kp, k2,
+                                 sh, f);
+    else
+      sym64_group<kMetric, false>(g, xa, ya, za, nxa, nya, nza, wpa, wna, xb, yb, zb, nxb, nyb, nzb, wpb, wnb, kp,
+                                  k2, sh, f);
+    __syncthreads();
+    // the four waves' reverse sums of the group, in wave order: threads 0..63 the ψ sums,
+    // 64..127 the ψn sums
+    if (tid < 128) {
+      const int c = tid >> 6, q = g + lane;
+      if (s0 + q < n) {
+        double x = 0.0;
+        for (int v = 0; v < kSymWaves; ++v) x += sh.racc[v][c][lane];
+        double* rev = c ? rev2 : rev1;
+        rev[q] = x + (rev_acc ? rev[q] : 0.0);
       }
-      rev1[q] = x1 + (rev_acc ? rev1[q] : 0.0);
-      rev2[q] = x2 + (rev_acc ? rev2[q] : 0.0);
     }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
 // Targets [t0, t0 + 512) (the same two per thread as sym64_block) against the sources of the
@@ -337,8 +338,10 @@ __device__ __forceinline__ void sym64_item(const BandDev& b, const double* __res
 }
 
 // Symmetric FP64 operator of one band: one block per work item. k2 = κ² (a kernel argument,
-// so that it stays in scalar registers).
-static __global__ void __attribute__((unused)) __launch_bounds__(kBlock)
+// so that it stays in scalar registers). Capped at 168 VGPRs for three waves per SIMD (37 KB
+// of LDS per block allows four blocks per CU): the pair loops stay free of spills, which fall
+// in the set-up code around them.
+static __global__ void __attribute__((unused)) __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
     k_p2p_f64_sym(BandDev b, const double* __restrict__ wpsi, const double* __restrict__ wpsn, int n, int nsub,
                   const int2* __restrict__ items, int n_items, KParams kp, double k2, double* __restrict__ partial,
                   const int* __restrict__ skip) {
