@@ -189,7 +189,10 @@ static __global__ void __launch_bounds__(kBlock) k_far64_batch(const Item* __res
 constexpr int kModeTiled = 0, kModeF64 = 1, kModeSym = 2, kModeF64Sym = 3;
 
 // y = Λx + Σ chunks (+ near), per molecule; x and y at step *kptr / *kptr + 1 of a basis
-// when kptr is given.
+// when kptr is given. kRowLanes lanes share a node: lane t sums the chunk rows t, t + 16, …
+// and the near-field pairs row[l] + t, row[l] + t + 16, … (coalesced across the lanes), then a
+// fixed-order lane reduction; thread g·kRowLanes + t. The lanes of a node sit in one wave and
+// take the same branches.
 static __global__ void __launch_bounds__(kBlock) k_reduce_batch(int ntot, const int* __restrict__ mol_of,
                                                                 const MolDev* __restrict__ mols,
                                                                 const int* __restrict__ active, int mode,
@@ -197,7 +200,8 @@ static __global__ void __launch_bounds__(kBlock) k_reduce_batch(int ntot, const 
                                                                 const double* __restrict__ x, double* __restrict__ y,
                                                                 const int* __restrict__ kptr, int kmax, int64_t ldv,
                                                                 double lam1, double lam2) {
-  const int g = blockIdx.x * kBlock + threadIdx.x;
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int g = (int)(t / kRowLanes), lane = (int)(t % kRowLanes);
   if (g >= ntot) return;
   const int mi = mol_of[g];
   if (!active[mi]) return;
@@ -212,13 +216,13 @@ static __global__ void __launch_bounds__(kBlock) k_reduce_batch(int ntot, const 
   const int S = sym ? m.Ssym : use64 ? m.S64 : m.S32;
   const double* part = partial + (sym ? m.poffsym : use64 ? m.poff64 : m.poff32);
   double s1 = 0.0, s2 = 0.0;
-  for (int c = 0; c < S; ++c) {
+  for (int c = lane; c < S; c += kRowLanes) {
     s1 += part[(int64_t)c * 2 * m.n + l];
     s2 += part[(int64_t)c * 2 * m.n + m.n + l];
   }
   if (!use64) {  // FP64 near field
     const int64_t e = m.row[l + 1];
-    for (int64_t q = m.row[l]; q < e; ++q) {
+    for (int64_t q = m.row[l] + lane; q < e; q += kRowLanes) {
       const int j = m.col[q];
       const double4 cf = m.coef[q];
       const double ps = xv[2 * (int64_t)m.off + j], pn = xv[2 * (int64_t)m.off + m.n + j];
@@ -226,9 +230,15 @@ static __global__ void __launch_bounds__(kBlock) k_reduce_batch(int ntot, const 
       s2 += cf.z * ps + cf.w * pn;
     }
   }
-  const int64_t e1 = 2 * (int64_t)m.off + l, e2 = e1 + m.n;
-  yv[e1] = lam1 * xv[e1] + s1;
-  yv[e2] = lam2 * xv[e2] + s2;
+  for (int off = kRowLanes / 2; off > 0; off >>= 1) {
+    s1 += __shfl_down(s1, off, kRowLanes);
+    s2 += __shfl_down(s2, off, kRowLanes);
+  }
+  if (lane == 0) {
+    const int64_t e1 = 2 * (int64_t)m.off + l, e2 = e1 + m.n;
+    yv[e1] = lam1 * xv[e1] + s1;
+    yv[e2] = lam2 * xv[e2] + s2;
+  }
 }
 
 // ---------------------------------------------------------------- Krylov kernels
@@ -700,13 +710,17 @@ void far64(Batch& B, int cfg, const int* sel) {
                                                  kparams(B.d), B.partial);
 }
 
+// Blocks of k_reduce_batch: kRowLanes threads per node.
+unsigned reduce_blocks(const Batch& B) { return (unsigned)(((int64_t)B.ntot * kRowLanes + kBlock - 1) / kBlock); }
+
 // Molecules selected by `sel` get y = A x with the FP64 operator (persistent launch).
 void op64(Batch& B, const double* x, double* y, const int* sel) {
   const unsigned nbn = (unsigned)((B.ntot + kBlock - 1) / kBlock);
   k_weights_batch<<<nbn, kBlock, 0, B.st>>>(B.ntot, B.mol_of, B.mols, x, B.d.h3 / (4.0 * kPi), B.wpsi, B.wpsn);
   far64(B, B.cfg64, sel);
-  k_reduce_batch<<<nbn, kBlock, 0, B.st>>>(B.ntot, B.mol_of, B.mols, sel, B.cfg64 ? kModeF64Sym : kModeF64, B.partial,
-                                           x, y, nullptr, 0, 0, B.d.lam1, B.d.lam2);
+  k_reduce_batch<<<reduce_blocks(B), kBlock, 0, B.st>>>(B.ntot, B.mol_of, B.mols, sel,
+                                                        B.cfg64 ? kModeF64Sym : kModeF64, B.partial, x, y, nullptr,
+                                                        0, 0, B.d.lam1, B.d.lam2);
 }
 
 // Mixed operator: y = A x for molecules in `act`; with kptr, x = V[*kptr] and y = V[*kptr+1].
@@ -714,8 +728,9 @@ void op_mixed(Batch& B, const double* x, double* y, const int* kptr, int64_t ldv
   const unsigned nbn = (unsigned)((B.ntot + kBlock - 1) / kBlock);
   k_pack_batch<<<nbn, kBlock, 0, B.st>>>(B.ntot, B.mol_of, B.mols, x, kptr, B.m, ldv, B.d.h3 / (4.0 * kPi), B.sigma);
   launch_far32(B, B.cfg, act, f32params(B.d, B.sigma), B.sigma, B.sigma * B.sigma);
-  k_reduce_batch<<<nbn, kBlock, 0, B.st>>>(B.ntot, B.mol_of, B.mols, act, B.cfg == kSymB ? kModeSym : kModeTiled,
-                                           B.partial, x, y, kptr, B.m, ldv, B.d.lam1, B.d.lam2);
+  k_reduce_batch<<<reduce_blocks(B), kBlock, 0, B.st>>>(B.ntot, B.mol_of, B.mols, act,
+                                                        B.cfg == kSymB ? kModeSym : kModeTiled, B.partial, x, y,
+                                                        kptr, B.m, ldv, B.d.lam1, B.d.lam2);
 }
 
 // Per-molecule 2-norms of v over the molecules in sel, into out[mol].
