@@ -430,6 +430,25 @@ def bench_batch(args):
     ctx.close()
 
 
+def issue_rates():
+    """Measured issue rates of single-instruction streams (wave instructions per second) from the
+    committed summary of probes/issue_rates.hip, or None when the probe has changed since."""
+    path = os.path.join(ROOT, "profiles", "valu_issue_rates_mi355x.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.split("#")[0].strip()
+    try:
+        if kernel_source_hash(os.path.join(ROOT, kv["probe"])) != kv.get("source_sha256_16"):
+            return None
+        return {k: float(v) for k, v in kv.items() if k.endswith("_wave_insts_per_s")}
+    except (KeyError, OSError, ValueError):
+        return None
+
+
 def executed_counts(kernel: str, workload: str, pairs_per_launch: float, launch_s: float):
     """Executed VALU work of the kernel from the committed rocprofv3 counter summary (only while
     the kernel's source is unchanged), against the measured launch time."""
@@ -450,10 +469,14 @@ def executed_counts(kernel: str, workload: str, pairs_per_launch: float, launch_
     except (KeyError, OSError, ValueError):
         return None
     flops = 64.0 * (2.0 * fma + mul + add)  # wave instructions × 64 lanes, FMA = 2
-    return {"source": os.path.relpath(path, ROOT), "valu_insts_per_pair": valu * 64.0 / pairs_per_launch,
-            "executed_fp32_tflops": flops / launch_s / 1e12, "frac_of_peak": flops / launch_s / PEAK_FP32,
-            "frac_of_nonpacked_ceiling": flops / launch_s / (PEAK_FP32 / 2),
-            "transcendentals_per_s": 64.0 * trans / launch_s}
+    out = {"source": os.path.relpath(path, ROOT), "valu_insts_per_pair": valu * 64.0 / pairs_per_launch,
+           "executed_fp32_tflops": flops / launch_s / 1e12, "frac_of_peak": flops / launch_s / PEAK_FP32,
+           "wave_insts_per_s": valu / launch_s, "transcendentals_per_s": 64.0 * trans / launch_s}
+    rates = issue_rates()
+    if rates and "fp32_fma_stream_wave_insts_per_s" in rates:
+        # the kernel's VALU issue rate against a stream of FP32 FMAs on vector registers
+        out["frac_of_fp32_fma_stream"] = valu / launch_s / rates["fp32_fma_stream_wave_insts_per_s"]
+    return out
 
 
 def main():

@@ -1,8 +1,9 @@
 """Builds libpb.so (the HIP library behind include/pb.h) for gfx950 with hipcc.
 
 Every .hip file under csrc/ is compiled to an object in _build/ (in parallel), then linked
-into paper_1709_08070_amd/libpb.so. Packed FP32 instructions are disabled: the compiler
-never emits v_pk_{add,mul,fma}_f32.
+into paper_1709_08070_amd/libpb.so. Each .hip file under probes/ is a standalone measurement
+program, built beside its source (probes/issue_rates.hip -> probes/issue_rates). Packed FP32
+instructions are disabled: the compiler never emits v_pk_{add,mul,fma}_f32.
 """
 from __future__ import annotations
 
@@ -15,6 +16,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
+PROBES = os.path.join(HERE, "probes")
 BUILD = os.path.join(ROOT, "_build")
 SO = os.path.join(HERE, "libpb.so")
 ARCH = os.environ.get("PB_OFFLOAD_ARCH", "gfx950")
@@ -39,11 +41,22 @@ def _compile(src: str) -> str:
     return obj
 
 
+def _probe(src: str) -> str:
+    exe = src[: -len(".hip")]
+    flags = [f for f in FLAGS if f not in ("-fPIC",)]
+    r = subprocess.run([HIPCC, *flags, "-o", exe, src], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
+    return exe
+
+
 def build(jobs: int = 8) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    probes = sorted(glob.glob(os.path.join(PROBES, "*.hip")))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, srcs))
+        list(ex.map(_probe, probes))
     tmp = SO + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
