@@ -39,7 +39,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FLOP_PER_PAIR = 61  # algorithmic FP32 FLOPs per pair-interaction (FMA = 2)
-PEAK_FP32 = 157.3e12  # MI355X FP32 vector peak (packed), FLOP/s
+PEAK_FP32 = 157.3e12  # MI355X FP32 vector peak, FLOP/s
 
 METRIC = "BIM pair-interactions/s; GMRES time-to-1e-6 (learned+mixed vs plain FP64)"
 
