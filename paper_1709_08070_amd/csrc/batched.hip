@@ -556,6 +556,17 @@ static __global__ void k_outer_check(int n_mol, const double* __restrict__ rn, c
   }
 }
 
+// Target of the first inner pass of the selected molecules, whose residual comes from the
+// mixed operator: the same max(½·tol·‖g‖, η·‖r‖) as after an FP64 residual, no convergence
+// decision.
+static __global__ void k_first_target(int n_mol, const double* __restrict__ rn, const double* __restrict__ gn,
+                                      double tol, double eta, const int* __restrict__ sel,
+                                      double* __restrict__ tol_abs) {
+  const int mol = blockIdx.x * blockDim.x + threadIdx.x;
+  if (mol >= n_mol || !sel[mol]) return;
+  tol_abs[mol] = fmax(0.5 * tol * gn[mol], eta * rn[mol]);
+}
+
 static __global__ void k_stamp(unsigned long long* t) { *t = wall_clock64(); }
 
 }  // namespace
@@ -1156,8 +1167,28 @@ extern "C" pb_status pb_ibim_solve_batched(pb_ctx* ctx, int n_mol, const pb_band
     return ctx->fail(PB_EINVAL, "the batched solve runs the mixed path (precision PB_MIXED)");
   if (prm->reg_avg != PB_AVG_FLAT)
     return ctx->fail(PB_EINVAL, "the batched solve takes the paper's disc averages (reg_avg PB_AVG_FLAT)");
-  // refinement over the molecules in sel: FP64 residual, inner solve, update
-  auto outer_loop = [&](bool with_prec) -> pb_status {
+  // refinement over the molecules in sel: FP64 residual, inner solve, update. With
+  // mixed_first the first pass runs straight on the mixed operator from the initial guess, as
+  // the single solve does: its residual comes from the mixed operator (none from a zero
+  // start), and only the FP64 residuals after it decide convergence.
+  auto outer_loop = [&](bool with_prec, bool mixed_first) -> pb_status {
+    if (mixed_first) {
+      if (opts.x0 == PB_X0_ZERO) {
+        k_copy<<<vb, kBlock, 0, B.st>>>(B.M, g, r);
+        k_zero_vec<<<vb, kBlock, 0, B.st>>>(B.M, dvec);
+      } else {
+        op_mixed(B, x, r, nullptr, 0, sel);
+        k_resid_batch<<<nbn, kBlock, 0, B.st>>>(B.ntot, B.mol_of, B.mols, sel, g, r, dvec);
+        for (int i = 0; i < n_mol; ++i) mvmx[i] += 1;  // every molecule is selected on entry
+      }
+      norms(B, r, sel, rn);
+      k_first_target<<<(n_mol + 63) / 64, 64, 0, B.st>>>(n_mol, rn, gn, opts.tol, kInnerEta, sel, tolabs);
+      PB_TRY(launch_ok(ctx, "first pass"));
+      PB_TRY(inner(sel, r, dvec, with_prec));
+      k_add_batch<<<B.nseg, kBlock, 0, B.st>>>(B.nseg, B.segs, sel, dvec, x);
+      ++outer;
+      ++outer_run;
+    }
     for (;;) {
       op64(B, x, r, sel);
       k_resid_batch<<<nbn, kBlock, 0, B.st>>>(B.ntot, B.mol_of, B.mols, sel, g, r, dvec);
@@ -1179,7 +1210,7 @@ extern "C" pb_status pb_ibim_solve_batched(pb_ctx* ctx, int n_mol, const pb_band
     }
   };
   std::vector<int> fallback(n_mol, 0);
-  PB_TRY(outer_loop(prec));
+  PB_TRY(outer_loop(prec, true));
   if (learned_x0 || prec) {
     // plain GMRES judges the learned path (x0 = M(g) and/or the preconditioner): molecules
     // still selected missed the tolerance; they continue without the network, from Λ⁻¹g where
@@ -1195,7 +1226,7 @@ extern "C" pb_status pb_ibim_solve_batched(pb_ctx* ctx, int n_mol, const pb_band
       k_reset_nonfinite<<<nbn, kBlock, 0, B.st>>>(B.ntot, B.mol_of, B.mols, relres, g, B.d.lam1, B.d.lam2, x);
       outer_run = 0;
       iter_cap = opts.max_iter;
-      PB_TRY(outer_loop(false));
+      PB_TRY(outer_loop(false, false));
     }
   }
 
