@@ -79,6 +79,30 @@ def test_batched_matches_single_solves(pbm):
     ctx.close()
 
 
+@pytest.mark.parametrize("x0", ["zero", "diag"])
+def test_batched_application_count(pbm, x0):
+    """The batched refinement's bookkeeping, as the single solve's: the first pass runs on the
+    mixed operator from the initial guess (its residual from one mixed application, none from a
+    zero start); with restart 400 every inner cycle ends on its residual estimate, so a molecule
+    spends one mixed application per Arnoldi step beyond that first residual, and one FP64
+    application per pass it takes (at least one, at most the batch's passes)."""
+    ctx = pbm.Context(0)
+    sizes = synth.batch_sizes(3, seed0=7300, lo=15, hi=120)
+    atoms_list = [synth.globule(n, 7300 + i) for i, n in enumerate(sizes)]
+    say(f"case: batch of {len(sizes)} globules, atoms {sizes}, h=0.5, tol 1e-9, restart 400, x0 {x0}")
+    prm, bands, ats = _prepare(pbm, ctx, atoms_list, 0.5)
+    mode = pbm.PB_X0_ZERO if x0 == "zero" else pbm.PB_X0_DIAG
+    opts = pbm.solve_opts(tol=1e-9, precision=pbm.PB_MIXED, restart=400, max_iter=400, x0=mode)
+    ps, stats, bst = pbm.pb_ibim_solve_batched(ctx, bands, ats, prm, opts)
+    for i, st in enumerate(stats):
+        say(f"  mol {i}: n={bands[i].n} iters {st.iters}, mixed {st.matvecs_mixed}, FP64 {st.matvecs_fp64}, "
+            f"batch passes {bst.outer}")
+        assert st.converged and st.true_relres <= 1e-9
+        assert 1 <= st.matvecs_fp64 <= bst.outer
+        assert st.matvecs_mixed == st.iters + (0 if x0 == "zero" else 1)
+    ctx.close()
+
+
 def test_batch64_full_size_sampled(pbm):
     """The benchmark's batch at full size (64 globules, atom counts log-uniform over 50–2000,
     seeds 64000 + m, h = 0.5, mixed solve to 1e-6 in one batched call). For the smallest,
