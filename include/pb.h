@@ -274,7 +274,9 @@ typedef struct {
    n_mol device pointers (n_atoms[m] × 5). p: host array of n_mol device pointers (2n_m
    doubles each), input when opts->x0 == PB_X0_USER, output always. stats: host, n_mol
    entries, may be NULL; bstats: host, may be NULL. PB_ENOCONV if any molecule misses the
-   tolerance (all results still written).
+   tolerance (all results still written). The refinement is pb_ibim_solve's: a first pass on
+   the mixed operator from the initial guess, then FP64 residuals (stats[m].matvecs_fp64, one
+   per pass of molecule m) decide convergence and drive the correction solves.
    Learned path (opts->x0 == PB_X0_LEARNED and/or opts->precond == PB_PRECOND_LEARNED,
    opts->nn set, every band's phi present): the network runs over all molecules at once;
    as right preconditioner inside the captured step (flexible GMRES), as x0 = M(g). A
